@@ -1,0 +1,101 @@
+"""Seeded synthetic inputs (densities, loads, objective vectors) and the
+workload table.  This module holds none of the method's arithmetic: it only
+draws random numbers and names grid coordinates, so the GPU library and the
+CPU oracle can both be fed identical arrays.
+
+Workloads (cantilevers of Sec. 7, Example 2 shapes, and a 3D analogue):
+  ip64x32        64x32 elements, IP run from x = V/m, V = 0.5 m, xbar = 1, 4 levels
+  grf1024x512    1024x512, Gaussian random field -> logistic in [1e-3, 1], 7 levels
+  thr2048x1024   2048x1024, random field thresholded to {1e-6, 1}, 40 % solid, 8 levels
+  uni512x256     512x256, x ~ U[0.01, 1], objective g ~ N(0, 1), 6 levels
+  ip128x64x64    128x64x64 hexahedra, IP run from x = 0.3, V = 0.3 m, 5 levels
+Loads: a unit downward (-y) point load at the right-edge mid node in 2D; in 3D
+a unit load split over a 4x4 node patch on the x = max face.
+"""
+import numpy as np
+
+
+def gaussian_random_field(shape, corr_len, seed):
+    """White N(0,1) noise on an element grid (C order, x fastest), convolved
+    periodically with exp(-d^2 / (2 corr_len^2)) via FFT, standardised."""
+    rng = np.random.default_rng(seed)
+    noise = rng.standard_normal(shape)
+    kern = np.ones(shape)
+    for ax, n in enumerate(shape):
+        d = np.minimum(np.arange(n), n - np.arange(n)).astype(np.float64)
+        g = np.exp(-d * d / (2.0 * corr_len * corr_len))
+        sh = [1] * len(shape)
+        sh[ax] = n
+        kern = kern * g.reshape(sh)
+    field = np.real(np.fft.ifftn(np.fft.fftn(noise) * np.fft.fftn(kern)))
+    field -= field.mean()
+    field /= field.std()
+    return field
+
+
+def _grid_shape(nel):
+    return tuple(int(v) for v in nel[::-1])       # (nz,) ny, nx: x fastest
+
+
+def density_logistic(nel, seed=1, lo=1e-3, gain=4.0, corr_len=16.0):
+    g = gaussian_random_field(_grid_shape(nel), corr_len, seed).ravel()
+    return lo + (1.0 - lo) / (1.0 + np.exp(-gain * g))
+
+
+def density_threshold(nel, seed=2, solid=0.4, lo=1e-6, corr_len=16.0):
+    g = gaussian_random_field(_grid_shape(nel), corr_len, seed).ravel()
+    m = g.size
+    order = np.argsort(-g, kind="stable")
+    x = np.full(m, lo)
+    x[order[: int(round(solid * m))]] = 1.0
+    return x
+
+
+def density_uniform(nel, seed=3, lo=0.01, hi=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, int(np.prod(nel)))
+
+
+def normal_slots(nslots, seed=33):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(int(nslots))
+
+
+def sample_elements(m, count=32, seed=333):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(int(m), size=int(count), replace=False))
+
+
+def point_load(nel):
+    """[(node coords, component, value)]: unit downward load (component 1 = y)."""
+    if len(nel) == 2:
+        nx, ny = nel
+        return [((nx, ny // 2), 1, -1.0)]
+    nx, ny, nz = nel
+    out = []
+    for k in range(nz // 2 - 2, nz // 2 + 2):
+        for j in range(ny // 2 - 2, ny // 2 + 2):
+            out.append(((nx, j, k), 1, -1.0 / 16.0))
+    return out
+
+
+WORKLOADS = {
+    "ip64x32": dict(nel=(64, 32), levels=4, kind="ip", vfrac=0.5, xbar=1.0),
+    "grf1024x512": dict(nel=(1024, 512), levels=7, kind="solve", density="logistic", seed=1),
+    "thr2048x1024": dict(nel=(2048, 1024), levels=8, kind="solve", density="threshold", seed=2),
+    "uni512x256": dict(nel=(512, 256), levels=6, kind="adjoint", density="uniform", seed=3),
+    "ip128x64x64": dict(nel=(128, 64, 64), levels=5, kind="ip", vfrac=0.3, xbar=1.0),
+}
+
+
+def density_for(name, nel=None):
+    w = WORKLOADS[name]
+    nel = nel or w["nel"]
+    kind = w.get("density")
+    if kind == "logistic":
+        return density_logistic(nel, w["seed"])
+    if kind == "threshold":
+        return density_threshold(nel, w["seed"])
+    if kind == "uniform":
+        return density_uniform(nel, w["seed"])
+    return np.full(int(np.prod(nel)), w["vfrac"])
