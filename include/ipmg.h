@@ -1,0 +1,202 @@
+/*
+ * ipmg.h - C ABI of the MI355X (gfx950) library for the multigrid-preconditioned
+ * conjugate-gradient solves of the primal-dual interior-point method for
+ * minimum-compliance topology optimisation (Kocvara & Mohammed, "Primal-dual
+ * interior-point multigrid method for topology optimization").
+ *
+ * Problem (Sec. 1, problem (1)): minimise (1/2) f'u subject to K(x) u = f,
+ * sum x = V, 0 <= x <= xbar, with K(x) = sum_e x_e K_e on a structured grid of
+ * unit square (2D, bilinear Q1, plane stress) or cube (3D, trilinear Q1)
+ * elements, one density x_e per element (Sec. 7).
+ *
+ * Conventions shared by every call
+ *   - Grid: nel[0] x nel[1] (x nel[2]) elements.  Element (i,j,k) has index
+ *     e = (k*ny + j)*nx + i; node (i,j,k) has index q = (k*(ny+1) + j)*(nx+1) + i;
+ *     DOF slot = dim*q + c (c = 0: x, 1: y, 2: z).  Vectors over DOFs are full
+ *     slot vectors ("n_slots" doubles) in this node-major interleaved layout.
+ *   - Every DOF of a node with i == 0 is clamped.  Outputs hold 0 there; the
+ *     entries of inputs at clamped slots are ignored (treated as 0).
+ *   - Vectors of the augmented Newton system Z (eq. (nwtr2Z), Sec. 2) have
+ *     n_slots + 1 entries, the volume multiplier lambda last.
+ *   - Pointers marked [device] are caller-owned device memory on the context's
+ *     GPU, contiguous, 8-byte aligned; the library never frees them and keeps
+ *     no reference after the call returns.  Pointers marked [host] are host
+ *     memory.  Inputs and outputs must not alias unless stated.
+ *   - All GPU work is enqueued on the stream given to ipmg_create; calls that
+ *     return host results (status, info structs, host outputs) synchronise it.
+ *   - Return value: IPMG_OK (0) or a negative IPMG_E* code.  No C++ exception
+ *     crosses this interface.  ipmg_last_error() gives a message.  A context
+ *     must not be used from two threads at once.
+ */
+#ifndef IPMG_H
+#define IPMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  IPMG_OK = 0,
+  IPMG_E_INVALID = -1,      /* null pointer, bad size or descriptor            */
+  IPMG_E_DOMAIN = -2,       /* x outside (0, xbar], non-finite data, bad V      */
+  IPMG_E_HIP = -3,          /* HIP runtime error                               */
+  IPMG_E_NOMEM = -4,        /* device or host allocation failed                */
+  IPMG_E_BREAKDOWN = -5,    /* p'Ap <= 0 or r'y <= 0 in PCG; coarse matrix not PD */
+  IPMG_E_NOT_CONVERGED = -6,/* PCG hit maxit (outputs valid, info filled)      */
+  IPMG_E_STALLED = -7,      /* interior-point step length below 1e-14          */
+  IPMG_E_STATE = -8         /* call out of order (e.g. solve before setup)     */
+};
+
+enum { IPMG_OP_K = 0, IPMG_OP_Z = 1 };
+
+typedef struct ipmg_ctx ipmg_ctx;
+
+/* Discretisation and multigrid description (Sec. 5.1, Sec. 7). */
+typedef struct {
+  int dim;          /* 2 or 3                                                     */
+  int nel[3];       /* elements per axis; nel[2] ignored in 2D; each divisible by
+                       2^(levels-1)                                               */
+  int levels;       /* number of multigrid levels, >= 1 (1 = direct solve only)   */
+  double E, nu;     /* Young's modulus and Poisson ratio (1, 0.3)                 */
+  int vcycle_fp32;  /* 1: V-cycle (smoothing, transfers, coarse operators) in FP32,
+                       coarsest solve and PCG in FP64; 0: everything FP64          */
+  int nu_pre, nu_post; /* damped-Jacobi sweeps before / after the coarse correction */
+  double omega;     /* Jacobi damping (0.6)                                       */
+} ipmg_desc;
+
+typedef struct {
+  int iters;           /* PCG iterations (alpha updates)                          */
+  int restarts;        /* true-residual restarts                                  */
+  int status;          /* IPMG_OK / IPMG_E_BREAKDOWN / IPMG_E_NOT_CONVERGED       */
+  double relres;       /* recurrence residual ||r|| / ||b|| at exit               */
+  double true_relres;  /* ||A u - b|| / ||b|| recomputed at exit                  */
+  double setup_ms;     /* hierarchy setup time for this system (0 if reused)      */
+  double solve_ms;     /* PCG wall time                                           */
+} ipmg_pcg_info;
+
+/* Interior-point state (Sec. 3.1): caller-owned device arrays plus host scalars. */
+typedef struct {
+  double* u;       /* [device] n_slots displacements                             */
+  double* x;       /* [device] m densities                                       */
+  double* phi;     /* [device] m multipliers of x >= 0                           */
+  double* psi;     /* [device] m multipliers of x <= xbar                        */
+  double lam;      /* volume multiplier                                          */
+  double s, r;     /* barrier parameters                                         */
+} ipmg_ip_state;
+
+typedef struct {
+  double V, xbar;     /* volume and upper bound of problem (1)                    */
+  double sigma;       /* barrier reduction factor (0.2, Sec. 3.2)                  */
+  double tau_nwt;     /* Newton test tolerance (0.1, Sec. 3.4)                     */
+  double pcg_rtol;    /* relative residual tolerance of every PCG solve            */
+  int pcg_maxit;      /* maximum PCG iterations per system (1000)                  */
+  double frac;        /* fraction to the boundary (0.9, Sec. 3.3)                  */
+  int step_all_blocks;/* 1: the 0.9 rule also keeps phi, psi > 0                   */
+  int stop_rule;      /* 0: relative duality gap <= kkt_tol at a point passing the
+                         Newton test; 1: max(s, r) <= tau_ip (eq. (crit:ip))       */
+  double kkt_tol, tau_ip;
+  int max_newton;     /* safety cap on Newton steps                               */
+} ipmg_ip_params;
+
+typedef struct {
+  double alpha;       /* step length taken                                         */
+  double nwt;         /* ||F1||/||f|| + ||G3||/(||phi|| + ||psi||) after the step  */
+  double gap;         /* (phi'x + psi'(xbar - x)) / f'u after the step             */
+  double volume_res;  /* sum x - V after the step                                  */
+  double compliance;  /* f'u after the step                                        */
+  int pcg_iters;      /* PCG iterations of the Newton system                       */
+  int pcg_status;
+  int barrier_updated;/* 1 if s, r were multiplied by sigma after this step        */
+  int converged;      /* 1 if the stop rule holds                                  */
+  double setup_ms, solve_ms;
+} ipmg_ip_info;
+
+/* Create a context: grid, element matrix, level hierarchy storage and scratch.
+ * hip_stream: a hipStream_t (NULL = default stream).  out: [host] receives the
+ * context.  Errors: IPMG_E_INVALID (bad desc), IPMG_E_NOMEM, IPMG_E_HIP. */
+int ipmg_create(const ipmg_desc* desc, void* hip_stream, ipmg_ctx** out);
+void ipmg_destroy(ipmg_ctx* ctx);
+const char* ipmg_last_error(const ipmg_ctx* ctx);
+const char* ipmg_status_string(int status);
+
+/* Sizes on a level (level = levels-1 is the finest, 0 the coarsest). [host] outputs. */
+int ipmg_sizes(const ipmg_ctx* ctx, int level, int64_t* n_slots, int64_t* n_free, int64_t* m_elems);
+
+/* Integer maps, computed by the library on the host (Sec. 7 grid; indexing above).
+ * free_to_slot: [host] n_free entries, the slot of every free DOF in slot order.
+ * slot_of_node: returns the slot of component c of node (i,j,k) on a level, or -1. */
+int ipmg_dof_map(const ipmg_ctx* ctx, int level, int64_t* free_to_slot);
+int64_t ipmg_slot_of(const ipmg_ctx* ctx, int level, int i, int j, int k, int c);
+
+/* Element stiffness K0 of the unit element (Sec. 7: Q1, E, nu; 2x2(x2) Gauss rule),
+ * computed on the GPU.  K0: [host] (dim*2^dim)^2 doubles, row-major, local DOF order
+ * node-major (nodes counter-clockwise on face k, then face k+1). */
+int ipmg_element_matrix(ipmg_ctx* ctx, double* K0);
+
+/* Set the densities x (K(x) = sum_e x_e K_e, Sec. 1).  x: [device] m doubles, each in
+ * (0, inf) and finite, else IPMG_E_DOMAIN.  The library copies x. */
+int ipmg_set_density(ipmg_ctx* ctx, const double* x);
+
+/* y = K(x) v on the finest grid in FP64 (matrix-free, element by element).
+ * v, y: [device] n_slots.  Requires ipmg_set_density. */
+int ipmg_apply_K(ipmg_ctx* ctx, const double* v, double* y);
+
+/* Build the multigrid hierarchy for op (Sec. 5.1 Galerkin coarse operators, dense
+ * Cholesky of the coarsest operator).  IPMG_OP_K uses the current densities;
+ * IPMG_OP_Z uses the Newton-system data of the last ipmg_ip_prepare. */
+int ipmg_mg_setup(ipmg_ctx* ctx, int op);
+
+/* Damping weight and spectral-radius estimate of the Jacobi smoother on a level after
+ * the last ipmg_mg_setup: omega_k = min(omega, 1.6 / rho_k), rho_k the Rayleigh
+ * quotient of D_k^-1 A_k after 12 power iterations from the vector (-1)^(i+j+k)(1+c)
+ * (damped Jacobi diverges once omega * rho >= 2; Sec. 5.1 leaves the smoother open).
+ * omega, rho: [host] outputs (rho = 0 on the coarsest level, which is solved directly). */
+int ipmg_level_damping(ipmg_ctx* ctx, int level, double* omega, double* rho);
+
+/* One V-cycle z = M r from the zero initial guess (Algorithm MG, Sec. 5.1).
+ * r, z: [device] n_slots (+1 for IPMG_OP_Z) doubles.  In FP32 mode r is rounded
+ * to FP32 on entry and z is widened on exit. */
+int ipmg_vcycle(ipmg_ctx* ctx, int op, const double* r, double* z);
+
+/* y = Z v for the augmented Newton matrix of the last ipmg_ip_prepare (FP64).
+ * v, y: [device] n_slots + 1. */
+int ipmg_apply_Z(ipmg_ctx* ctx, const double* v, double* y);
+
+/* Algorithm PCG (Sec. 5.2) with one V-cycle per step, to ||r|| <= rtol ||b||,
+ * confirmed by the true residual.  b: [device] right-hand side; u: [device]
+ * initial guess on entry (zero it for a cold start), solution on exit.  Sizes as
+ * in ipmg_vcycle.  info: [host] may be NULL.  Returns IPMG_OK, IPMG_E_BREAKDOWN or
+ * IPMG_E_NOT_CONVERGED (u holds the last iterate). */
+int ipmg_pcg(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int maxit,
+             ipmg_pcg_info* info);
+
+/* Element sensitivities g_e = scale * w_e' K0 u_e (B(u)' w of Sec. 2 scaled; with
+ * w = lambda, scale = -1 this is the adjoint gradient -lambda_e' K_e u_e).
+ * w, u: [device] n_slots; g: [device] m. */
+int ipmg_element_sens(ipmg_ctx* ctx, const double* w, const double* u, double scale, double* g);
+
+/* Interior-point method (Sec. 3).  ipmg_ip_init sets x = V/m, u = K(x)^-1 f (MG-PCG),
+ * lambda = 1, phi = psi = 1, s = r = 1 (Sec. 3.1).  f: [device] n_slots load vector.
+ * st: [host] struct whose device arrays the caller allocated (n_slots, m, m, m). */
+int ipmg_ip_init(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
+                 ipmg_pcg_info* info);
+
+/* Form the Newton system at st (residuals F1..F5, D, G3, augmented matrix data and
+ * its right-hand side; Sec. 2, eqs. (nwtr2Z), (nwtr2rhs)).  rhs: [device] n_slots+1
+ * output, may be NULL. */
+int ipmg_ip_prepare(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm,
+                    const ipmg_ip_state* st, double* rhs);
+
+/* One Newton step (Sec. 3.1 steps 1-4): prepare, MG-PCG on Z, recovery of d_x,
+ * d_phi, d_psi, step length (Sec. 3.3), update, Newton test and barrier update
+ * (Sec. 3.2, 3.4), stop rule.  Updates st in place.  info: [host] may be NULL.
+ * Returns IPMG_OK, IPMG_E_STALLED, IPMG_E_DOMAIN (non-finite iterate) or an error. */
+int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
+                 ipmg_ip_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPMG_H */

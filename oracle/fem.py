@@ -218,3 +218,23 @@ def load_vector(grid, loads):
         q = int(grid.node_index(*coords))
         f[grid.dim * q + comp] += val
     return f
+
+
+def apply_slots(grid, x, K0, v_slots):
+    """y = K(x) v = sum_e x_e K_e v over all slots, element by element (the
+    definition of K(x), problem (1)), without forming the matrix.  Used to
+    certify residuals of large solves."""
+    edofs = grid.element_dofs()
+    ve = np.asarray(v_slots, dtype=np.float64)[edofs]
+    ye = (ve @ K0) * np.asarray(x, dtype=np.float64)[:, None]   # K0 symmetric
+    return np.bincount(edofs.ravel(), weights=ye.ravel(), minlength=grid.nslots)
+
+
+def apply_free_masked(grid, x, K0, v_slots):
+    """K(x) restricted to the free DOFs, as a slot vector: clamped inputs are
+    treated as zero and clamped outputs are zero."""
+    mask = grid.clamped_mask()
+    v = np.where(mask, 0.0, np.asarray(v_slots, dtype=np.float64))
+    y = apply_slots(grid, x, K0, v)
+    y[mask] = 0.0
+    return y

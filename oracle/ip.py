@@ -194,11 +194,10 @@ class IPLog:
 
 
 def solve_linear(Z, rhs, params, grid, augmented, x0=None):
-    """MG-PCG (or a sparse direct solve); Z systems use the damping safeguard."""
+    """MG-PCG (or a sparse direct solve)."""
     if params.solver == "direct":
         return spla.spsolve(Z.tocsc(), rhs), 0
-    H = mg.Hierarchy(grid, Z, params.levels, augmented=augmented, omega=params.omega,
-                     safeguard=augmented)
+    H = mg.Hierarchy(grid, Z, params.levels, augmented=augmented, omega=params.omega)
     res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, None,
                          params.nu1, params.nu2)
     return res.z, res.iters

@@ -17,14 +17,15 @@ Readings where the paper is silent (shared with the GPU path):
     which is where the paper defines A_1;
   * clamped nodes stay clamped on every level (the clamped edge x = 0 is a
     grid line of every level, so the coarse spaces are nested subspaces);
-  * damping safeguard (augmented system Z only): late in the interior-point
-    run the rank-one element terms of Z push the spectral radius of D^-1 Z
-    above 2/omega, where damped Jacobi diverges and the V-cycle stops being
-    positive definite.  With `safeguard=True` every non-coarsest level uses
+  * damping safeguard: damped Jacobi diverges (and the V-cycle stops being
+    positive definite) once omega * rho(D^-1 A) >= 2.  That happens for
+    omega = 0.6 on 3D elasticity (rho about 3.3-3.8) and on the augmented
+    system Z late in the interior-point run (its rank-one element terms push
+    rho near 4).  Every non-coarsest level therefore uses
     omega_k = min(omega, SAFE_PRODUCT / rho_k), rho_k the Rayleigh-quotient
     estimate of the largest eigenvalue of D_k^-1 A_k after POWER_STEPS power
     iterations from the vector (-1)^(i+j+k) (1 + c) on DOF component c of node
-    (i, j, k) (and 1 on lambda).  For K(x) rho stays near 2.2-2.6, so
+    (i, j, k) (and 1 on lambda).  For 2D K(x), rho stays near 2.2-2.6, so
     omega = 0.6 is kept there.
 """
 import numpy as np
@@ -96,7 +97,7 @@ class Hierarchy:
     A_fine is the operator on the free DOFs of the finest grid (for Z: the
     (n+1)x(n+1) augmented matrix with lambda last)."""
 
-    def __init__(self, fine_grid, A_fine, levels, augmented=False, omega=0.6, safeguard=False):
+    def __init__(self, fine_grid, A_fine, levels, augmented=False, omega=0.6, safeguard=True):
         if levels < 1:
             raise ValueError("levels >= 1")
         self.augmented = augmented

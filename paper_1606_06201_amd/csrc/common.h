@@ -1,0 +1,99 @@
+// Internal declarations of the ipmg library (gfx950 / HIP).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+#include <stdexcept>
+
+#include "../../include/ipmg.h"
+
+namespace ipmg {
+
+// ---------------------------------------------------------------- errors ----
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define IPMG_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::ipmg::Error(IPMG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_) + \
+                                          " (" __FILE__ ":" + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+#define IPMG_REQUIRE(cond, code, msg) \
+  do { if (!(cond)) throw ::ipmg::Error((code), (msg)); } while (0)
+
+// ------------------------------------------------------------ geometry ----
+// Element local node a (0..2^dim-1): counter-clockwise on face z, then face z+1.
+__host__ __device__ constexpr int loc_x(int a) { return ((a & 3) == 1 || (a & 3) == 2) ? 1 : 0; }
+__host__ __device__ constexpr int loc_y(int a) { return (a & 3) >= 2 ? 1 : 0; }
+__host__ __device__ constexpr int loc_z(int a) { return a >> 2; }
+__host__ __device__ constexpr int loc_index(int ox, int oy, int oz) {
+  return 4 * oz + (oy ? (ox ? 2 : 3) : (ox ? 1 : 0));
+}
+
+template <int DIM>
+struct Geo {
+  static constexpr int NN = 1 << DIM;             // nodes per element
+  static constexpr int ND = DIM * NN;             // DOFs per element
+  static constexpr int NSYM = ND * (ND + 1) / 2;  // packed symmetric element matrix
+  static constexpr int NB = DIM == 2 ? 9 : 27;    // node neighbourhood
+};
+
+// Packed upper-triangular index of (r, c) in an n x n symmetric matrix.
+__host__ __device__ constexpr int sym_index(int r, int c, int n) {
+  return r <= c ? r * n - (r * (r - 1)) / 2 + (c - r) : c * n - (c * (c - 1)) / 2 + (r - c);
+}
+
+// Neighbourhood index of node offset (dx,dy,dz) in {-1,0,1}^dim.
+template <int DIM>
+__host__ __device__ constexpr int nb_index(int dx, int dy, int dz) {
+  return (DIM == 3 ? (dz + 1) * 9 : 0) + (dy + 1) * 3 + (dx + 1);
+}
+
+// Grid of one level: elements per axis and nodes per axis (nz = 0 -> 2D).
+struct Dims {
+  int nx, ny, nz;      // elements (nz = 1 in 2D for element counts)
+  int nx1, ny1, nz1;   // nodes (nz1 = 1 in 2D)
+  int64_t nnodes, nslots, m;
+};
+
+inline Dims make_dims(int dim, int nx, int ny, int nz) {
+  Dims d;
+  d.nx = nx; d.ny = ny; d.nz = dim == 3 ? nz : 1;
+  d.nx1 = nx + 1; d.ny1 = ny + 1; d.nz1 = dim == 3 ? nz + 1 : 1;
+  d.nnodes = (int64_t)d.nx1 * d.ny1 * d.nz1;
+  d.nslots = d.nnodes * dim;
+  d.m = (int64_t)d.nx * d.ny * d.nz;
+  return d;
+}
+
+// ----------------------------------------------------------- scratch ----
+// Indices into the FP64 device scalar array.
+enum Scal {
+  S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RN2, S_BN2, S_TOL2, S_RHONEW, S_TMP0, S_TMP1, S_TMP2,
+  S_TMP3, S_TMP4, S_TMP5, S_TMP6, S_TMP7, S_MIN0, S_MIN1, S_MIN2, S_MIN3, S_COUNT = 32
+};
+// Indices into the int device flag array.
+enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_COUNT = 8 };
+// Reduction counters (one per concurrently pending reduction kind).
+enum { C_MAIN = 0, C_AUX, C_COUNT = 8 };
+
+constexpr int BS = 256;           // threads per block for level and vector kernels
+constexpr int MAX_PARTIALS = 1 << 16;
+
+struct Red {
+  double* partials;   // MAX_PARTIALS * 4 doubles
+  unsigned* counter;  // C_COUNT
+  double* scal;       // S_COUNT
+  int* flags;         // F_COUNT
+};
+
+// Scalar type of the V-cycle.
+enum Prec { P64 = 0, P32 = 1 };
+
+}  // namespace ipmg

@@ -1,0 +1,115 @@
+// Library context: grid hierarchy, device buffers and the per-dimension kernel set.
+#pragma once
+#include "common.h"
+
+namespace ipmg {
+
+struct Ctx;
+
+// Level arrays (precision of the V-cycle, T = float or double).
+struct Level {
+  Dims d;
+  void* r = nullptr;    // right-hand side of the level problem (n_slots + 1)
+  void* z = nullptr;    // current iterate
+  void* z2 = nullptr;   // Jacobi ping-pong partner
+  void* t = nullptr;    // residual
+  void* E = nullptr;    // coarse element matrices (NSYM * m), levels below the finest
+  void* bZ = nullptr;   // border vector of Z on this level (n_slots)
+};
+
+// Kernel set of one dimension (implemented for 2 and 3 in ops2d.hip / ops3d.hip).
+struct Ops {
+  virtual ~Ops() {}
+  virtual void element_stiffness(Ctx& c, double* dK0) = 0;           // into device buffer
+  virtual void upload_k0(const double* K0) = 0;                       // host -> __constant__
+  // One level pass (see LevelMode) on level lev with operator op.
+  // omg: device pointer to the damping weight (Jacobi modes); sidx/sidx_in: scalar
+  // slots of the mode's reductions.
+  virtual void level(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out,
+                     const double* omg, int sidx, int sidx_in, const int* gate) = 0;
+  // FP64 operator on the finest grid (PCG operator), y = A v.
+  virtual void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) = 0;
+  virtual void restrict_to(Ctx& c, int lev_f, const void* rf, void* rc, int aug, const int* gate) = 0;
+  virtual void prolong_from(Ctx& c, int lev_f, void* z, const void* zc, int aug, const int* gate) = 0;
+  virtual void restrict64_to_T(Ctx& c, int lev_f, const void* rf, void* rc) = 0;  // border vectors
+  virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E of level lev_f-1
+  virtual void dense_assemble(Ctx& c, int op, double* A, int n) = 0;
+  virtual void power_start(Ctx& c, int lev, int aug, void* v) = 0;
+  virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
+  // Interior point kernels (FP64).
+  virtual void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi,
+                           double lam, double s, double r, double xbar) = 0;
+  virtual void ip_nodes(Ctx& c, const double* Ku, const double* f, const double* u, double* rhs) = 0;
+  virtual void ip_recover(Ctx& c, const double* du, const double* x, const double* phi, const double* psi,
+                          double s, double r, double xbar, double frac, int all_blocks) = 0;
+  virtual void ip_update(Ctx& c, double* u, const double* du, double* x, double* phi, double* psi) = 0;
+};
+
+Ops* make_ops2d();
+Ops* make_ops3d();
+
+struct Ctx {
+  ipmg_desc desc{};
+  int dim = 2;
+  bool fp32 = true;
+  int L = 1;
+  hipStream_t stream = nullptr;
+  Ops* ops = nullptr;
+  std::vector<Level> lev;      // lev[L-1] finest
+  size_t tsz = 4;              // sizeof(T) of the V-cycle
+
+  double K0[576] = {0};        // host copy of the element matrix
+  int nd = 8;                  // DOFs per element
+
+  // finest-level operator data
+  double* x64 = nullptr;       // densities (m)
+  void* xT = nullptr;          // V-cycle copy (aliases x64 in FP64 mode)
+  double* h64 = nullptr;       // Z rank-one factors h_e (ND * m)
+  void* hT = nullptr;
+  double* bZ64 = nullptr;      // border of Z on the finest grid (n_slots)
+  double cZ = 0.0;             // corner of Z
+  bool have_x = false;
+  bool have_z = false;
+  int hier_op = -1;            // operator the hierarchy currently holds (-1: none)
+
+  // PCG work vectors (FP64, n_slots + 1)
+  double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pt = nullptr, *pb = nullptr, *pu = nullptr;
+
+  // coarsest dense solve
+  int ncoarse = 0;             // dense size incl. lambda (n_slots_coarse + 1)
+  double *dA = nullptr, *dLi = nullptr, *dAi = nullptr;
+
+  // per-level damping on the device: omega_dev[k] = weight, omega_dev[L + k] = rho estimate
+  double* omega_dev = nullptr;
+
+  // reductions / scalars
+  Red red{};
+  double* hscal = nullptr;     // pinned host mirror of scal
+  int* hflags = nullptr;       // pinned host mirror of flags
+
+  // interior-point scratch (FP64, m or n_slots + 1)
+  double *ipG3 = nullptr, *ipW = nullptr, *ipSW = nullptr, *ipDx = nullptr, *ipDphi = nullptr, *ipDpsi = nullptr;
+  double *ipRhs = nullptr, *ipD = nullptr, *ipKu = nullptr;
+  double ipV = 0.0;            // volume of the current interior-point problem
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+
+  const Dims& fine() const { return lev[L - 1].d; }
+};
+
+// Host driver (solver.hip).
+void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st);
+void ctx_free(Ctx& c);
+void set_density(Ctx& c, const double* x);
+void mg_setup(Ctx& c, int op, double* ms);
+void* vcycle(Ctx& c, int op, const int* gate);    // lev[L-1].r -> returned level buffer
+void vcycle64(Ctx& c, int op, const double* r, double* z);
+int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info);
+void sync(Ctx& c);
+void read_scalars(Ctx& c);
+int ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_pcg_info* info);
+void ip_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, const ipmg_ip_state& st);
+int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_ip_info* info);
+
+}  // namespace ipmg

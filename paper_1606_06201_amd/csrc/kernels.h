@@ -1,0 +1,555 @@
+// Device kernels of the ipmg library, generic in the dimension (2: bilinear
+// quadrilaterals, 3: trilinear hexahedra) and in the V-cycle precision.
+// Included by one translation unit per dimension (ops2d.hip, ops3d.hip).
+#pragma once
+#include "common.h"
+
+namespace ipmg {
+
+// Element stiffness of the unit element, uploaded once per context
+// (computed by k_element_stiffness below).  Row-major ND x ND.
+static __constant__ double cK0d[576];
+static __constant__ float cK0f[576];
+
+template <typename T> __device__ inline T k0(int idx);
+template <> __device__ inline double k0<double>(int idx) { return cK0d[idx]; }
+template <> __device__ inline float k0<float>(int idx) { return cK0f[idx]; }
+
+// ------------------------------------------------------------------ reductions --
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ inline double load_acquire(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic two-stage reduction of NV sums per thread (or mins if IS_MIN).
+// Every block publishes its partials; the last block to arrive sums all partials
+// in block order and returns true with the totals in tot[] (valid in all threads of
+// that block).  Other blocks return false.  The block must hold BS threads.
+template <int NV, bool IS_MIN = false>
+__device__ bool reduce_last(const double (&v)[NV], const Red& red, int ctr, double (&tot)[NV]) {
+  __shared__ double sh[NV][BS / 64];
+  __shared__ int is_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    double s = IS_MIN ? wave_min(v[n]) : wave_sum(v[n]);
+    if (lane == 0) sh[n][wid] = s;
+  }
+  __syncthreads();
+  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      double s = sh[n][0];
+      for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh[n][w]) : s + sh[n][w];
+      red.partials[(size_t)n * MAX_PARTIALS + bid] = s;
+    }
+    __threadfence();
+    const unsigned prev = atomicAdd(&red.counter[ctr], 1u);
+    is_last = (prev == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  __shared__ double sh2[NV][BS / 64];
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    double s = IS_MIN ? INFINITY : 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += BS) {
+      const double p = load_acquire(&red.partials[(size_t)n * MAX_PARTIALS + b]);
+      s = IS_MIN ? fmin(s, p) : s + p;
+    }
+    s = IS_MIN ? wave_min(s) : wave_sum(s);
+    if (lane == 0) sh2[n][wid] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < NV; ++n) {
+    double s = sh2[n][0];
+    for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh2[n][w]) : s + sh2[n][w];
+    tot[n] = s;
+  }
+  if (threadIdx.x == 0) red.counter[ctr] = 0u;
+  return true;
+}
+
+// --------------------------------------------------------------- operators ----
+// Each operator gives, for element e and local node a, the contribution of the
+// element matrix rows (a,c) times the local vector ve, and the diagonal entries.
+
+// K(x) on the finest grid: A_e = x_e K0 (Sec. 1, problem (1)).
+template <int DIM, typename T>
+struct OpFineK {
+  const T* x;
+  int64_t m;
+  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+    constexpr int ND = Geo<DIM>::ND;
+    const T xe = x[e];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      T s = 0;
+#pragma unroll
+      for (int col = 0; col < ND; ++col) s += k0<T>(r * ND + col) * ve[col];
+      acc[c] += xe * s;
+    }
+  }
+  __device__ inline void diag(int64_t e, int a, T* dg) const {
+    constexpr int ND = Geo<DIM>::ND;
+    const T xe = x[e];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) dg[c] += xe * k0<T>((a * DIM + c) * ND + a * DIM + c);
+  }
+  __device__ inline double entry(int64_t e, int r, int c) const {
+    return (double)x[e] * (double)k0<T>(r * Geo<DIM>::ND + c);
+  }
+};
+
+// Displacement block of the augmented Newton matrix on the finest grid:
+// A_e = x_e K0 + h_e h_e', h_e = sqrt(1/D_e) K0 u_e (eq. (nwtr2Z)).  h is stored
+// component-major: h[col * m + e].
+template <int DIM, typename T>
+struct OpFineZ {
+  const T* x;
+  const T* h;
+  int64_t m;
+  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+    constexpr int ND = Geo<DIM>::ND;
+    const T xe = x[e];
+    T hv = 0;
+#pragma unroll
+    for (int col = 0; col < ND; ++col) hv += h[col * m + e] * ve[col];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      T s = 0;
+#pragma unroll
+      for (int col = 0; col < ND; ++col) s += k0<T>(r * ND + col) * ve[col];
+      acc[c] += xe * s + h[r * m + e] * hv;
+    }
+  }
+  __device__ inline void diag(int64_t e, int a, T* dg) const {
+    constexpr int ND = Geo<DIM>::ND;
+    const T xe = x[e];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      const T hr = h[r * m + e];
+      dg[c] += xe * k0<T>(r * ND + r) + hr * hr;
+    }
+  }
+  __device__ inline double entry(int64_t e, int r, int c) const {
+    return (double)x[e] * (double)k0<T>(r * Geo<DIM>::ND + c) +
+           (double)h[r * m + e] * (double)h[c * m + e];
+  }
+};
+
+// Coarse level: general symmetric element matrices from the Galerkin products,
+// packed upper-triangular, stored E[sym(r,c) * m + e].
+template <int DIM, typename T>
+struct OpCoarse {
+  const T* E;
+  int64_t m;
+  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+    constexpr int ND = Geo<DIM>::ND;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      T s = 0;
+#pragma unroll
+      for (int col = 0; col < ND; ++col) s += E[sym_index(r, col, ND) * m + e] * ve[col];
+      acc[c] += s;
+    }
+  }
+  __device__ inline void diag(int64_t e, int a, T* dg) const {
+    constexpr int ND = Geo<DIM>::ND;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      dg[c] += E[sym_index(r, r, ND) * m + e];
+    }
+  }
+  __device__ inline double entry(int64_t e, int r, int c) const {
+    return (double)E[sym_index(r, c, Geo<DIM>::ND) * m + e];
+  }
+};
+
+// Border of the augmented matrix (lambda row/column): b (n_slots) and corner c.
+template <typename T>
+struct Aug {
+  const T* b;     // nullptr: no border (plain K)
+  double c;
+  int64_t n;      // index of lambda in level vectors (= n_slots)
+};
+
+// ------------------------------------------------------------- node helpers --
+template <int DIM, typename T>
+__device__ inline void load_node(const T* __restrict__ v, int64_t q, T* out) {
+  if constexpr (DIM == 2) {
+    if constexpr (sizeof(T) == 8) {
+      const double2 t = *reinterpret_cast<const double2*>(v + 2 * q);
+      out[0] = t.x; out[1] = t.y;
+    } else {
+      const float2 t = *reinterpret_cast<const float2*>(v + 2 * q);
+      out[0] = t.x; out[1] = t.y;
+    }
+  } else {
+    out[0] = v[3 * q]; out[1] = v[3 * q + 1]; out[2] = v[3 * q + 2];
+  }
+}
+
+template <int DIM, typename T>
+__device__ inline void store_node(T* __restrict__ v, int64_t q, const T* in) {
+  if constexpr (DIM == 2) {
+    if constexpr (sizeof(T) == 8) {
+      *reinterpret_cast<double2*>(v + 2 * q) = make_double2(in[0], in[1]);
+    } else {
+      *reinterpret_cast<float2*>(v + 2 * q) = make_float2(in[0], in[1]);
+    }
+  } else {
+    v[3 * q] = in[0]; v[3 * q + 1] = in[1]; v[3 * q + 2] = in[2];
+  }
+}
+
+// Gather v on the 3^dim neighbourhood of node (i,j,k); nodes outside the grid and
+// clamped nodes (i == 0) read as zero.
+template <int DIM, typename T>
+__device__ inline void load_neighbourhood(const T* __restrict__ v, const Dims& d, int i, int j, int k,
+                                          T (&vn)[Geo<DIM>::NB][DIM]) {
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nb = nb_index<DIM>(dx, dy, dz);
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        const bool in = ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1 && kk >= 0 && kk < d.nz1;
+        if (in) {
+          load_node<DIM, T>(v, ((int64_t)kk * d.ny1 + jj) * d.nx1 + ii, vn[nb]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) vn[nb][c] = T(0);
+        }
+      }
+}
+
+// acc += (A v) at node (i,j,k) and dg += diag(A) there, summing over the 2^dim
+// elements that share the node (gather form: no atomics, fixed order).
+template <int DIM, typename T, class Op, bool ROWS, bool DIAG>
+__device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int k,
+                                  const T (&vn)[Geo<DIM>::NB][DIM], T* acc, T* dg) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+#pragma unroll
+  for (int q = 0; q < NN; ++q) {
+    const int ex = q & 1, ey = (q >> 1) & 1, ez = (q >> 2) & 1;
+    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny &&
+                    (DIM == 2 || (ek >= 0 && ek < d.nz));
+    if (!ok) continue;
+    const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
+    const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
+    if constexpr (ROWS) {
+      T ve[ND];
+#pragma unroll
+      for (int b = 0; b < NN; ++b) {
+        const int nb = nb_index<DIM>(ex + loc_x(b) - 1, ey + loc_y(b) - 1,
+                                     DIM == 3 ? ez + loc_z(b) - 1 : 0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = vn[nb][c];
+      }
+      op.rows(e, a, ve, acc);
+    }
+    if constexpr (DIAG) op.diag(e, a, dg);
+  }
+}
+
+// ------------------------------------------------------------ level kernels --
+enum LevelMode { M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5 };
+
+// One pass over the nodes of a level.
+//   M_APPLY    out = A v
+//   M_RESID    out = r - A v
+//   M_JACOBI   out = v + omega D^-1 (r - A v)       (damped Jacobi sweep)
+//   M_JACOBI0  out = omega D^-1 r                   (first sweep from v = 0)
+//   M_POWER    out = D^-1 A v / ||v||, scal[sidx] = ||out||^2 (||v||^2 read from
+//              scal[sidx_in] when sidx_in >= 0, else taken as 1)
+//   M_RAYLEIGH scal[sidx] = v'Av, scal[sidx+1] = v'Dv
+// Clamped slots of out are written as 0.  With a border (aug.b != nullptr) the
+// lambda entry (index aug.n) is handled by the last block of a reduction.
+template <int DIM, typename T, class Op, int MODE>
+__global__ __launch_bounds__(BS) void k_level(Op op, Dims d, const T* __restrict__ v,
+                                              const T* __restrict__ r, T* __restrict__ out,
+                                              const double* __restrict__ omg, Aug<T> aug, Red red, int sidx,
+                                              int sidx_in, const int* gate) {
+  if (gate && *gate) return;
+  const T omega = omg ? T(*omg) : T(0);
+  double pin = 1.0;
+  if constexpr (MODE == M_POWER) {
+    if (sidx_in >= 0) {
+      const double s = red.scal[sidx_in];
+      pin = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+    }
+  }
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  const bool active = i < d.nx1 && j < d.ny1;
+  constexpr bool NEED_ROWS = MODE != M_JACOBI0;
+  constexpr bool NEED_RED = MODE == M_POWER || MODE == M_RAYLEIGH;
+  double red0 = 0.0, red1 = 0.0;   // border dot b.v (aug) / mode reductions
+  double bdot = 0.0;
+  if (active) {
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    T o[DIM];
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) o[c] = T(0);
+    } else {
+      T acc[DIM], dg[DIM], vc[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
+      if constexpr (NEED_ROWS) {
+        T vn[Geo<DIM>::NB][DIM];
+        load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
+        node_apply<DIM, T, Op, true, true>(op, d, i, j, k, vn, acc, dg);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
+        if (aug.b) {
+          const T vl = v[aug.n];
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) {
+            const T bc = aug.b[q * DIM + c];
+            acc[c] += bc * vl;
+            bdot += (double)bc * (double)vc[c];
+          }
+        }
+      } else {
+        T vn[Geo<DIM>::NB][DIM];
+        node_apply<DIM, T, Op, false, true>(op, d, i, j, k, vn, acc, dg);
+      }
+      T rr[DIM];
+      if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0)
+        load_node<DIM, T>(r, q, rr);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        if constexpr (MODE == M_APPLY) o[c] = acc[c];
+        if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
+        if constexpr (MODE == M_JACOBI) o[c] = vc[c] + omega * (rr[c] - acc[c]) / dg[c];
+        if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] / dg[c];
+        if constexpr (MODE == M_POWER) {
+          o[c] = T(pin * (double)(acc[c] / dg[c]));
+          red0 += (double)o[c] * (double)o[c];
+        }
+        if constexpr (MODE == M_RAYLEIGH) {
+          red0 += (double)vc[c] * (double)acc[c];
+          red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
+        }
+      }
+    }
+    if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+  }
+  if (aug.b) {
+    if constexpr (MODE == M_JACOBI0) {
+      if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+        out[aug.n] = T((double)omega * (double)r[aug.n] / aug.c);
+    } else {
+      double vals[3] = {bdot, red0, red1};
+      double tot[3];
+      if (reduce_last<3>(vals, red, C_AUX, tot)) {
+        if (threadIdx.x == 0) {
+          const double vl = (double)v[aug.n];
+          const double rowl = tot[0] + aug.c * vl;   // (Z v)_lambda
+          if constexpr (MODE == M_APPLY) out[aug.n] = T(rowl);
+          if constexpr (MODE == M_RESID) out[aug.n] = T((double)r[aug.n] - rowl);
+          if constexpr (MODE == M_JACOBI)
+            out[aug.n] = T(vl + (double)omega * ((double)r[aug.n] - rowl) / aug.c);
+          if constexpr (MODE == M_POWER) {
+            const double ol = pin * rowl / aug.c;
+            out[aug.n] = T(ol);
+            red.scal[sidx] = tot[1] + ol * ol;
+          }
+          if constexpr (MODE == M_RAYLEIGH) {
+            red.scal[sidx] = tot[1] + vl * rowl;
+            red.scal[sidx + 1] = tot[2] + vl * aug.c * vl;
+          }
+        }
+      }
+    }
+  } else if constexpr (NEED_RED) {
+    double vals[2] = {red0, red1};
+    double tot[2];
+    if (reduce_last<2>(vals, red, C_AUX, tot)) {
+      if (threadIdx.x == 0) {
+        red.scal[sidx] = tot[0];
+        if constexpr (MODE == M_RAYLEIGH) red.scal[sidx + 1] = tot[1];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- transfers --
+// 1D linear interpolation weight between a fine offset and its coarse node.
+__device__ inline float w1(int off) { return off == 0 ? 1.0f : 0.5f; }
+
+// Restriction rc = P' rf (transpose of the bilinear / trilinear prolongation,
+// Sec. 7), one thread per coarse node; clamped coarse nodes get 0.
+template <int DIM, typename T, typename TS = T>
+__global__ __launch_bounds__(BS) void k_restrict(Dims f, Dims c, const TS* __restrict__ rf,
+                                                 T* __restrict__ rc, int aug, const int* gate) {
+  if (gate && *gate) return;
+  const int I = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int J = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
+  const int K = blockIdx.z;
+  if (aug && I == 0 && J == 0 && K == 0) rc[c.nslots] = T(rf[f.nslots]);
+  if (I >= c.nx1 || J >= c.ny1) return;
+  const int64_t qc = ((int64_t)K * c.ny1 + J) * c.nx1 + I;
+  T acc[DIM];
+#pragma unroll
+  for (int cc = 0; cc < DIM; ++cc) acc[cc] = T(0);
+  if (I > 0) {
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
+          if (i < 1 || i >= f.nx1 || j < 0 || j >= f.ny1 || k < 0 || k >= f.nz1) continue;
+          const T w = T(w1(dx) * w1(dy) * (DIM == 3 ? w1(dz) : 1.0f));
+          TS vv[DIM];
+          load_node<DIM, TS>(rf, ((int64_t)k * f.ny1 + j) * f.nx1 + i, vv);
+#pragma unroll
+          for (int cc = 0; cc < DIM; ++cc) acc[cc] += w * T(vv[cc]);
+        }
+  }
+  store_node<DIM, T>(rc, qc, acc);
+}
+
+// Prolongation and correction z += P zc (Sec. 5.1 solution update), one thread
+// per fine node.
+template <int DIM, typename T>
+__global__ __launch_bounds__(BS) void k_prolong(Dims f, Dims c, T* __restrict__ z,
+                                                const T* __restrict__ zc, int aug, const int* gate) {
+  if (gate && *gate) return;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (aug && i == 0 && j == 0 && k == 0) z[f.nslots] += zc[c.nslots];
+  if (i >= f.nx1 || j >= f.ny1 || i == 0) return;
+  const int64_t q = ((int64_t)k * f.ny1 + j) * f.nx1 + i;
+  T acc[DIM];
+  load_node<DIM, T>(z, q, acc);
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
+  for (int a = 0; a < nk; ++a)
+    for (int b = 0; b < nj; ++b)
+      for (int e = 0; e < ni; ++e) {
+        const int I = (i >> 1) + e, J = (j >> 1) + b, K = DIM == 3 ? (k >> 1) + a : 0;
+        const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f) * (nk == 2 ? 0.5f : 1.0f));
+        T vv[DIM];
+        load_node<DIM, T>(zc, ((int64_t)K * c.ny1 + J) * c.nx1 + I, vv);
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) acc[cc] += w * vv[cc];
+      }
+  store_node<DIM, T>(z, q, acc);
+}
+
+// ------------------------------------------------------------------ Galerkin --
+// Coarse element matrices A_C = sum_{fine e in C} W_e' A_e W_e (Sec. 5.1), where
+// W_e interpolates the 2^dim coarse corner values of C to the nodes of fine
+// element e (each fine node interpolates only from the corners of the coarse
+// element containing it, so the sum equals the Galerkin product P' A P).
+// One thread per (coarse element, coarse local row R); writes the packed
+// entries (R, col >= R).  Accumulation in FP64, stored as T.
+template <int DIM, typename T, class Op>
+__global__ __launch_bounds__(BS) void k_galerkin(Op op, Dims f, Dims c, T* __restrict__ Ec) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  const int64_t tid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (tid >= c.m * ND) return;
+  const int R = (int)(tid % ND);
+  const int64_t C = tid / ND;
+  const int CI = (int)(C % c.nx), CJ = (int)((C / c.nx) % c.ny), CK = DIM == 3 ? (int)(C / ((int64_t)c.nx * c.ny)) : 0;
+  const int A = R / DIM, comp = R % DIM;
+  double row[ND];
+#pragma unroll
+  for (int col = 0; col < ND; ++col) row[col] = 0.0;
+  for (int qe = 0; qe < NN; ++qe) {                 // fine sub-element offset in C
+    const int qx = qe & 1, qy = (qe >> 1) & 1, qz = (qe >> 2) & 1;
+    const int64_t e = ((int64_t)(2 * CK + qz) * f.ny + (2 * CJ + qy)) * f.nx + (2 * CI + qx);
+    // weight of coarse corner B at fine local node a: product of 1D hat values
+    double W[NN][NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a)
+#pragma unroll
+      for (int B = 0; B < NN; ++B) {
+        const int px = qx + loc_x(a), py = qy + loc_y(a), pz = qz + loc_z(a);   // 0..2
+        const double wx = 1.0 - fabs(0.5 * px - loc_x(B));
+        const double wy = 1.0 - fabs(0.5 * py - loc_y(B));
+        const double wz = DIM == 3 ? 1.0 - fabs(0.5 * pz - loc_z(B)) : 1.0;
+        W[a][B] = wx * wy * wz;
+      }
+    for (int a = 0; a < NN; ++a) {
+      const double wa = W[a][A];
+      if (wa == 0.0) continue;
+      for (int b = 0; b < NN; ++b) {
+        for (int cb = 0; cb < DIM; ++cb) {
+          const double t = wa * op.entry(e, a * DIM + comp, b * DIM + cb);
+#pragma unroll
+          for (int B = 0; B < NN; ++B) row[B * DIM + cb] += t * W[b][B];
+        }
+      }
+    }
+  }
+  for (int col = R; col < ND; ++col) Ec[(int64_t)sym_index(R, col, ND) * c.m + C] = T(row[col]);
+}
+
+// ---------------------------------------------------------- coarsest solve --
+// Dense operator of the coarsest level over all slots (+ lambda): rows gathered
+// from the element matrices; clamped rows/columns replaced by identity.
+template <int DIM, class Op, typename TB>
+__global__ __launch_bounds__(BS) void k_dense_assemble(Op op, Dims d, const TB* border, double corner,
+                                                       int aug, double* __restrict__ A, int n) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  const int row = blockIdx.x * BS + threadIdx.x;
+  if (row >= n) return;
+  double* Ar = A + (int64_t)row * n;
+  for (int col = 0; col < n; ++col) Ar[col] = 0.0;
+  if (aug && row == n - 1) {
+    for (int s = 0; s < n - 1; ++s) {
+      const int q = s / DIM;
+      Ar[s] = (q % d.nx1 == 0) ? 0.0 : (double)border[s];
+    }
+    Ar[row] = corner;
+    return;
+  }
+  const int q = row / DIM, comp = row % DIM;
+  const int i = q % d.nx1, j = (q / d.nx1) % d.ny1, k = DIM == 3 ? q / (d.nx1 * d.ny1) : 0;
+  if (i == 0) { Ar[row] = 1.0; return; }
+  for (int qq = 0; qq < NN; ++qq) {
+    const int ex = qq & 1, ey = (qq >> 1) & 1, ez = (qq >> 2) & 1;
+    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    if (ei < 0 || ei >= d.nx || ej < 0 || ej >= d.ny || (DIM == 3 && (ek < 0 || ek >= d.nz))) continue;
+    const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
+    const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
+    for (int b = 0; b < NN; ++b) {
+      const int bi = ei + loc_x(b), bj = ej + loc_y(b), bk = DIM == 3 ? ek + loc_z(b) : 0;
+      if (bi == 0) continue;
+      const int qb = (bk * d.ny1 + bj) * d.nx1 + bi;
+      for (int cb = 0; cb < DIM; ++cb) Ar[qb * DIM + cb] += op.entry(e, a * DIM + comp, b * DIM + cb);
+    }
+  }
+  if (aug) Ar[n - 1] = (double)border[row];
+}
+
+}  // namespace ipmg

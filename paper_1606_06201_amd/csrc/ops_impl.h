@@ -1,0 +1,467 @@
+// Per-dimension kernel set: element stiffness, sensitivities, interior-point
+// element/node kernels and the dispatch of the level kernels (kernels.h).
+#pragma once
+#include "ctx.h"
+#include "kernels.h"
+
+namespace ipmg {
+
+// ---------------------------------------------------------- element matrix --
+// K0 = integral over the unit element of the isotropic elasticity bilinear form
+//   K[(a,i),(b,j)] = int lam dN_a/dx_i dN_b/dx_j + mu (delta_ij grad N_a . grad N_b
+//                                                     + dN_a/dx_j dN_b/dx_i)
+// (plane stress in 2D: lam = E nu / (1 - nu^2)), 2-point Gauss rule per axis.
+template <int DIM>
+__global__ void k_element_stiffness(double E, double nu, double* __restrict__ K) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ND * ND) return;
+  const int r = t / ND, c = t % ND;
+  const int a = r / DIM, i = r % DIM, b = c / DIM, j = c % DIM;
+  const double mu = E / (2.0 * (1.0 + nu));
+  const double lam = DIM == 2 ? E * nu / (1.0 - nu * nu) : E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double g = 0.5 / sqrt(3.0);
+  const double pts[2] = {0.5 - g, 0.5 + g};
+  const double w = DIM == 2 ? 0.25 : 0.125;
+  int oa[3] = {loc_x(a), loc_y(a), loc_z(a)}, ob[3] = {loc_x(b), loc_y(b), loc_z(b)};
+  double s = 0.0;
+  for (int gp = 0; gp < NN; ++gp) {
+    double xi[3] = {pts[gp & 1], pts[(gp >> 1) & 1], pts[(gp >> 2) & 1]};
+    double da[3], db[3];
+    for (int d = 0; d < DIM; ++d) {
+      double pa = oa[d] ? 1.0 : -1.0, pb = ob[d] ? 1.0 : -1.0;
+      for (int e = 0; e < DIM; ++e) {
+        if (e == d) continue;
+        pa *= oa[e] ? xi[e] : 1.0 - xi[e];
+        pb *= ob[e] ? xi[e] : 1.0 - xi[e];
+      }
+      da[d] = pa; db[d] = pb;
+    }
+    double dot = 0.0;
+    for (int d = 0; d < DIM; ++d) dot += da[d] * db[d];
+    s += w * (lam * da[i] * db[j] + mu * ((i == j ? dot : 0.0) + da[j] * db[i]));
+  }
+  K[t] = s;
+}
+
+// Element coordinates of element e.
+template <int DIM>
+__device__ inline void elem_coords(const Dims& d, int64_t e, int& ei, int& ej, int& ek) {
+  ei = (int)(e % d.nx);
+  ej = (int)((e / d.nx) % d.ny);
+  ek = DIM == 3 ? (int)(e / ((int64_t)d.nx * d.ny)) : 0;
+}
+
+// Gather the local vector of element e from a slot vector (clamped slots read 0).
+template <int DIM>
+__device__ inline void gather_elem(const double* __restrict__ v, const Dims& d, int ei, int ej, int ek,
+                                   double* ve) {
+  constexpr int NN = Geo<DIM>::NN;
+#pragma unroll
+  for (int b = 0; b < NN; ++b) {
+    const int i = ei + loc_x(b), j = ej + loc_y(b), k = DIM == 3 ? ek + loc_z(b) : 0;
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = (i == 0) ? 0.0 : v[q * DIM + c];
+  }
+}
+
+// g_e = scale * w_e' K0 u_e  (B(u)' w scaled).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_elem_sens(Dims d, const double* __restrict__ w, const double* __restrict__ u,
+                                                  double scale, double* __restrict__ g) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= d.m) return;
+  int ei, ej, ek;
+  elem_coords<DIM>(d, e, ei, ej, ek);
+  double we[ND], ue[ND];
+  gather_elem<DIM>(w, d, ei, ej, ek, we);
+  gather_elem<DIM>(u, d, ei, ej, ek, ue);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < ND; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) t += cK0d[r * ND + c] * ue[c];
+    s += we[r] * t;
+  }
+  g[e] = scale * s;
+}
+
+// Start vector of the spectral-radius estimate: (-1)^(i+j+k) (1 + c), 0 on clamped
+// slots, 1 on lambda.
+template <int DIM, typename T>
+__global__ __launch_bounds__(BS) void k_power_start(Dims d, int aug, T* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t == d.nslots && aug) v[t] = T(1);
+  if (t >= d.nslots) return;
+  const int64_t q = t / DIM;
+  const int c = (int)(t % DIM);
+  const int i = (int)(q % d.nx1), j = (int)((q / d.nx1) % d.ny1), k = (int)(q / ((int64_t)d.nx1 * d.ny1));
+  const double sg = ((i + j + k) & 1) ? -1.0 : 1.0;
+  v[t] = i == 0 ? T(0) : T(sg * (1.0 + c));
+}
+
+// ---------------------------------------------------------- interior point --
+// Per element at the current iterate (Sec. 2): g = K0 u_e, F3, F4, F5,
+// D = phi/x + psi/(xbar-x), G3 = F3 + F4/x - F5/(xbar-x), w = 1/D,
+// h = sqrt(w) g (rank-one factor of Z), and the sums
+//   scal[S_TMP0..6] = sum w, sum G3 w, sum x, ||G3||^2, ||phi||^2, ||psi||^2,
+//                     phi'x + psi'(xbar - x).
+template <int DIM, typename T>
+__global__ __launch_bounds__(BS) void k_ip_elements(Dims d, const double* __restrict__ u, const double* __restrict__ x,
+                                                    const double* __restrict__ phi, const double* __restrict__ psi,
+                                                    double lam, double s, double r, double xbar,
+                                                    double* __restrict__ G3o, double* __restrict__ Wo,
+                                                    double* __restrict__ SWo, double* __restrict__ h64,
+                                                    T* __restrict__ hT, Red red) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (e < d.m) {
+    int ei, ej, ek;
+    elem_coords<DIM>(d, e, ei, ej, ek);
+    double ue[ND], g[ND];
+    gather_elem<DIM>(u, d, ei, ej, ek, ue);
+    double en = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < ND; ++rr) {
+      double t = 0.0;
+#pragma unroll
+      for (int c = 0; c < ND; ++c) t += cK0d[rr * ND + c] * ue[c];
+      g[rr] = t;
+      en += ue[rr] * t;
+    }
+    const double xe = x[e], ph = phi[e], ps = psi[e], xt = xbar - xe;
+    if (!(xe > 0.0) || !(xt > 0.0) || !isfinite(xe) || !isfinite(ph) || !isfinite(ps) || !isfinite(en))
+      red.flags[F_BAD] = 1;
+    const double F3 = -0.5 * en - lam - ph + ps;
+    const double F4 = ph * xe - s;
+    const double F5 = ps * xt - r;
+    const double D = ph / xe + ps / xt;
+    const double G3 = F3 + F4 / xe - F5 / xt;
+    const double w = 1.0 / D, sw = sqrt(w);
+    G3o[e] = G3;
+    Wo[e] = w;
+    SWo[e] = sw;
+#pragma unroll
+    for (int rr = 0; rr < ND; ++rr) {
+      const double hv = sw * g[rr];
+      h64[rr * d.m + e] = hv;
+      if (hT) hT[rr * d.m + e] = T(hv);
+    }
+    acc[0] = w; acc[1] = G3 * w; acc[2] = xe; acc[3] = G3 * G3;
+    acc[4] = ph * ph; acc[5] = ps * ps; acc[6] = ph * xe + ps * xt;
+  }
+  double tot[7];
+  if (reduce_last<7>(acc, red, C_AUX, tot) && threadIdx.x == 0)
+    for (int n = 0; n < 7; ++n) red.scal[S_TMP0 + n] = tot[n];
+}
+
+// Per node: F1 = K u - f, border b = sum_e sqrt(w_e) h_e (= B D^-1 e), right-hand
+// side rhs_u = -F1 + sum_e G3_e sqrt(w_e) h_e (= -F1 + B D^-1 G3, eq. (nwtr2rhs)),
+// and rhs_lambda = -(sum x - V) + sum G3 w.  Sums: scal[S_MIN0..2] = ||F1||^2,
+// ||f||^2, f'u.
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_ip_nodes(Dims d, const double* __restrict__ Ku, const double* __restrict__ f,
+                                                 const double* __restrict__ u, const double* __restrict__ G3,
+                                                 const double* __restrict__ SW, const double* __restrict__ h64,
+                                                 double V, double* __restrict__ rhs, double* __restrict__ bZ,
+                                                 Red red) {
+  constexpr int NN = Geo<DIM>::NN;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  double acc[3] = {0, 0, 0};
+  if (i < d.nx1 && j < d.ny1) {
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    double bb[DIM], tt[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { bb[c] = 0.0; tt[c] = 0.0; }
+    if (i > 0) {
+#pragma unroll
+      for (int qq = 0; qq < NN; ++qq) {
+        const int ex = qq & 1, ey = (qq >> 1) & 1, ez = (qq >> 2) & 1;
+        const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+        if (ei < 0 || ei >= d.nx || ej < 0 || ej >= d.ny || (DIM == 3 && (ek < 0 || ek >= d.nz))) continue;
+        const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
+        const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
+        const double sw = SW[e], gw = G3[e] * sw;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const double hv = h64[(a * DIM + c) * d.m + e];
+          bb[c] += sw * hv;
+          tt[c] += gw * hv;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t sl = q * DIM + c;
+      const double fc = i > 0 ? f[sl] : 0.0;
+      const double F1 = i > 0 ? Ku[sl] - fc : 0.0;
+      rhs[sl] = i > 0 ? -F1 + tt[c] : 0.0;
+      bZ[sl] = bb[c];
+      acc[0] += F1 * F1;
+      acc[1] += fc * fc;
+      acc[2] += fc * (i > 0 ? u[sl] : 0.0);
+    }
+  }
+  double tot[3];
+  if (reduce_last<3>(acc, red, C_AUX, tot) && threadIdx.x == 0) {
+    red.scal[S_MIN0] = tot[0];
+    red.scal[S_MIN1] = tot[1];
+    red.scal[S_MIN2] = tot[2];
+    rhs[d.nslots] = -(red.scal[S_TMP2] - V) + red.scal[S_TMP1];
+  }
+}
+
+// Recovery of d_x, d_phi, d_psi from (d_u, d_lambda) and the fraction-to-boundary
+// step length (Sec. 3.3): scal[S_ALPHA] = min(1, frac * distance ratios).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_ip_recover(Dims d, const double* __restrict__ du, const double* __restrict__ x,
+                                                   const double* __restrict__ phi, const double* __restrict__ psi,
+                                                   const double* __restrict__ G3, const double* __restrict__ W,
+                                                   const double* __restrict__ SW, const double* __restrict__ h64,
+                                                   double s, double r, double xbar, double frac, int all_blocks,
+                                                   double* __restrict__ dx, double* __restrict__ dphi,
+                                                   double* __restrict__ dpsi, Red red) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double mins[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  if (e < d.m) {
+    int ei, ej, ek;
+    elem_coords<DIM>(d, e, ei, ej, ek);
+    double de[ND];
+    gather_elem<DIM>(du, d, ei, ej, ek, de);
+    double hd = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < ND; ++rr) hd += h64[rr * d.m + e] * de[rr];
+    const double dl = du[d.nslots];
+    const double xe = x[e], ph = phi[e], ps = psi[e], xt = xbar - xe;
+    // d_x = D^-1 (B' d_u + d_lambda - G3), B' d_u = g . d_u = (h . d_u) / sqrt(w)
+    const double ddx = SW[e] * hd + W[e] * (dl - G3[e]);
+    const double F4 = ph * xe - s, F5 = ps * xt - r;
+    const double ddphi = (-F4 - ph * ddx) / xe;
+    const double ddpsi = (-F5 + ps * ddx) / xt;
+    dx[e] = ddx; dphi[e] = ddphi; dpsi[e] = ddpsi;
+    if (ddx < 0.0) mins[0] = -xe / ddx;
+    if (ddx > 0.0) mins[1] = xt / ddx;
+    if (ddphi < 0.0) mins[2] = -ph / ddphi;
+    if (ddpsi < 0.0) mins[3] = -ps / ddpsi;
+  }
+  double tot[4];
+  if (reduce_last<4, true>(mins, red, C_AUX, tot) && threadIdx.x == 0) {
+    double a = fmin(1.0, fmin(frac * tot[0], frac * tot[1]));
+    if (all_blocks) a = fmin(a, fmin(frac * tot[2], frac * tot[3]));
+    red.scal[S_ALPHA] = a;
+    for (int n = 0; n < 4; ++n) red.scal[S_MIN0 + n] = tot[n];
+  }
+}
+
+// z += alpha d for (u, x, phi, psi).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_ip_update(Dims d, double* __restrict__ u, const double* __restrict__ du,
+                                                  double* __restrict__ x, double* __restrict__ phi,
+                                                  double* __restrict__ psi, const double* __restrict__ dx,
+                                                  const double* __restrict__ dphi, const double* __restrict__ dpsi,
+                                                  Red red) {
+  const double a = red.scal[S_ALPHA];
+  const int64_t n = d.nslots > d.m ? d.nslots : d.m;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+    if (t < d.nslots) u[t] += a * du[t];
+    if (t < d.m) {
+      x[t] += a * dx[t];
+      phi[t] += a * dphi[t];
+      psi[t] += a * dpsi[t];
+    }
+  }
+}
+
+// ------------------------------------------------------------------- dispatch --
+template <int DIM>
+struct OpsImpl : Ops {
+  static dim3 node_grid(const Dims& d) {
+    return dim3((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + BS / 64 - 1) / (BS / 64)), (unsigned)d.nz1);
+  }
+  static unsigned lin_grid(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
+
+  void element_stiffness(Ctx& c, double* dK0) override {
+    constexpr int ND = Geo<DIM>::ND;
+    k_element_stiffness<DIM><<<(ND * ND + 63) / 64, 64, 0, c.stream>>>(c.desc.E, c.desc.nu, dK0);
+  }
+  void upload_k0(const double* K0) override {
+    constexpr int ND = Geo<DIM>::ND;
+    float kf[576];
+    for (int t = 0; t < ND * ND; ++t) kf[t] = (float)K0[t];
+    IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0d), K0, sizeof(double) * ND * ND));
+    IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0f), kf, sizeof(float) * ND * ND));
+  }
+
+  template <typename T, class Op>
+  void launch_level(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out,
+                    const double* omg, Aug<T> aug, int sidx, int sidx_in, const int* gate) {
+    const dim3 g = node_grid(d);
+    IPMG_REQUIRE((int64_t)g.x * g.y * g.z <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+#define IPMG_LEVEL_CASE(M) \
+  case M: k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, gate); break;
+    switch (mode) {
+      IPMG_LEVEL_CASE(M_APPLY)
+      IPMG_LEVEL_CASE(M_RESID)
+      IPMG_LEVEL_CASE(M_JACOBI)
+      IPMG_LEVEL_CASE(M_JACOBI0)
+      IPMG_LEVEL_CASE(M_POWER)
+      IPMG_LEVEL_CASE(M_RAYLEIGH)
+      default: throw Error(IPMG_E_INVALID, "bad level mode");
+    }
+#undef IPMG_LEVEL_CASE
+  }
+
+  template <typename T>
+  void level_t(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out, const double* omg,
+               int sidx, int sidx_in, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    Aug<T> aug{op == IPMG_OP_Z ? (const T*)c.lev[lev].bZ : nullptr, c.cZ, d.nslots};
+    if (lev == c.L - 1) {
+      if (op == IPMG_OP_K)
+        launch_level<T>(c, d, OpFineK<DIM, T>{(const T*)c.xT, d.m}, mode, (const T*)v, (const T*)r, (T*)out, omg,
+                        aug, sidx, sidx_in, gate);
+      else
+        launch_level<T>(c, d, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, mode, (const T*)v, (const T*)r,
+                        (T*)out, omg, aug, sidx, sidx_in, gate);
+    } else {
+      launch_level<T>(c, d, OpCoarse<DIM, T>{(const T*)c.lev[lev].E, d.m}, mode, (const T*)v, (const T*)r, (T*)out,
+                      omg, aug, sidx, sidx_in, gate);
+    }
+  }
+
+  void level(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out, const double* omg,
+             int sidx, int sidx_in, const int* gate) override {
+    if (c.fp32) level_t<float>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate);
+    else level_t<double>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate);
+  }
+
+  void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) override {
+    const Dims& d = c.fine();
+    if (op == IPMG_OP_K) {
+      launch_level<double>(c, d, OpFineK<DIM, double>{c.x64, d.m}, M_APPLY, v, nullptr, y, nullptr,
+                           Aug<double>{nullptr, 0.0, d.nslots}, 0, -1, gate);
+    } else {
+      launch_level<double>(c, d, OpFineZ<DIM, double>{c.x64, c.h64, d.m}, M_APPLY, v, nullptr, y, nullptr,
+                           Aug<double>{c.bZ64, c.cZ, d.nslots}, 0, -1, gate);
+    }
+  }
+
+  void restrict_to(Ctx& c, int lev_f, const void* rf, void* rc, int aug, const int* gate) override {
+    const Dims& f = c.lev[lev_f].d;
+    const Dims& cd = c.lev[lev_f - 1].d;
+    if (c.fp32)
+      k_restrict<DIM, float><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const float*)rf, (float*)rc, aug, gate);
+    else
+      k_restrict<DIM, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (double*)rc, aug, gate);
+  }
+  void restrict64_to_T(Ctx& c, int lev_f, const void* rf, void* rc) override {
+    const Dims& f = c.lev[lev_f].d;
+    const Dims& cd = c.lev[lev_f - 1].d;
+    if (c.fp32)
+      k_restrict<DIM, float, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (float*)rc, 0,
+                                                                          nullptr);
+    else
+      k_restrict<DIM, double, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (double*)rc, 0,
+                                                                           nullptr);
+  }
+  void prolong_from(Ctx& c, int lev_f, void* z, const void* zc, int aug, const int* gate) override {
+    const Dims& f = c.lev[lev_f].d;
+    const Dims& cd = c.lev[lev_f - 1].d;
+    if (c.fp32)
+      k_prolong<DIM, float><<<node_grid(f), BS, 0, c.stream>>>(f, cd, (float*)z, (const float*)zc, aug, gate);
+    else
+      k_prolong<DIM, double><<<node_grid(f), BS, 0, c.stream>>>(f, cd, (double*)z, (const double*)zc, aug, gate);
+  }
+
+  template <typename T, class Op>
+  void launch_galerkin(Ctx& c, const Op& op, const Dims& f, const Dims& cd, T* Ec) {
+    constexpr int ND = Geo<DIM>::ND;
+    k_galerkin<DIM, T, Op><<<lin_grid(cd.m * ND), BS, 0, c.stream>>>(op, f, cd, Ec);
+  }
+  template <typename T>
+  void galerkin_t(Ctx& c, int lev_f, int op) {
+    const Dims& f = c.lev[lev_f].d;
+    const Dims& cd = c.lev[lev_f - 1].d;
+    T* Ec = (T*)c.lev[lev_f - 1].E;
+    if (lev_f == c.L - 1) {
+      if (op == IPMG_OP_K) launch_galerkin<T>(c, OpFineK<DIM, double>{c.x64, f.m}, f, cd, Ec);
+      else launch_galerkin<T>(c, OpFineZ<DIM, double>{c.x64, c.h64, f.m}, f, cd, Ec);
+    } else {
+      launch_galerkin<T>(c, OpCoarse<DIM, T>{(const T*)c.lev[lev_f].E, f.m}, f, cd, Ec);
+    }
+  }
+  void galerkin(Ctx& c, int lev_f, int op) override {
+    if (c.fp32) galerkin_t<float>(c, lev_f, op);
+    else galerkin_t<double>(c, lev_f, op);
+  }
+
+  template <typename T>
+  void dense_t(Ctx& c, int op, double* A, int n) {
+    const Dims& d = c.lev[0].d;
+    const int aug = op == IPMG_OP_Z;
+    const unsigned g = lin_grid(n);
+    if (c.L == 1) {
+      if (op == IPMG_OP_K)
+        k_dense_assemble<DIM, OpFineK<DIM, double>, double><<<g, BS, 0, c.stream>>>(
+            OpFineK<DIM, double>{c.x64, d.m}, d, c.bZ64, c.cZ, aug, A, n);
+      else
+        k_dense_assemble<DIM, OpFineZ<DIM, double>, double><<<g, BS, 0, c.stream>>>(
+            OpFineZ<DIM, double>{c.x64, c.h64, d.m}, d, c.bZ64, c.cZ, aug, A, n);
+    } else {
+      k_dense_assemble<DIM, OpCoarse<DIM, T>, T><<<g, BS, 0, c.stream>>>(
+          OpCoarse<DIM, T>{(const T*)c.lev[0].E, d.m}, d, (const T*)c.lev[0].bZ, c.cZ, aug, A, n);
+    }
+  }
+  void dense_assemble(Ctx& c, int op, double* A, int n) override {
+    if (c.fp32) dense_t<float>(c, op, A, n);
+    else dense_t<double>(c, op, A, n);
+  }
+
+  void power_start(Ctx& c, int lev, int aug, void* v) override {
+    const Dims& d = c.lev[lev].d;
+    if (c.fp32) k_power_start<DIM, float><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (float*)v);
+    else k_power_start<DIM, double><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (double*)v);
+  }
+
+  void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) override {
+    const Dims& d = c.fine();
+    k_elem_sens<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, w, u, scale, g);
+  }
+
+  void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi, double lam,
+                   double s, double r, double xbar) override {
+    const Dims& d = c.fine();
+    if (c.fp32)
+      k_ip_elements<DIM, float><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, x, phi, psi, lam, s, r, xbar, c.ipG3,
+                                                                     c.ipW, c.ipSW, c.h64, (float*)c.hT, c.red);
+    else
+      k_ip_elements<DIM, double><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, x, phi, psi, lam, s, r, xbar, c.ipG3,
+                                                                      c.ipW, c.ipSW, c.h64, nullptr, c.red);
+  }
+  void ip_nodes(Ctx& c, const double* Ku, const double* f, const double* u, double* rhs) override {
+    const Dims& d = c.fine();
+    k_ip_nodes<DIM><<<node_grid(d), BS, 0, c.stream>>>(d, Ku, f, u, c.ipG3, c.ipSW, c.h64, c.ipV, rhs, c.bZ64,
+                                                        c.red);
+  }
+  void ip_recover(Ctx& c, const double* du, const double* x, const double* phi, const double* psi, double s,
+                  double r, double xbar, double frac, int all_blocks) override {
+    const Dims& d = c.fine();
+    k_ip_recover<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, du, x, phi, psi, c.ipG3, c.ipW, c.ipSW, c.h64, s, r,
+                                                           xbar, frac, all_blocks, c.ipDx, c.ipDphi, c.ipDpsi, c.red);
+  }
+  void ip_update(Ctx& c, double* u, const double* du, double* x, double* phi, double* psi) override {
+    const Dims& d = c.fine();
+    const int64_t n = d.nslots > d.m ? d.nslots : d.m;
+    const unsigned g = lin_grid(n) < 2048 ? lin_grid(n) : 2048;
+    k_ip_update<DIM><<<g, BS, 0, c.stream>>>(d, u, du, x, phi, psi, c.ipDx, c.ipDphi, c.ipDpsi, c.red);
+  }
+};
+
+}  // namespace ipmg

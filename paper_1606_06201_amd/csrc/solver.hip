@@ -1,0 +1,504 @@
+// Host driver: context set-up, multigrid hierarchy (Sec. 5.1), V-cycle, PCG
+// (Sec. 5.2) and the interior-point step (Sec. 3).  All arithmetic runs in the
+// kernels; the host only sequences launches and reads scalars.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+#include "kernels.h"
+#include "vec.h"
+
+namespace ipmg {
+
+namespace {
+
+template <typename P>
+void dalloc(P*& p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes ? bytes : 8) != hipSuccess) throw Error(IPMG_E_NOMEM, "device allocation failed");
+  p = (P*)q;
+}
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// Safeguard of the Jacobi damping on every level except the coarsest:
+// omega_k = min(omega, SAFE_PRODUCT / rho_k), rho_k the Rayleigh-quotient estimate of
+// the largest eigenvalue of D_k^-1 A_k after POWER_STEPS power iterations.  Damped
+// Jacobi diverges once omega * rho >= 2, which happens for omega = 0.6 on 3D
+// elasticity and on the augmented system Z late in the interior-point run.
+constexpr double SAFE_PRODUCT = 1.6;
+constexpr int POWER_STEPS = 12;
+
+}  // namespace
+
+void sync(Ctx& c) { IPMG_HIP(hipStreamSynchronize(c.stream)); }
+
+void read_scalars(Ctx& c) {
+  IPMG_HIP(hipMemcpyAsync(c.hscal, c.red.scal, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, c.stream));
+  IPMG_HIP(hipMemcpyAsync(c.hflags, c.red.flags, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, c.stream));
+  sync(c);
+}
+
+static void ensure_z_buffers(Ctx& c) {
+  if (c.h64) return;
+  const Dims& d = c.fine();
+  const size_t m = (size_t)d.m, n1 = (size_t)d.nslots + 1;
+  dalloc(c.h64, sizeof(double) * c.nd * m);
+  if (c.fp32) dalloc(c.hT, sizeof(float) * c.nd * m);
+  else c.hT = c.h64;
+  dalloc(c.bZ64, sizeof(double) * n1);
+  if (c.fp32) dalloc(c.lev[c.L - 1].bZ, sizeof(float) * n1);
+  else c.lev[c.L - 1].bZ = c.bZ64;
+  for (int k = 0; k < c.L - 1; ++k) dalloc(c.lev[k].bZ, c.tsz * ((size_t)c.lev[k].d.nslots + 1));
+  dalloc(c.ipG3, sizeof(double) * m);
+  dalloc(c.ipW, sizeof(double) * m);
+  dalloc(c.ipSW, sizeof(double) * m);
+  dalloc(c.ipDx, sizeof(double) * m);
+  dalloc(c.ipDphi, sizeof(double) * m);
+  dalloc(c.ipDpsi, sizeof(double) * m);
+  dalloc(c.ipRhs, sizeof(double) * n1);
+  dalloc(c.ipD, sizeof(double) * n1);
+  dalloc(c.ipKu, sizeof(double) * n1);
+}
+
+void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
+  IPMG_REQUIRE(d.dim == 2 || d.dim == 3, IPMG_E_INVALID, "dim must be 2 or 3");
+  IPMG_REQUIRE(d.levels >= 1 && d.levels <= 16, IPMG_E_INVALID, "levels must be in [1, 16]");
+  IPMG_REQUIRE(d.nu_pre >= 1 && d.nu_post >= 0 && d.nu_pre <= 64 && d.nu_post <= 64, IPMG_E_INVALID,
+               "sweeps: need 1 <= nu_pre <= 64, 0 <= nu_post <= 64");
+  IPMG_REQUIRE(d.omega > 0.0 && d.omega < 2.0, IPMG_E_INVALID, "omega must be in (0, 2)");
+  IPMG_REQUIRE(d.E > 0.0 && d.nu > -1.0 && d.nu < 0.5, IPMG_E_INVALID, "material: E > 0, -1 < nu < 0.5");
+  const int f = 1 << (d.levels - 1);
+  for (int a = 0; a < d.dim; ++a) {
+    IPMG_REQUIRE(d.nel[a] >= 1 && d.nel[a] <= (1 << 16), IPMG_E_INVALID, "element counts must be in [1, 65536]");
+    IPMG_REQUIRE(d.nel[a] % f == 0, IPMG_E_INVALID, "element counts must be divisible by 2^(levels-1)");
+  }
+  c.desc = d;
+  c.dim = d.dim;
+  c.fp32 = d.vcycle_fp32 != 0;
+  c.tsz = c.fp32 ? sizeof(float) : sizeof(double);
+  c.L = d.levels;
+  c.stream = st;
+  c.nd = d.dim * (1 << d.dim);
+  c.ops = d.dim == 2 ? make_ops2d() : make_ops3d();
+  c.lev.resize(c.L);
+  for (int k = 0; k < c.L; ++k) {
+    const int s = 1 << (c.L - 1 - k);
+    c.lev[k].d = make_dims(d.dim, d.nel[0] / s, d.nel[1] / s, d.dim == 3 ? d.nel[2] / s : 1);
+  }
+  const Dims& fd = c.fine();
+  IPMG_REQUIRE(fd.nslots < ((int64_t)1 << 31), IPMG_E_INVALID, "grid too large");
+  c.ncoarse = (int)std::min<int64_t>(c.lev[0].d.nslots + 1, (int64_t)1 << 30);
+
+  // reductions
+  dalloc(c.red.partials, sizeof(double) * 8 * MAX_PARTIALS);
+  dalloc(c.red.counter, sizeof(unsigned) * C_COUNT);
+  dalloc(c.red.scal, sizeof(double) * S_COUNT);
+  dalloc(c.red.flags, sizeof(int) * F_COUNT);
+  IPMG_HIP(hipMemsetAsync(c.red.counter, 0, sizeof(unsigned) * C_COUNT, st));
+  IPMG_HIP(hipMemsetAsync(c.red.scal, 0, sizeof(double) * S_COUNT, st));
+  IPMG_HIP(hipMemsetAsync(c.red.flags, 0, sizeof(int) * F_COUNT, st));
+  if (hipHostMalloc((void**)&c.hscal, sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess)
+    throw Error(IPMG_E_NOMEM, "pinned allocation failed");
+  if (hipHostMalloc((void**)&c.hflags, sizeof(int) * F_COUNT * 4, hipHostMallocDefault) != hipSuccess)
+    throw Error(IPMG_E_NOMEM, "pinned allocation failed");
+  IPMG_HIP(hipEventCreate(&c.ev0));
+  IPMG_HIP(hipEventCreate(&c.ev1));
+
+  // level vectors
+  const int nsym = c.nd * (c.nd + 1) / 2;
+  for (int k = 0; k < c.L; ++k) {
+    Level& l = c.lev[k];
+    const size_t n1 = (size_t)l.d.nslots + 1;
+    dalloc(l.r, c.tsz * n1);
+    dalloc(l.z, c.tsz * n1);
+    dalloc(l.z2, c.tsz * n1);
+    dalloc(l.t, c.tsz * n1);
+    IPMG_HIP(hipMemsetAsync(l.z, 0, c.tsz * n1, st));
+    IPMG_HIP(hipMemsetAsync(l.z2, 0, c.tsz * n1, st));
+    if (k < c.L - 1) dalloc(l.E, c.tsz * (size_t)nsym * (size_t)l.d.m);
+  }
+  dalloc(c.x64, sizeof(double) * fd.m);
+  if (c.fp32) dalloc(c.xT, sizeof(float) * fd.m);
+  else c.xT = c.x64;
+  const size_t n1 = (size_t)fd.nslots + 1;
+  dalloc(c.pr, sizeof(double) * n1);
+  dalloc(c.pp, sizeof(double) * n1);
+  dalloc(c.pq, sizeof(double) * n1);
+  dalloc(c.pt, sizeof(double) * n1);
+  dalloc(c.pb, sizeof(double) * n1);
+  dalloc(c.pu, sizeof(double) * n1);
+  dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
+  vfill_small(st, c.omega_dev, c.L, d.omega);
+
+  // element matrix on the GPU, mirrored to the host and to constant memory
+  double* dK0 = nullptr;
+  dalloc(dK0, sizeof(double) * c.nd * c.nd);
+  c.ops->element_stiffness(c, dK0);
+  IPMG_HIP(hipGetLastError());
+  IPMG_HIP(hipMemcpyAsync(c.K0, dK0, sizeof(double) * c.nd * c.nd, hipMemcpyDeviceToHost, st));
+  sync(c);
+  dfree(dK0);
+  c.ops->upload_k0(c.K0);
+}
+
+void ctx_free(Ctx& c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  for (auto& l : c.lev) {
+    dfree(l.r); dfree(l.z); dfree(l.z2); dfree(l.t); dfree(l.E);
+    if (l.bZ != (void*)c.bZ64) dfree(l.bZ);
+    l.bZ = nullptr;
+  }
+  if (c.xT != (void*)c.x64) dfree(c.xT);
+  c.xT = nullptr;
+  if (c.hT != (void*)c.h64) dfree(c.hT);
+  c.hT = nullptr;
+  dfree(c.x64); dfree(c.h64); dfree(c.bZ64);
+  dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu);
+  dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.omega_dev);
+  dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
+  dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
+  dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
+  if (c.hscal) (void)hipHostFree(c.hscal);
+  if (c.hflags) (void)hipHostFree(c.hflags);
+  c.hscal = nullptr; c.hflags = nullptr;
+  if (c.ev0) (void)hipEventDestroy(c.ev0);
+  if (c.ev1) (void)hipEventDestroy(c.ev1);
+  c.ev0 = c.ev1 = nullptr;
+  delete c.ops;
+  c.ops = nullptr;
+}
+
+void set_density(Ctx& c, const double* x) {
+  const Dims& d = c.fine();
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  vcopy_positive(c.stream, x, c.x64, d.m, c.red);
+  if (c.fp32) vconvert<float, double>(c.stream, c.x64, (float*)c.xT, d.m, nullptr);
+  read_scalars(c);
+  if (c.hflags[F_BAD]) {
+    c.have_x = false;
+    throw Error(IPMG_E_DOMAIN, "densities must be finite and positive");
+  }
+  c.have_x = true;
+  c.hier_op = -1;
+}
+
+// Damping of level k from the spectral-radius estimate of D^-1 A (power iteration
+// with the normalisation folded into the next step, then the Rayleigh quotient);
+// everything stays on the device.
+static void jacobi_damping(Ctx& c, int k, int op) {
+  Level& l = c.lev[k];
+  const int aug = op == IPMG_OP_Z;
+  c.ops->power_start(c, k, aug, l.z);
+  void* v = l.z;
+  void* w = l.z2;
+  int sin = -1, sout = S_TMP4;
+  for (int it = 0; it < POWER_STEPS; ++it) {
+    c.ops->level(c, k, op, M_POWER, v, nullptr, w, nullptr, sout, sin, nullptr);
+    std::swap(v, w);
+    sin = sout;
+    sout = sout == S_TMP4 ? S_TMP5 : S_TMP4;
+  }
+  c.ops->level(c, k, op, M_RAYLEIGH, v, nullptr, nullptr, nullptr, S_TMP6, -1, nullptr);
+  vset_omega(c.stream, c.red, c.omega_dev + k, c.omega_dev + c.L + k, S_TMP6, S_TMP7, c.desc.omega, SAFE_PRODUCT);
+}
+
+static void ensure_dense(Ctx& c) {
+  if (c.dA) return;
+  const int64_t n = c.lev[0].d.nslots + 1;
+  IPMG_REQUIRE(n <= 6000, IPMG_E_INVALID, "coarsest level too large for the dense solve; use more levels");
+  dalloc(c.dA, sizeof(double) * n * n);
+  dalloc(c.dLi, sizeof(double) * n * n);
+  dalloc(c.dAi, sizeof(double) * n * n);
+}
+
+void mg_setup(Ctx& c, int op, double* ms) {
+  IPMG_REQUIRE(c.have_x, IPMG_E_STATE, "set the densities first");
+  IPMG_REQUIRE(op == IPMG_OP_K || c.have_z, IPMG_E_STATE, "prepare the Newton system first");
+  auto t0 = std::chrono::steady_clock::now();
+  const int L = c.L;
+  if (op == IPMG_OP_Z && c.fp32)
+    vconvert<float, double>(c.stream, c.bZ64, (float*)c.lev[L - 1].bZ, c.fine().nslots, nullptr);
+  for (int k = L - 1; k >= 1; --k) {
+    c.ops->galerkin(c, k, op);
+    if (op == IPMG_OP_Z) {
+      if (k == L - 1) c.ops->restrict64_to_T(c, k, c.bZ64, c.lev[k - 1].bZ);
+      else c.ops->restrict_to(c, k, c.lev[k].bZ, c.lev[k - 1].bZ, 0, nullptr);
+    }
+  }
+  IPMG_HIP(hipGetLastError());
+  ensure_dense(c);
+  for (int k = 1; k < L; ++k) jacobi_damping(c, k, op);
+  const int n = c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  c.ops->dense_assemble(c, op, c.dA, n);
+  dense_cholesky(c.stream, c.dA, n, c.red);
+  dense_inverse(c.stream, c.dA, c.dLi, c.dAi, n);
+  IPMG_HIP(hipGetLastError());
+  read_scalars(c);
+  IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_BREAKDOWN, "coarsest operator is not positive definite");
+  c.hier_op = op;
+  auto t1 = std::chrono::steady_clock::now();
+  if (ms) *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+// V-cycle on level k: lev[k].r -> returned buffer (Algorithm MG, zero start).
+static void* vcycle_level(Ctx& c, int op, int k, const int* gate) {
+  Level& l = c.lev[k];
+  const int aug = op == IPMG_OP_Z;
+  if (k == 0) {
+    const int n = l.d.nslots + aug;
+    if (c.fp32) dense_solve<float>(c.stream, c.dAi, n, (const float*)l.r, (float*)l.z, gate);
+    else dense_solve<double>(c.stream, c.dAi, n, (const double*)l.r, (double*)l.z, gate);
+    return l.z;
+  }
+  void* cur = l.z;
+  void* nxt = l.z2;
+  const double* w = c.omega_dev + k;
+  c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);       // pre-smoothing
+  for (int s = 1; s < c.desc.nu_pre; ++s) {
+    c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
+    std::swap(cur, nxt);
+  }
+  c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);       // restricted residual
+  c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
+  void* vc = vcycle_level(c, op, k - 1, gate);                                // coarse correction
+  c.ops->prolong_from(c, k, cur, vc, aug, gate);                              // solution update
+  for (int s = 0; s < c.desc.nu_post; ++s) {                                  // post-smoothing
+    c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
+    std::swap(cur, nxt);
+  }
+  return cur;
+}
+
+void* vcycle(Ctx& c, int op, const int* gate) { return vcycle_level(c, op, c.L - 1, gate); }
+
+void vcycle64(Ctx& c, int op, const double* r, double* z) {
+  IPMG_REQUIRE(c.hier_op == op, IPMG_E_STATE, "multigrid hierarchy not set up for this operator");
+  const Dims& d = c.fine();
+  const int64_t n = d.nslots + (op == IPMG_OP_Z ? 1 : 0);
+  vmask_copy(c.stream, r, c.pt, n, d.nslots, c.dim, d.nx1, c.red, S_TMP0);
+  if (c.fp32) vconvert<float, double>(c.stream, c.pt, (float*)c.lev[c.L - 1].r, n, nullptr);
+  else vconvert<double, double>(c.stream, c.pt, (double*)c.lev[c.L - 1].r, n, nullptr);
+  void* y = vcycle(c, op, nullptr);
+  if (c.fp32) vconvert<double, float>(c.stream, (const float*)y, z, n, nullptr);
+  else vconvert<double, double>(c.stream, (const double*)y, z, n, nullptr);
+  IPMG_HIP(hipGetLastError());
+  sync(c);
+}
+
+// Enqueue one PCG iteration (all kernels gated on flags[F_DONE]).
+static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate) {
+  c.ops->fine_apply64(c, op, c.pp, c.pq, gate);                        // q = A p
+  vdot_alpha(c.stream, c.pp, c.pq, n, c.red, gate);                    // alpha = r'y / p'q
+  void* rT = c.lev[c.L - 1].r;
+  if (c.fp32)
+    vpcg_update<float>(c.stream, c.pu, c.pr, c.pp, c.pq, (float*)rT, n, c.red, gate);
+  else
+    vpcg_update<double>(c.stream, c.pu, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
+  void* y = vcycle(c, op, gate);                                        // y = M r
+  if (c.fp32) {
+    vdot_beta<float>(c.stream, c.pr, (const float*)y, n, c.red, gate);  // beta
+    vpcg_dir<float>(c.stream, c.pp, (const float*)y, n, c.red, 0, gate);
+  } else {
+    vdot_beta<double>(c.stream, c.pr, (const double*)y, n, c.red, gate);
+    vpcg_dir<double>(c.stream, c.pp, (const double*)y, n, c.red, 0, gate);
+  }
+}
+
+// r (in c.pr) -> y = M r, rho = r'y, p = -y.
+static void pcg_restart_direction(Ctx& c, int op, int64_t n) {
+  const int* gate = c.red.flags + F_DONE;
+  void* rT = c.lev[c.L - 1].r;
+  if (c.fp32) vconvert<float, double>(c.stream, c.pr, (float*)rT, n, nullptr);
+  else vconvert<double, double>(c.stream, c.pr, (double*)rT, n, nullptr);
+  void* y = vcycle(c, op, gate);
+  if (c.fp32) {
+    vdot_store<float>(c.stream, c.pr, (const float*)y, n, c.red, S_TMP0, gate);
+    vset_rho(c.stream, c.red, S_TMP0);
+    vpcg_dir<float>(c.stream, c.pp, (const float*)y, n, c.red, 1, gate);
+  } else {
+    vdot_store<double>(c.stream, c.pr, (const double*)y, n, c.red, S_TMP0, gate);
+    vset_rho(c.stream, c.red, S_TMP0);
+    vpcg_dir<double>(c.stream, c.pp, (const double*)y, n, c.red, 1, gate);
+  }
+}
+
+int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info) {
+  IPMG_REQUIRE(rtol > 0.0 && maxit >= 0, IPMG_E_INVALID, "rtol > 0 and maxit >= 0 required");
+  IPMG_REQUIRE(c.have_x, IPMG_E_STATE, "set the densities first");
+  double setup_ms = 0.0;
+  if (c.hier_op != op) mg_setup(c, op, &setup_ms);
+  auto t0 = std::chrono::steady_clock::now();
+  const Dims& d = c.fine();
+  const int64_t n = d.nslots + (op == IPMG_OP_Z ? 1 : 0);
+  const int* gate = c.red.flags + F_DONE;
+  IPMG_HIP(hipMemsetAsync(c.red.flags, 0, sizeof(int) * F_COUNT, c.stream));
+  vmask_copy(c.stream, b, c.pb, n, d.nslots, c.dim, d.nx1, c.red, S_BN2);
+  vmask_copy(c.stream, u, c.pu, n, d.nslots, c.dim, d.nx1, c.red, S_TMP1);
+  read_scalars(c);
+  IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_DOMAIN, "right-hand side or initial guess is not finite");
+  const double bn2 = c.hscal[S_BN2];
+  ipmg_pcg_info inf{};
+  inf.setup_ms = setup_ms;
+  if (bn2 == 0.0) {
+    IPMG_HIP(hipMemsetAsync(u, 0, sizeof(double) * n, c.stream));
+    sync(c);
+    if (info) *info = inf;
+    return IPMG_OK;
+  }
+  // r = A u - b
+  c.ops->fine_apply64(c, op, c.pu, c.pq, nullptr);
+  vsub_norm(c.stream, c.pq, c.pb, c.pr, n, c.red, S_RN2);
+  vset_tol(c.stream, c.red, rtol);
+  read_scalars(c);
+  int status = IPMG_OK;
+  int restarts = 0;
+  double rn2 = c.hscal[S_RN2];
+  bool converged = rn2 <= c.hscal[S_TOL2];
+  if (!converged) pcg_restart_direction(c, op, n);
+  int enq = 0;   // iterations enqueued in this pass
+  while (!converged) {
+    // pipeline: keep one iteration in flight while reading the previous flags
+    int iters_before = 0;
+    read_scalars(c);
+    iters_before = c.hflags[F_ITERS];
+    if (c.hflags[F_DONE] == 2) { status = IPMG_E_BREAKDOWN; break; }
+    int done = 0;
+    int slot = 0;
+    enq = 0;
+    while (iters_before + enq < maxit) {
+      pcg_iteration(c, op, n, gate);
+      IPMG_HIP(hipMemcpyAsync(c.hflags + F_COUNT * (1 + slot), c.red.flags, sizeof(int) * F_COUNT,
+                              hipMemcpyDeviceToHost, c.stream));
+      IPMG_HIP(hipEventRecord(slot ? c.ev1 : c.ev0, c.stream));
+      ++enq;
+      if (enq >= 2) {
+        IPMG_HIP(hipEventSynchronize(slot ? c.ev0 : c.ev1));
+        if (c.hflags[F_COUNT * (1 + (slot ^ 1)) + F_DONE]) { done = 1; break; }
+      }
+      slot ^= 1;
+    }
+    IPMG_HIP(hipGetLastError());
+    read_scalars(c);
+    (void)done;
+    if (c.hflags[F_DONE] == 2) { status = IPMG_E_BREAKDOWN; break; }
+    if (c.hflags[F_DONE] != 1) { status = IPMG_E_NOT_CONVERGED; break; }
+    // confirm with the true residual; restart from it if the recurrence drifted
+    c.ops->fine_apply64(c, op, c.pu, c.pq, nullptr);
+    vsub_norm(c.stream, c.pq, c.pb, c.pr, n, c.red, S_RN2);
+    read_scalars(c);
+    if (c.hscal[S_RN2] <= c.hscal[S_TOL2]) { converged = true; break; }
+    if (c.hflags[F_ITERS] >= maxit) { status = IPMG_E_NOT_CONVERGED; break; }
+    ++restarts;
+    vset_tol(c.stream, c.red, rtol);
+    pcg_restart_direction(c, op, n);
+  }
+  read_scalars(c);
+  const double relres_rec = std::sqrt(c.hscal[S_RN2] / bn2);
+  // true residual at exit
+  c.ops->fine_apply64(c, op, c.pu, c.pq, nullptr);
+  vsub_norm(c.stream, c.pq, c.pb, c.pt, n, c.red, S_TMP2);
+  IPMG_HIP(hipMemcpyAsync(u, c.pu, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
+  read_scalars(c);
+  auto t1 = std::chrono::steady_clock::now();
+  inf.iters = c.hflags[F_ITERS];
+  inf.restarts = restarts;
+  inf.status = status;
+  inf.relres = relres_rec;
+  inf.true_relres = std::sqrt(c.hscal[S_TMP2] / bn2);
+  inf.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+// ------------------------------------------------------------ interior point --
+int ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_pcg_info* info) {
+  const Dims& d = c.fine();
+  IPMG_REQUIRE(p.xbar > 0.0 && p.V > 0.0 && p.V < p.xbar * (double)d.m, IPMG_E_DOMAIN,
+               "need 0 < V < m * xbar");
+  vfill(c.stream, st.x, p.V / (double)d.m, d.m);
+  vfill(c.stream, st.phi, 1.0, d.m);
+  vfill(c.stream, st.psi, 1.0, d.m);
+  IPMG_HIP(hipMemsetAsync(st.u, 0, sizeof(double) * d.nslots, c.stream));
+  st.lam = 1.0;
+  st.s = 1.0;
+  st.r = 1.0;
+  set_density(c, st.x);
+  return pcg(c, IPMG_OP_K, f, st.u, p.pcg_rtol, p.pcg_maxit, info);
+}
+
+void ip_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, const ipmg_ip_state& st) {
+  ensure_z_buffers(c);
+  set_density(c, st.x);
+  c.ipV = p.V;
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  c.ops->ip_elements(c, st.u, st.x, st.phi, st.psi, st.lam, st.s, st.r, p.xbar);
+  c.ops->fine_apply64(c, IPMG_OP_K, st.u, c.ipKu, nullptr);
+  c.ops->ip_nodes(c, c.ipKu, f, st.u, c.ipRhs);
+  IPMG_HIP(hipGetLastError());
+  read_scalars(c);
+  IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_DOMAIN, "interior-point iterate left the interior or is not finite");
+  c.cZ = c.hscal[S_TMP0];
+  c.have_z = true;
+  c.hier_op = -1;
+}
+
+int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_ip_info* info) {
+  const Dims& d = c.fine();
+  ipmg_ip_info inf{};
+  ip_prepare(c, f, p, st);
+  double setup_ms = 0.0;
+  mg_setup(c, IPMG_OP_Z, &setup_ms);
+  IPMG_HIP(hipMemsetAsync(c.ipD, 0, sizeof(double) * (d.nslots + 1), c.stream));
+  ipmg_pcg_info pin{};
+  const int ps = pcg(c, IPMG_OP_Z, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, &pin);
+  if (ps == IPMG_E_BREAKDOWN) return ps;
+  inf.pcg_iters = pin.iters;
+  inf.pcg_status = ps;
+  inf.setup_ms = setup_ms;
+  inf.solve_ms = pin.solve_ms;
+  c.ops->ip_recover(c, c.ipD, st.x, st.phi, st.psi, st.s, st.r, p.xbar, p.frac, p.step_all_blocks);
+  double dlam = 0.0;
+  IPMG_HIP(hipMemcpyAsync(&dlam, c.ipD + d.nslots, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  read_scalars(c);
+  const double alpha = c.hscal[S_ALPHA];
+  inf.alpha = alpha;
+  if (!(alpha >= 1e-14) || !std::isfinite(dlam)) {
+    if (info) *info = inf;
+    return IPMG_E_STALLED;
+  }
+  c.ops->ip_update(c, st.u, c.ipD, st.x, st.phi, st.psi);
+  st.lam += alpha * dlam;
+  // measures at the new iterate (same barrier parameters)
+  ip_prepare(c, f, p, st);
+  const double* S = c.hscal;
+  const double nF1 = std::sqrt(S[S_MIN0]), nf = std::sqrt(S[S_MIN1]);
+  const double nG3 = std::sqrt(S[S_TMP3]), nphi = std::sqrt(S[S_TMP4]), npsi = std::sqrt(S[S_TMP5]);
+  inf.nwt = nF1 / nf + nG3 / (nphi + npsi);
+  inf.compliance = S[S_MIN2];
+  inf.gap = S[S_TMP6] / S[S_MIN2];
+  inf.volume_res = S[S_TMP2] - p.V;
+  if (!std::isfinite(inf.nwt) || !std::isfinite(inf.gap)) {
+    if (info) *info = inf;
+    return IPMG_E_DOMAIN;
+  }
+  const bool newton_ok = inf.nwt <= p.tau_nwt;
+  if (p.stop_rule == 0 && newton_ok && inf.gap <= p.kkt_tol) {
+    inf.converged = 1;
+  } else if (newton_ok) {
+    st.s *= p.sigma;
+    st.r *= p.sigma;
+    inf.barrier_updated = 1;
+    if (p.stop_rule == 1 && std::fmax(st.s, st.r) <= p.tau_ip) inf.converged = 1;
+  }
+  if (info) *info = inf;
+  return IPMG_OK;
+}
+
+}  // namespace ipmg

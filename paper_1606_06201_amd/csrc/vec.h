@@ -1,0 +1,37 @@
+// Launchers of the dimension-independent kernels (vec.hip).
+#pragma once
+#include "common.h"
+
+namespace ipmg {
+
+void vdot(hipStream_t st, const double* a, const double* b, int64_t n, const Red& red, int sidx, const int* gate);
+void vdot_alpha(hipStream_t st, const double* p, const double* q, int64_t n, const Red& red, const int* gate);
+template <typename T>
+void vdot_beta(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, const int* gate);
+template <typename T>
+void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, int sidx, const int* gate);
+template <typename T>
+void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
+                 const Red& red, const int* gate);
+template <typename T>
+void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate);
+void vsub_norm(hipStream_t st, const double* a, const double* b, double* out, int64_t n, const Red& red, int sidx);
+void vmask_copy(hipStream_t st, const double* src, double* dst, int64_t n, int64_t nslots, int dim, int nx1,
+                const Red& red, int sidx);
+template <typename TD, typename TS>
+void vconvert(hipStream_t st, const TS* src, TD* dst, int64_t n, const int* gate);
+void vset_tol(hipStream_t st, const Red& red, double rtol);
+void vset_rho(hipStream_t st, const Red& red, int sidx);
+template <typename T>
+void vnormalize(hipStream_t st, T* x, int64_t n, const Red& red, int sidx);
+void vfill(hipStream_t st, double* dst, double value, int64_t n);
+void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red);
+void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
+                double product);
+void vfill_small(hipStream_t st, double* w, int n, double value);   // n <= 64
+void dense_cholesky(hipStream_t st, double* A, int n, const Red& red);
+void dense_inverse(hipStream_t st, const double* L, double* Li, double* Ai, int n);
+template <typename T>
+void dense_solve(hipStream_t st, const double* Ai, int n, const T* rc, T* zc, const int* gate);
+
+}  // namespace ipmg

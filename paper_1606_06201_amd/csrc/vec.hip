@@ -1,0 +1,338 @@
+// PCG vector kernels (Algorithm PCG, Sec. 5.2) and the dense coarsest-level
+// solve (Cholesky factor and explicit inverse, FP64).
+#include "kernels.h"
+#include "vec.h"
+
+namespace ipmg {
+
+namespace {
+
+constexpr int VBLOCKS = 1024;   // grid of the streaming vector kernels
+
+inline int vgrid(int64_t n) {
+  int64_t b = (n + BS - 1) / BS;
+  return (int)(b < VBLOCKS ? (b < 1 ? 1 : b) : VBLOCKS);
+}
+
+// Post-processing done by the last block of a reduction.
+enum Fin { FIN_STORE = 0, FIN_ALPHA = 1, FIN_RN2 = 2, FIN_BETA = 3 };
+
+__device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
+  if (fin == FIN_STORE) {
+    red.scal[sidx] = tot;
+  } else if (fin == FIN_ALPHA) {                 // alpha = r'y / p'Ap
+    red.scal[S_PQ] = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      red.flags[F_DONE] = 2;
+      red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+    } else {
+      red.scal[S_ALPHA] = red.scal[S_RHO] / tot;
+    }
+  } else if (fin == FIN_RN2) {                   // convergence test on ||r||^2
+    red.scal[S_RN2] = tot;
+    red.flags[F_ITERS] += 1;
+    if (!isfinite(tot)) {
+      red.flags[F_DONE] = 2;
+      red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+    } else if (tot <= red.scal[S_TOL2]) {
+      red.flags[F_DONE] = 1;
+    }
+  } else if (fin == FIN_BETA) {                  // beta = r~'y~ / r'y
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      red.flags[F_DONE] = 2;
+      red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+    } else {
+      red.scal[S_BETA] = tot / red.scal[S_RHO];
+      red.scal[S_RHO] = tot;
+    }
+  }
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(BS) void k_dot(const TA* __restrict__ a, const TB* __restrict__ b, int64_t n,
+                                            Red red, int fin, int sidx, const int* gate) {
+  if (gate && *gate) return;
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    s += (double)a[t] * (double)b[t];
+  double v[1] = {s}, tot[1];
+  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) finish(fin, tot[0], red, sidx);
+}
+
+// z += alpha p; r += alpha q; rT = (T) r; ||r||^2 -> convergence flag.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   T* __restrict__ rT, int64_t n, Red red, const int* gate) {
+  if (gate && *gate) return;
+  const double alpha = red.scal[S_ALPHA];
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+    z[t] += alpha * p[t];
+    const double rn = r[t] + alpha * q[t];
+    r[t] = rn;
+    if (rT) rT[t] = T(rn);
+    s += rn * rn;
+  }
+  double v[1] = {s}, tot[1];
+  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) finish(FIN_RN2, tot[0], red, 0);
+}
+
+// p = -y + beta p  (the reading p := -y~ + beta p of Algorithm PCG).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_dir(double* __restrict__ p, const T* __restrict__ y, int64_t n,
+                                                Red red, int first, const int* gate) {
+  if (gate && *gate) return;
+  const double beta = first ? 0.0 : red.scal[S_BETA];
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    p[t] = -(double)y[t] + beta * p[t];
+}
+
+// out = a - b; scal[sidx] = ||out||^2.
+__global__ __launch_bounds__(BS) void k_sub_norm(const double* __restrict__ a, const double* __restrict__ b,
+                                                 double* __restrict__ out, int64_t n, Red red, int sidx) {
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+    const double o = a[t] - b[t];
+    out[t] = o;
+    s += o * o;
+  }
+  double v[1] = {s}, tot[1];
+  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) red.scal[sidx] = tot[0];
+}
+
+// dst = src with clamped slots (nodes with i == 0) zeroed; entries beyond the
+// slots (lambda) copied.  scal[sidx] = ||dst||^2, flags[F_BAD] set if non-finite.
+__global__ __launch_bounds__(BS) void k_mask_copy(const double* __restrict__ src, double* __restrict__ dst,
+                                                  int64_t n, int64_t nslots, int dim, int nx1, Red red, int sidx) {
+  double s = 0.0;
+  int bad = 0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+    double v = src[t];
+    if (t < nslots && ((t / dim) % nx1) == 0) v = 0.0;
+    if (!isfinite(v)) bad = 1;
+    dst[t] = v;
+    s += v * v;
+  }
+  if (bad) red.flags[F_BAD] = 1;
+  double v[1] = {s}, tot[1];
+  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) red.scal[sidx] = tot[0];
+}
+
+__global__ __launch_bounds__(BS) void k_fill(double* __restrict__ dst, double value, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) dst[t] = value;
+}
+
+// dst = src; flags[F_BAD] = 1 unless every entry is finite and > 0.
+__global__ __launch_bounds__(BS) void k_copy_positive(const double* __restrict__ src, double* __restrict__ dst,
+                                                      int64_t n, Red red) {
+  int bad = 0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+    const double v = src[t];
+    if (!(v > 0.0) || !isfinite(v)) bad = 1;
+    dst[t] = v;
+  }
+  if (bad) red.flags[F_BAD] = 1;
+}
+
+template <typename TD, typename TS>
+__global__ __launch_bounds__(BS) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, int64_t n,
+                                                const int* gate) {
+  if (gate && *gate) return;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    dst[t] = TD(src[t]);
+}
+
+__global__ void k_set_tol(Red red, double rtol2) {
+  if (threadIdx.x == 0) {
+    red.scal[S_TOL2] = rtol2 * red.scal[S_BN2];
+    red.flags[F_DONE] = 0;
+  }
+}
+
+__global__ void k_set_rho(Red red, int sidx) {
+  if (threadIdx.x == 0) {
+    const double rho = red.scal[sidx];
+    red.scal[S_RHO] = rho;
+    if (!(rho > 0.0) || !isfinite(rho)) {
+      red.flags[F_DONE] = 2;
+      red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+    }
+  }
+}
+
+// Damping safeguard: rho = v'Av / v'Dv from scal[s_vav], scal[s_vdv];
+// w[0] = min(omega, product / rho), w[1] = rho (omega kept if rho is not usable).
+__global__ void k_set_omega(Red red, double* __restrict__ w, double* __restrict__ rho_out, int s_vav, int s_vdv,
+                            double omega, double product) {
+  if (threadIdx.x == 0) {
+    const double rho = red.scal[s_vav] / red.scal[s_vdv];
+    double o = omega;
+    if (rho > 0.0 && isfinite(rho)) o = fmin(omega, product / rho);
+    w[0] = o;
+    rho_out[0] = rho;
+  }
+}
+
+__global__ void k_fill_value(double* __restrict__ w, int n, double value) {
+  if ((int)threadIdx.x < n) w[threadIdx.x] = value;
+}
+
+// x = x / sqrt(scal[sidx]) (power-iteration normalisation)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_normalize(T* __restrict__ x, int64_t n, Red red, int sidx) {
+  const double s = red.scal[sidx];
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    x[t] = T((double)x[t] * inv);
+}
+
+// ------------------------------------------------------------- dense coarse ---
+// In-place lower Cholesky factor of the n x n row-major SPD matrix A (one block).
+// flags[F_BAD] = 1 if a pivot is not positive.
+__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n, Red red) {
+  __shared__ double piv;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[(int64_t)j * n + j];
+      if (!(d > 0.0)) { red.flags[F_BAD] = 1; d = 1.0; }
+      d = sqrt(d);
+      A[(int64_t)j * n + j] = d;
+      piv = d;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(int64_t)i * n + j] /= piv;
+    __syncthreads();
+    const int m = n - j - 1;                      // trailing lower triangle, m(m+1)/2 entries
+    const int64_t cnt = (int64_t)m * (m + 1) / 2;
+    for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+      // t -> (ii, kk) with 0 <= kk <= ii < m
+      int ii = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((int64_t)ii * (ii + 1) / 2 > t) --ii;
+      while ((int64_t)(ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      const int kk = (int)(t - (int64_t)ii * (ii + 1) / 2);
+      const int gi = j + 1 + ii, gk = j + 1 + kk;
+      A[(int64_t)gi * n + gk] -= A[(int64_t)gi * n + j] * A[(int64_t)gk * n + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Column j of L^-1 by forward substitution (one thread per column).
+__global__ __launch_bounds__(BS) void k_tri_inverse(const double* __restrict__ L, double* __restrict__ Li, int n) {
+  const int j = blockIdx.x * BS + threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < j; ++i) Li[(int64_t)i * n + j] = 0.0;
+  for (int i = j; i < n; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = j; k < i; ++k) s -= L[(int64_t)i * n + k] * Li[(int64_t)k * n + j];
+    Li[(int64_t)i * n + j] = s / L[(int64_t)i * n + i];
+  }
+}
+
+// A^-1 = L^-T L^-1, one thread per entry.
+__global__ __launch_bounds__(BS) void k_inv_product(const double* __restrict__ Li, double* __restrict__ Ai, int n) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int r = (int)(t / n), c = (int)(t % n);
+  double s = 0.0;
+  for (int k = r > c ? r : c; k < n; ++k) s += Li[(int64_t)k * n + r] * Li[(int64_t)k * n + c];
+  Ai[t] = s;
+}
+
+// zc = A^-1 rc, one wavefront per row.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dense_solve(const double* __restrict__ Ai, int n, const T* __restrict__ rc,
+                                                    T* __restrict__ zc, const int* gate) {
+  if (gate && *gate) return;
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s += Ai[(int64_t)row * n + c] * (double)rc[c];
+  s = wave_sum(s);
+  if (lane == 0) zc[row] = T(s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers --
+void vdot(hipStream_t st, const double* a, const double* b, int64_t n, const Red& red, int sidx, const int* gate) {
+  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(a, b, n, red, FIN_STORE, sidx, gate);
+}
+void vdot_alpha(hipStream_t st, const double* p, const double* q, int64_t n, const Red& red, const int* gate) {
+  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(p, q, n, red, FIN_ALPHA, 0, gate);
+}
+template <typename T>
+void vdot_beta(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, const int* gate) {
+  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, FIN_BETA, 0, gate);
+}
+template <typename T>
+void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, int sidx, const int* gate) {
+  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, FIN_STORE, sidx, gate);
+}
+template <typename T>
+void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
+                 const Red& red, const int* gate) {
+  k_pcg_update<T><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+}
+template <typename T>
+void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate) {
+  k_pcg_dir<T><<<vgrid(n), BS, 0, st>>>(p, y, n, red, first, gate);
+}
+void vsub_norm(hipStream_t st, const double* a, const double* b, double* out, int64_t n, const Red& red, int sidx) {
+  k_sub_norm<<<vgrid(n), BS, 0, st>>>(a, b, out, n, red, sidx);
+}
+void vmask_copy(hipStream_t st, const double* src, double* dst, int64_t n, int64_t nslots, int dim, int nx1,
+                const Red& red, int sidx) {
+  k_mask_copy<<<vgrid(n), BS, 0, st>>>(src, dst, n, nslots, dim, nx1, red, sidx);
+}
+template <typename TD, typename TS>
+void vconvert(hipStream_t st, const TS* src, TD* dst, int64_t n, const int* gate) {
+  k_convert<TD, TS><<<vgrid(n), BS, 0, st>>>(src, dst, n, gate);
+}
+void vset_tol(hipStream_t st, const Red& red, double rtol) { k_set_tol<<<1, 64, 0, st>>>(red, rtol * rtol); }
+void vset_rho(hipStream_t st, const Red& red, int sidx) { k_set_rho<<<1, 64, 0, st>>>(red, sidx); }
+template <typename T>
+void vnormalize(hipStream_t st, T* x, int64_t n, const Red& red, int sidx) {
+  k_normalize<T><<<vgrid(n), BS, 0, st>>>(x, n, red, sidx);
+}
+void vfill(hipStream_t st, double* dst, double value, int64_t n) { k_fill<<<vgrid(n), BS, 0, st>>>(dst, value, n); }
+void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red) {
+  k_copy_positive<<<vgrid(n), BS, 0, st>>>(src, dst, n, red);
+}
+void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
+                double product) {
+  k_set_omega<<<1, 64, 0, st>>>(red, w, rho, s_vav, s_vdv, omega, product);
+}
+void vfill_small(hipStream_t st, double* w, int n, double value) { k_fill_value<<<1, 64, 0, st>>>(w, n, value); }
+void dense_cholesky(hipStream_t st, double* A, int n, const Red& red) { k_cholesky<<<1, 1024, 0, st>>>(A, n, red); }
+void dense_inverse(hipStream_t st, const double* L, double* Li, double* Ai, int n) {
+  k_tri_inverse<<<(n + BS - 1) / BS, BS, 0, st>>>(L, Li, n);
+  const int64_t nn = (int64_t)n * n;
+  k_inv_product<<<(unsigned)((nn + BS - 1) / BS), BS, 0, st>>>(Li, Ai, n);
+}
+template <typename T>
+void dense_solve(hipStream_t st, const double* Ai, int n, const T* rc, T* zc, const int* gate) {
+  k_dense_solve<T><<<(n + BS / 64 - 1) / (BS / 64), BS, 0, st>>>(Ai, n, rc, zc, gate);
+}
+
+template void vdot_beta<float>(hipStream_t, const double*, const float*, int64_t, const Red&, const int*);
+template void vdot_beta<double>(hipStream_t, const double*, const double*, int64_t, const Red&, const int*);
+template void vdot_store<float>(hipStream_t, const double*, const float*, int64_t, const Red&, int, const int*);
+template void vdot_store<double>(hipStream_t, const double*, const double*, int64_t, const Red&, int, const int*);
+template void vpcg_update<float>(hipStream_t, double*, double*, const double*, const double*, float*, int64_t,
+                                 const Red&, const int*);
+template void vpcg_update<double>(hipStream_t, double*, double*, const double*, const double*, double*, int64_t,
+                                  const Red&, const int*);
+template void vpcg_dir<float>(hipStream_t, double*, const float*, int64_t, const Red&, int, const int*);
+template void vpcg_dir<double>(hipStream_t, double*, const double*, int64_t, const Red&, int, const int*);
+template void vconvert<float, double>(hipStream_t, const double*, float*, int64_t, const int*);
+template void vconvert<double, float>(hipStream_t, const float*, double*, int64_t, const int*);
+template void vconvert<double, double>(hipStream_t, const double*, double*, int64_t, const int*);
+template void vnormalize<float>(hipStream_t, float*, int64_t, const Red&, int);
+template void vnormalize<double>(hipStream_t, double*, int64_t, const Red&, int);
+template void dense_solve<float>(hipStream_t, const double*, int, const float*, float*, const int*);
+template void dense_solve<double>(hipStream_t, const double*, int, const double*, double*, const int*);
+
+}  // namespace ipmg

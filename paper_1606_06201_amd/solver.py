@@ -1,0 +1,244 @@
+"""Python front end of libipmg: one Solver per grid, torch tensors for device
+memory and the current HIP stream.  Every numerical step runs in the library's
+kernels; this module only checks arguments and passes pointers."""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+OP_K, OP_Z = L.OP_K, L.OP_Z
+
+
+class IPMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ipmg error {code}: {msg}")
+        self.code = code
+
+
+class Solver:
+    """Multigrid-preconditioned CG on K(x) (and the interior-point augmented
+    system Z) for a structured Q1 grid of nel = (nx, ny[, nz]) unit elements."""
+
+    def __init__(self, nel, levels, fp32=True, E=1.0, nu=0.3, nu_pre=2, nu_post=2, omega=0.6,
+                 device="cuda:0"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the ipmg library runs on a GPU device")
+        nel = tuple(int(v) for v in nel)
+        d = L.Desc()
+        d.dim = len(nel)
+        for a in range(3):
+            d.nel[a] = nel[a] if a < len(nel) else 1
+        d.levels, d.E, d.nu = int(levels), float(E), float(nu)
+        d.vcycle_fp32, d.nu_pre, d.nu_post, d.omega = int(bool(fp32)), int(nu_pre), int(nu_post), float(omega)
+        self.nel, self.dim, self.levels, self.fp32 = nel, len(nel), int(levels), bool(fp32)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            rc = self.lib.ipmg_create(C.byref(d), C.c_void_p(stream), C.byref(h))
+        if rc != L.OK:
+            raise IPMGError(rc, self.lib.ipmg_status_string(rc).decode())
+        self.h = h
+        self.n_slots, self.n_free, self.m = self.sizes(levels - 1)
+
+    # -------------------------------------------------------------- plumbing --
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ipmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != L.OK and rc not in allow:
+            msg = self.lib.ipmg_last_error(self.h).decode()
+            raise IPMGError(rc, msg or self.lib.ipmg_status_string(rc).decode())
+        return rc
+
+    def _ptr(self, t, n, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != n:
+            raise ValueError(f"{name} must have {n} entries, got {t.numel()}")
+        return C.c_void_p(t.data_ptr())
+
+    def _empty(self, n):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    def _zeros(self, n):
+        return torch.zeros(n, dtype=torch.float64, device=self.device)
+
+    def _call(self, fn, *args, allow=()):
+        with torch.cuda.device(self.device):
+            return self._check(fn(self.h, *args), allow)
+
+    def _n(self, op):
+        return self.n_slots + (1 if op == OP_Z else 0)
+
+    # ------------------------------------------------------------- integer maps --
+    def sizes(self, level):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.lib.ipmg_sizes(self.h, int(level), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def dof_map(self, level):
+        n_free = self.sizes(level)[1]
+        out = np.empty(n_free, dtype=np.int64)
+        self._check(self.lib.ipmg_dof_map(self.h, int(level), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def slot_of(self, level, i, j, k=0, c=0):
+        return int(self.lib.ipmg_slot_of(self.h, int(level), int(i), int(j), int(k), int(c)))
+
+    def load_vector(self, loads):
+        """Slot vector from [(node coords, component, value)] point loads."""
+        f = np.zeros(self.n_slots)
+        for coords, comp, val in loads:
+            coords = tuple(coords) + (0,) * (3 - len(coords))
+            s = self.slot_of(self.levels - 1, coords[0], coords[1], coords[2], comp)
+            if s < 0:
+                raise ValueError(f"load outside the grid: {coords}")
+            f[s] += val
+        return torch.from_numpy(f).to(self.device)
+
+    def element_matrix(self):
+        nd = self.dim * 2 ** self.dim
+        out = np.empty((nd, nd))
+        self._check(self.lib.ipmg_element_matrix(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    # ---------------------------------------------------------------- operators --
+    def set_density(self, x):
+        self._call(self.lib.ipmg_set_density, self._ptr(x, self.m, "x"))
+
+    def apply_K(self, v, out=None):
+        out = self._empty(self.n_slots) if out is None else out
+        self._call(self.lib.ipmg_apply_K, self._ptr(v, self.n_slots, "v"), self._ptr(out, self.n_slots, "y"))
+        return out
+
+    def apply_Z(self, v, out=None):
+        n = self.n_slots + 1
+        out = self._empty(n) if out is None else out
+        self._call(self.lib.ipmg_apply_Z, self._ptr(v, n, "v"), self._ptr(out, n, "y"))
+        return out
+
+    def mg_setup(self, op=OP_K):
+        self._call(self.lib.ipmg_mg_setup, int(op))
+
+    def level_damping(self, level):
+        """(omega_k, rho_k) of the Jacobi smoother on a level after mg_setup."""
+        w, r = C.c_double(), C.c_double()
+        self._call(self.lib.ipmg_level_damping, int(level), C.byref(w), C.byref(r))
+        return w.value, r.value
+
+    def vcycle(self, r, op=OP_K, out=None):
+        n = self._n(op)
+        out = self._empty(n) if out is None else out
+        self._call(self.lib.ipmg_vcycle, int(op), self._ptr(r, n, "r"), self._ptr(out, n, "z"))
+        return out
+
+    def pcg(self, b, op=OP_K, u0=None, rtol=1e-8, maxit=1000, check=True):
+        """Solve A u = b by MG-PCG; returns (u, info dict)."""
+        n = self._n(op)
+        u = self._zeros(n) if u0 is None else u0.clone()
+        info = L.PCGInfo()
+        allow = () if check else (L.E_NOT_CONVERGED, L.E_BREAKDOWN)
+        rc = self._call(self.lib.ipmg_pcg, int(op), self._ptr(b, n, "b"), self._ptr(u, n, "u"),
+                        float(rtol), int(maxit), C.byref(info), allow=allow)
+        return u, dict(iters=info.iters, restarts=info.restarts, status=info.status, relres=info.relres,
+                       true_relres=info.true_relres, setup_ms=info.setup_ms, solve_ms=info.solve_ms, rc=rc)
+
+    def element_sens(self, w, u, scale=1.0, out=None):
+        out = self._empty(self.m) if out is None else out
+        self._call(self.lib.ipmg_element_sens, self._ptr(w, self.n_slots, "w"), self._ptr(u, self.n_slots, "u"),
+                   float(scale), self._ptr(out, self.m, "g"))
+        return out
+
+    # ------------------------------------------------------------ interior point --
+    @staticmethod
+    def ip_params(V, xbar=1.0, sigma=0.2, tau_nwt=0.1, pcg_rtol=1e-8, pcg_maxit=1000, frac=0.9,
+                  step_all_blocks=True, stop="kkt", kkt_tol=1e-6, tau_ip=1e-8, max_newton=300):
+        p = L.IPParams()
+        p.V, p.xbar, p.sigma, p.tau_nwt = float(V), float(xbar), float(sigma), float(tau_nwt)
+        p.pcg_rtol, p.pcg_maxit, p.frac = float(pcg_rtol), int(pcg_maxit), float(frac)
+        p.step_all_blocks = int(bool(step_all_blocks))
+        p.stop_rule = {"kkt": 0, "barrier": 1}[stop]
+        p.kkt_tol, p.tau_ip, p.max_newton = float(kkt_tol), float(tau_ip), int(max_newton)
+        return p
+
+    def new_ip_state(self):
+        return dict(u=self._zeros(self.n_slots), x=self._zeros(self.m), phi=self._zeros(self.m),
+                    psi=self._zeros(self.m), lam=0.0, s=0.0, r=0.0)
+
+    def _state_struct(self, st):
+        s = L.IPState()
+        s.u = self._ptr(st["u"], self.n_slots, "u").value
+        s.x = self._ptr(st["x"], self.m, "x").value
+        s.phi = self._ptr(st["phi"], self.m, "phi").value
+        s.psi = self._ptr(st["psi"], self.m, "psi").value
+        s.lam, s.s, s.r = float(st["lam"]), float(st["s"]), float(st["r"])
+        return s
+
+    @staticmethod
+    def _state_back(s, st):
+        st["lam"], st["s"], st["r"] = s.lam, s.s, s.r
+
+    def ip_init(self, f, params, state=None):
+        st = self.new_ip_state() if state is None else state
+        s = self._state_struct(st)
+        info = L.PCGInfo()
+        self._call(self.lib.ipmg_ip_init, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
+                   C.byref(info))
+        self._state_back(s, st)
+        return st, dict(iters=info.iters, true_relres=info.true_relres)
+
+    def ip_prepare(self, f, params, st):
+        rhs = self._empty(self.n_slots + 1)
+        s = self._state_struct(st)
+        self._call(self.lib.ipmg_ip_prepare, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
+                   self._ptr(rhs, self.n_slots + 1, "rhs"))
+        return rhs
+
+    def ip_step(self, f, params, st):
+        s = self._state_struct(st)
+        info = L.IPInfo()
+        rc = self._call(self.lib.ipmg_ip_step, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
+                        C.byref(info), allow=(L.E_STALLED,))
+        self._state_back(s, st)
+        return dict(alpha=info.alpha, nwt=info.nwt, gap=info.gap, volume_res=info.volume_res,
+                    compliance=info.compliance, pcg_iters=info.pcg_iters, pcg_status=info.pcg_status,
+                    barrier_updated=info.barrier_updated, converged=info.converged, setup_ms=info.setup_ms,
+                    solve_ms=info.solve_ms, rc=rc)
+
+    def ip_run(self, f, params, callback=None):
+        """Interior-point loop (Sec. 3.1): init, then Newton steps until the stop rule."""
+        st, init = self.ip_init(f, params)
+        log = dict(newton=0, barrier_updates=0, pcg_iters=[init["iters"]], steps=[], status="max_newton")
+        while log["newton"] < params.max_newton:
+            inf = self.ip_step(f, params, st)
+            log["newton"] += 1
+            log["pcg_iters"].append(inf["pcg_iters"])
+            log["steps"].append(inf)
+            log["barrier_updates"] += inf["barrier_updated"]
+            if callback:
+                callback(st, inf)
+            if inf["rc"] == L.E_STALLED:
+                log["status"] = "stalled"
+                break
+            if inf["converged"]:
+                log["status"] = "converged"
+                break
+        return st, log

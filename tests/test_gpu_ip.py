@@ -1,0 +1,126 @@
+"""GPU parity of the interior-point path (augmented system Z, Newton step, full
+run) and of the differentiable solve, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import fem, ip as oip, mg, sens
+from tests.gpu_util import T, N, relerr, grid_and_k0, tip_load
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(nel, vfrac=0.5, xbar=1.0):
+    g, K0 = grid_and_k0(nel)
+    f = fem.load_vector(g, tip_load(nel))
+    return oip.Problem(g, K0, f, vfrac * g.m, xbar)
+
+
+def _state(prob, seed=1):
+    rng = np.random.default_rng(seed)
+    m, g = prob.grid.m, prob.grid
+    u = rng.standard_normal(g.nslots) * 10
+    u[g.clamped_mask()] = 0
+    return oip.IPState(fem.to_free(g, u), 0.7, rng.uniform(0.2, 0.8, m), rng.uniform(0.5, 2, m),
+                       rng.uniform(0.5, 2, m), 0.3, 0.2), u
+
+
+def _gpu_state(s, st, u_slots):
+    return dict(u=T(u_slots), x=T(st.x), phi=T(st.phi), psi=T(st.psi), lam=st.lam, s=st.s, r=st.r)
+
+
+@pytest.mark.parametrize("nel,levels,fp32", [((32, 16), 3, False), ((8, 4, 4), 2, False), ((32, 16), 3, True)])
+def test_newton_system_and_z_operator(nel, levels, fp32):
+    from paper_1606_06201_amd import Solver
+    prob = _problem(nel)
+    g = prob.grid
+    st, u_slots = _state(prob)
+    Z, rhs, parts = prob.z_system(st)
+    s = Solver(nel, levels, fp32=fp32)
+    params = s.ip_params(prob.V, prob.xbar)
+    gst = _gpu_state(s, st, u_slots)
+    grhs = N(s.ip_prepare(T(prob.f_slots), params, gst))
+    free = g.free_to_slot()
+    assert relerr(np.concatenate([grhs[free], grhs[-1:]]), rhs) < 1e-12
+    v = np.random.default_rng(3).standard_normal(g.nslots + 1)
+    v[:-1][g.clamped_mask()] = 0
+    zv = N(s.apply_Z(T(v)))
+    ref = Z @ np.concatenate([v[:-1][free], v[-1:]])
+    assert relerr(np.concatenate([zv[free], zv[-1:]]), ref) < 1e-12
+    # V-cycle on Z with the damping safeguard
+    s.mg_setup(1)
+    H = mg.Hierarchy(g, Z, levels, augmented=True, safeguard=True)
+    zc = N(s.vcycle(T(v), op=1))
+    zref = mg.vcycle(H, np.concatenate([v[:-1][free], v[-1:]]))
+    tol = 2e-4 if fp32 else 1e-9
+    assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < tol
+
+
+def test_newton_step_matches_oracle():
+    from paper_1606_06201_amd import Solver
+    nel, levels = (32, 16), 3
+    prob = _problem(nel)
+    g = prob.grid
+    params_o = oip.IPParams(solver="mg", levels=levels, pcg_rtol=1e-10)
+    st0, _ = oip.initial_state(prob, params_o)
+    st1, alpha, _ = oip.newton_step(prob, st0, params_o)
+    s = Solver(nel, levels, fp32=False)
+    params = s.ip_params(prob.V, prob.xbar, pcg_rtol=1e-10)
+    gst, init = s.ip_init(T(prob.f_slots), params)
+    assert relerr(fem.to_free(g, N(gst["u"])), st0.u) < 1e-8
+    inf = s.ip_step(T(prob.f_slots), params, gst)
+    assert abs(inf["alpha"] - alpha) < 1e-8
+    assert relerr(N(gst["x"]), st1.x) < 1e-8
+    assert relerr(fem.to_free(g, N(gst["u"])), st1.u) < 1e-7
+    assert abs(gst["lam"] - st1.lam) < 1e-7 * abs(st1.lam)
+    assert relerr(N(gst["phi"]), st1.phi) < 1e-7 and relerr(N(gst["psi"]), st1.psi) < 1e-7
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ip_run_64x32_matches_oracle(fp32):
+    # The 64x32 cantilever of the paper's Example 2 ("425"): V = 0.5 m, xbar = 1.
+    from paper_1606_06201_amd import Solver
+    nel, levels = (64, 32), 4
+    prob = _problem(nel)
+    params_o = oip.IPParams(stop="kkt", kkt_tol=1e-6, solver="mg", levels=levels)
+    st_o, log_o = oip.run(prob, params_o)
+    s = Solver(nel, levels, fp32=fp32)
+    params = s.ip_params(prob.V, prob.xbar, stop="kkt", kkt_tol=1e-6)
+    gst, log = s.ip_run(T(prob.f_slots), params)
+    assert log["status"] == "converged"
+    assert abs(log["newton"] - log_o.newton) <= 1
+    assert abs(log["barrier_updates"] - log_o.barrier_updates) <= 1
+    c = float(prob.f_slots @ N(gst["u"]))
+    c_o = float(prob.f @ st_o.u)
+    assert abs(c - c_o) <= 1e-6 * c_o
+    x = N(gst["x"])
+    # sum x = V holds to the accumulated PCG tolerance (the oracle reaches 1.4e-7 V too)
+    assert abs(x.sum() - prob.V) <= 1e-6 * prob.V
+    assert x.min() > 0 and x.max() < prob.xbar
+    # oracle certificate of the final iterate's KKT quantities
+    og = oip.IPState(fem.to_free(prob.grid, N(gst["u"])), gst["lam"], x, N(gst["phi"]), N(gst["psi"]),
+                     gst["s"] / 0.2 if log["steps"][-1]["barrier_updated"] else gst["s"],
+                     gst["r"] / 0.2 if log["steps"][-1]["barrier_updated"] else gst["r"])
+    nwt, gap, _ = prob.measures(og)
+    assert nwt <= 0.1 and gap <= 1e-6
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_adjoint_gradient_matches_oracle(fp32):
+    import torch
+    from paper_1606_06201_amd import Solver, solve_K, inputs
+    nel, levels = (64, 32), 4
+    g, K0 = grid_and_k0(nel)
+    x = inputs.density_uniform(nel, seed=3)
+    f = fem.load_vector(g, tip_load(nel))
+    gv = inputs.normal_slots(g.nslots, seed=33)
+    gv[g.clamped_mask()] = 0
+    s = Solver(nel, levels, fp32=fp32)
+    xt = T(x).requires_grad_(True)
+    u = solve_K(xt, T(f), s, rtol=1e-12)
+    J = torch.dot(T(gv), u) + torch.dot(T(f), u)
+    J.backward()
+    J_o, grad_o, _, _ = sens.linear_objective_gradient(g, x, K0, f, gv)
+    assert abs(float(J) - J_o) <= 1e-9 * abs(J_o)
+    assert relerr(N(xt.grad), grad_o) < 1e-8
+    # Euler identity on the GPU gradient: sum x_e dJ/dx_e = -J
+    assert abs(float(np.dot(x, N(xt.grad))) + J_o) <= 1e-8 * abs(J_o)

@@ -1,0 +1,175 @@
+"""GPU parity tests: the HIP library (through its C ABI) against the FP64 oracle
+on seeded inputs.  Sizes span several 64-wide tiles plus ragged tails."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fem, mg, pcg as opcg, sens
+from tests.gpu_util import T, N, relerr, grid_and_k0, tip_load
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(nel, levels, fp32=False, **kw):
+    from paper_1606_06201_amd import Solver
+    return Solver(nel, levels, fp32=fp32, **kw)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_element_matrix_matches_oracle(dim):
+    nel = (4, 2) if dim == 2 else (2, 2, 2)
+    s = _solver(nel, 1)
+    K0 = s.element_matrix()
+    np.testing.assert_allclose(K0, fem.element_stiffness(dim), rtol=0, atol=2e-16 * 8)
+
+
+@pytest.mark.parametrize("nel,levels", [((16, 8), 4), ((8, 4, 4), 3), ((130, 66), 2)])
+def test_dof_maps_bit_exact(nel, levels):
+    s = _solver(nel, levels)
+    g = fem.Grid(nel)
+    for lev in range(levels - 1, -1, -1):
+        n_slots, n_free, m = s.sizes(lev)
+        assert (n_slots, n_free, m) == (g.nslots, len(g.free_to_slot()), g.m)
+        assert np.array_equal(s.dof_map(lev), g.free_to_slot())
+        assert s.slot_of(lev, g.nel[0], 1, 0 if g.dim == 2 else 1, 1) == \
+            g.dim * int(g.node_index(g.nel[0], 1, 0 if g.dim == 2 else 1)) + 1
+        if lev > 0:
+            g = g.coarsen()
+
+
+@pytest.mark.parametrize("nel", [(5, 3), (130, 67), (7, 3, 2), (9, 5, 4)])
+def test_apply_K_matches_oracle(nel):
+    g, K0 = grid_and_k0(nel)
+    rng = np.random.default_rng(21)
+    x = rng.uniform(1e-3, 1.0, g.m)
+    v = rng.standard_normal(g.nslots)            # clamped entries are ignored by contract
+    s = _solver(nel, 1)
+    s.set_density(T(x))
+    y = N(s.apply_K(T(v)))
+    ref = fem.apply_free_masked(g, x, K0, v)
+    assert relerr(y, ref) < 1e-13
+    assert np.all(y[g.clamped_mask()] == 0.0)
+
+
+def _kproblem(nel, seed=5, lo=1e-2):
+    g, K0 = grid_and_k0(nel)
+    x = np.random.default_rng(seed).uniform(lo, 1.0, g.m)
+    return g, K0, x
+
+
+@pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 3, False, 1e-11), ((8, 4, 4), 2, False, 1e-11),
+                                                  ((32, 16), 4, True, 2e-4), ((8, 8, 4), 3, True, 2e-4)])
+def test_vcycle_matches_oracle(nel, levels, fp32, tol):
+    g, K0, x = _kproblem(nel)
+    H = mg.kstiffness_hierarchy(g, x, K0, levels)
+    r = np.random.default_rng(6).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    s = _solver(nel, levels, fp32=fp32)
+    s.set_density(T(x))
+    s.mg_setup()
+    for k in range(1, levels):
+        w, rho = s.level_damping(k)
+        assert abs(rho - H.rho[k]) <= (1e-10 if not fp32 else 1e-5) * H.rho[k]
+        assert abs(w - H.omega[k]) <= 1e-5 * H.omega[k]
+    z = N(s.vcycle(T(r)))
+    zref = mg.vcycle(H, fem.to_free(g, r))
+    assert relerr(fem.to_free(g, z), zref) < tol
+    assert np.all(z[g.clamped_mask()] == 0)
+    # determinism: bitwise identical on a second call
+    z2 = N(s.vcycle(T(r)))
+    assert np.array_equal(z, z2)
+
+
+@pytest.mark.parametrize("nel,levels,fp32", [((64, 32), 4, False), ((64, 32), 4, True),
+                                             ((16, 8, 8), 3, False), ((16, 8, 8), 3, True)])
+def test_pcg_matches_direct_solve(nel, levels, fp32):
+    g, K0, x = _kproblem(nel, lo=1e-3)
+    f = fem.load_vector(g, tip_load(nel))
+    s = _solver(nel, levels, fp32=fp32)
+    s.set_density(T(x))
+    u, info = s.pcg(T(f), rtol=1e-8)
+    u = N(u)
+    assert info["true_relres"] <= 1e-8 and info["status"] == 0
+    K = fem.stiffness_free(g, x, K0)
+    ustar = spla.spsolve(K.tocsc(), fem.to_free(g, f))
+    uf = fem.to_free(g, u)
+    # oracle-side true residual of the GPU solution
+    rres = np.linalg.norm(fem.to_free(g, f) - K @ uf) / np.linalg.norm(fem.to_free(g, f))
+    assert rres <= 1.01e-8
+    c_gpu, c_ref = float(f @ u), float(fem.to_free(g, f) @ ustar)
+    assert abs(c_gpu - c_ref) <= 1e-6 * abs(c_ref)
+    # same iteration count as the oracle's FP64 MG-PCG (mixed precision within a few)
+    H = mg.kstiffness_hierarchy(g, x, K0, levels)
+    ref = opcg.mg_pcg(H, fem.to_free(g, f), rtol=1e-8)
+    assert abs(info["iters"] - ref.iters) <= (0 if not fp32 else 2), (info["iters"], ref.iters)
+
+
+def test_pcg_contrast_1e6_threshold_density():
+    from paper_1606_06201_amd import inputs
+    nel, levels = (128, 64), 5
+    g, K0 = grid_and_k0(nel)
+    x = inputs.density_threshold(nel, seed=2)
+    f = fem.load_vector(g, tip_load(nel))
+    K = fem.stiffness_free(g, x, K0)
+    ustar = spla.spsolve(K.tocsc(), fem.to_free(g, f))
+    c_ref = float(fem.to_free(g, f) @ ustar)
+    for fp32 in (False, True):
+        s = _solver(nel, levels, fp32=fp32)
+        s.set_density(T(x))
+        u, info = s.pcg(T(f), rtol=1e-8)
+        assert info["true_relres"] <= 1e-8
+        assert abs(float(f @ N(u)) - c_ref) <= 1e-6 * c_ref
+
+
+def test_pcg_edge_cases():
+    nel = (16, 8)
+    g, K0, x = _kproblem(nel)
+    s = _solver(nel, 3)
+    s.set_density(T(x))
+    # zero right-hand side -> zero solution, no iterations
+    u, info = s.pcg(T(np.zeros(g.nslots)))
+    assert info["iters"] == 0 and np.all(N(u) == 0)
+    # initial guess equal to the solution -> no iterations
+    f = fem.load_vector(g, tip_load(nel))
+    u, _ = s.pcg(T(f), rtol=1e-10)
+    u2, info2 = s.pcg(T(f), u0=u, rtol=1e-8)
+    assert info2["iters"] == 0
+    # maxit reached -> status reported, iterate returned
+    u3, info3 = s.pcg(T(f), rtol=1e-14, maxit=2, check=False)
+    assert info3["iters"] == 2 and info3["rc"] != 0
+    # one level: the V-cycle is the exact coarse solve -> one iteration
+    s1 = _solver((8, 4), 1)
+    x1 = np.random.default_rng(1).uniform(0.1, 1, 32)
+    s1.set_density(T(x1))
+    u4, info4 = s1.pcg(T(fem.load_vector(fem.Grid((8, 4)), tip_load((8, 4)))), rtol=1e-10)
+    assert info4["iters"] == 1
+
+
+def test_invalid_arguments_raise():
+    import torch
+    from paper_1606_06201_amd import IPMGError, Solver
+    with pytest.raises(IPMGError):
+        Solver((10, 6), 3)                          # 6 not divisible by 4
+    s = _solver((8, 4), 2)
+    with pytest.raises(IPMGError):
+        s.set_density(T(-np.ones(32)))              # x <= 0
+    with pytest.raises(TypeError):
+        s.set_density(torch.ones(32, dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(ValueError):
+        s.set_density(T(np.ones(31)))
+    with pytest.raises(IPMGError):
+        s.pcg(T(np.ones(s.n_slots)))                # before any density -> state error
+
+
+def test_element_sensitivities_match_oracle():
+    nel = (33 * 2, 17 * 2)
+    g, K0, x = _kproblem(nel)
+    rng = np.random.default_rng(9)
+    w, u = rng.standard_normal(g.nslots), rng.standard_normal(g.nslots)
+    s = _solver(nel, 1)
+    gs = N(s.element_sens(T(w), T(u), -0.5))
+    wm, um = w.copy(), u.copy()
+    wm[g.clamped_mask()] = 0
+    um[g.clamped_mask()] = 0
+    ref = -0.5 * sens.element_products(g, K0, wm, um)
+    assert relerr(gs, ref) < 1e-13

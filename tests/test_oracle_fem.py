@@ -183,3 +183,18 @@ def test_compliance_identity_and_dense_solve():
     u2 = np.linalg.solve(L.T, np.linalg.solve(L, ff))
     np.testing.assert_allclose(u, u2, rtol=1e-12)
     assert abs(ff @ u - u @ (K @ u)) < 1e-12 * abs(ff @ u)
+
+
+@pytest.mark.parametrize("nel", [(7, 3), (3, 2, 2)])
+def test_matrix_free_apply_equals_assembled(nel):
+    g = fem.Grid(nel)
+    K0 = fem.element_stiffness(g.dim)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.1, 1.0, g.m)
+    v = rng.standard_normal(g.nslots)
+    A = fem.stiffness_slots(g, x, K0)
+    np.testing.assert_allclose(fem.apply_slots(g, x, K0, v), A @ v, rtol=0, atol=1e-13 * np.abs(A @ v).max())
+    Af = fem.stiffness_free(g, x, K0)
+    yf = fem.apply_free_masked(g, x, K0, v)
+    np.testing.assert_allclose(fem.to_free(g, yf), Af @ fem.to_free(g, v), rtol=0, atol=1e-13 * np.abs(yf).max())
+    assert np.all(yf[g.clamped_mask()] == 0)
