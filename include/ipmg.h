@@ -196,6 +196,19 @@ int ipmg_ip_prepare(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm,
 int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
                  ipmg_ip_info* info);
 
+/* Kernel timing for roofline measurements.  Between begin and end, every launch of
+ * one kernel class is bracketed by a pair of HIP events on the context's stream:
+ *   0: damped-Jacobi sweep on the finest level (V-cycle precision)
+ *   1: FP64 operator apply on the finest level (PCG q = A p)
+ *   2: residual pass on the finest level (V-cycle precision)
+ *   3: fused PCG update (z += alpha p, r += alpha q, ||r||^2)
+ * Launches skipped on device after convergence are recorded too (with near-zero
+ * duration).  max_launches: event pairs to keep (further launches are not timed).
+ * durations_ms: [host] capacity entries, each launch's duration; launches: [host]
+ * number recorded.  Both calls synchronise the stream. */
+int ipmg_profile_begin(ipmg_ctx* ctx, int kernel_class, int max_launches);
+int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int capacity, int* launches);
+
 #ifdef __cplusplus
 }
 #endif

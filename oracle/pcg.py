@@ -30,7 +30,11 @@ class PCGResult:
         self.status = status
 
 
-def pcg(apply_A, b, precond, rtol=1e-8, maxit=1000, z0=None):
+def pcg(apply_A, b, precond, rtol=1e-8, maxit=1000, z0=None, flexible=False):
+    """flexible=True replaces the ratio r~'y~ / r'y by the Polak-Ribiere form
+    r~'(y~ - y) / r'y, which keeps conjugacy when the preconditioner varies
+    slightly between applications (a V-cycle evaluated in reduced precision);
+    in exact arithmetic with a fixed preconditioner both forms coincide."""
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
     z = np.zeros_like(b) if z0 is None else np.array(z0, dtype=np.float64)
@@ -69,19 +73,20 @@ def pcg(apply_A, b, precond, rtol=1e-8, maxit=1000, z0=None):
             p = -y
             rho = float(r @ y)
             continue
-        y = precond(r)
-        rho_new = float(r @ y)
+        y_new = precond(r)
+        rho_new = float(r @ y_new)
         if not rho_new > 0.0:
             true_rel = float(np.linalg.norm(apply_A(z) - b)) / bnorm
             return PCGResult(z, iters, rel, true_rel, False, restarts, history, "breakdown")
-        beta = rho_new / rho
+        beta = (rho_new - float(r @ y)) / rho if flexible else rho_new / rho
+        y = y_new
         p = -y + beta * p
         rho = rho_new
     true_rel = float(np.linalg.norm(apply_A(z) - b)) / bnorm
     return PCGResult(z, iters, history[-1], true_rel, False, restarts, history, "maxit")
 
 
-def mg_pcg(H, b, rtol=1e-8, maxit=1000, z0=None, nu1=2, nu2=2, mixed=False):
+def mg_pcg(H, b, rtol=1e-8, maxit=1000, z0=None, nu1=2, nu2=2, mixed=False, flexible=False):
     """PCG on the finest operator of hierarchy H with one V-cycle per step
     (the damping weights live in the hierarchy)."""
     from . import mg
@@ -90,4 +95,4 @@ def mg_pcg(H, b, rtol=1e-8, maxit=1000, z0=None, nu1=2, nu2=2, mixed=False):
         pre = lambda r: mg.vcycle_f32(H, r, nu1, nu2)
     else:
         pre = lambda r: mg.vcycle(H, r, nu1, nu2)
-    return pcg(lambda v: A @ v, b, pre, rtol, maxit, z0)
+    return pcg(lambda v: A @ v, b, pre, rtol, maxit, z0, flexible)

@@ -198,6 +198,38 @@ int ipmg_element_sens(ipmg_ctx* ctx, const double* w, const double* u, double sc
   });
 }
 
+int ipmg_profile_begin(ipmg_ctx* ctx, int kernel_class, int max_launches) {
+  if (kernel_class < 0 || kernel_class > 3 || max_launches < 1 || max_launches > (1 << 16)) return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) {
+    ipmg::sync(c);
+    while ((int)c.prof_ev.size() < 2 * max_launches) {
+      hipEvent_t e;
+      IPMG_HIP(hipEventCreate(&e));
+      c.prof_ev.push_back(e);
+    }
+    c.prof_class = kernel_class;
+    c.prof_used = 0;
+    return IPMG_OK;
+  });
+}
+
+int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int capacity, int* launches) {
+  if (!launches || (capacity > 0 && !durations_ms)) return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) {
+    ipmg::sync(c);
+    const int n = c.prof_used;
+    for (int i = 0; i < n && i < capacity; ++i) {
+      float ms = 0.0f;
+      IPMG_HIP(hipEventElapsedTime(&ms, c.prof_ev[2 * i], c.prof_ev[2 * i + 1]));
+      durations_ms[i] = ms;
+    }
+    *launches = n;
+    c.prof_class = -1;
+    c.prof_used = 0;
+    return IPMG_OK;
+  });
+}
+
 static int check_ip(const ipmg_ip_params* p, const ipmg_ip_state* st) {
   if (!p || !st || !st->u || !st->x || !st->phi || !st->psi) return IPMG_E_INVALID;
   if (!(p->sigma > 0.0 && p->sigma < 1.0) || !(p->frac > 0.0 && p->frac < 1.0) || !(p->pcg_rtol > 0.0) ||

@@ -14,7 +14,9 @@ struct Level {
   void* z2 = nullptr;   // Jacobi ping-pong partner
   void* t = nullptr;    // residual
   void* E = nullptr;    // coarse element matrices (NSYM * m), levels below the finest
+  double* E64 = nullptr;// the same in FP64: the Galerkin chain is formed in FP64 (aliases E in FP64 mode)
   void* bZ = nullptr;   // border vector of Z on this level (n_slots)
+  double* bZ64 = nullptr;// the same in FP64 (aliases bZ in FP64 mode)
 };
 
 // Kernel set of one dimension (implemented for 2 and 3 in ops2d.hip / ops3d.hip).
@@ -26,15 +28,21 @@ struct Ops {
   // omg: device pointer to the damping weight (Jacobi modes); sidx/sidx_in: scalar
   // slots of the mode's reductions.
   virtual void level(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out,
-                     const double* omg, int sidx, int sidx_in, const int* gate) = 0;
+                     const double* omg, int sidx, int sidx_in, const int* gate, const double* dot64 = nullptr) = 0;
+  // p = -y + beta p_old; q = A p (FP64, finest level); alpha = rho / p'q on the device.
+  virtual void dir_apply(Ctx& c, int op, const void* y, const double* pold, double* p, double* q, int first,
+                         const int* gate) = 0;
   // FP64 operator on the finest grid (PCG operator), y = A v.
   virtual void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) = 0;
   virtual void restrict_to(Ctx& c, int lev_f, const void* rf, void* rc, int aug, const int* gate) = 0;
   virtual void prolong_from(Ctx& c, int lev_f, void* z, const void* zc, int aug, const int* gate) = 0;
-  virtual void restrict64_to_T(Ctx& c, int lev_f, const void* rf, void* rc) = 0;  // border vectors
-  virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E of level lev_f-1
+  virtual void restrict64(Ctx& c, int lev_f, const double* rf, double* rc) = 0;    // border vectors
+  virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E64 of level lev_f-1
   virtual void dense_assemble(Ctx& c, int op, double* A, int n) = 0;
   virtual void power_start(Ctx& c, int lev, int aug, void* v) = 0;
+  // Levels 0..tail_top of the V-cycle in one single-workgroup launch:
+  // lev[tail_top].r -> lev[tail_top].z.
+  virtual void tail(Ctx& c, int op, const int* gate) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
   // Interior point kernels (FP64).
   virtual void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi,
@@ -57,6 +65,7 @@ struct Ctx {
   Ops* ops = nullptr;
   std::vector<Level> lev;      // lev[L-1] finest
   size_t tsz = 4;              // sizeof(T) of the V-cycle
+  int tail_top = -1;           // highest level handled by the single-workgroup tail (-1: none)
 
   double K0[576] = {0};        // host copy of the element matrix
   int nd = 8;                  // DOFs per element
@@ -74,6 +83,8 @@ struct Ctx {
 
   // PCG work vectors (FP64, n_slots + 1)
   double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pt = nullptr, *pb = nullptr, *pu = nullptr;
+  double* pp2 = nullptr;       // second search-direction buffer (p is double-buffered)
+  void* yT = nullptr;          // level buffer holding the last preconditioned residual
 
   // coarsest dense solve
   int ncoarse = 0;             // dense size incl. lambda (n_slots_coarse + 1)
@@ -95,7 +106,31 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 
+  // kernel timing (ipmg_profile_*): HIP event pairs around every launch of one class
+  int prof_class = -1;
+  int prof_used = 0;
+  std::vector<hipEvent_t> prof_ev;
+
   const Dims& fine() const { return lev[L - 1].d; }
+};
+
+// Kernel classes timed by ipmg_profile_begin.
+enum ProfClass { PC_FINE_JACOBI = 0, PC_FINE_APPLY64 = 1, PC_FINE_RESID = 2, PC_PCG_UPDATE = 3 };
+
+struct ProfScope {
+  Ctx& c;
+  bool on;
+  int slot;
+  ProfScope(Ctx& cc, int cls) : c(cc), on(false), slot(0) {
+    if (c.prof_class == cls && 2 * (c.prof_used + 1) <= (int)c.prof_ev.size()) {
+      on = true;
+      slot = c.prof_used++;
+      (void)hipEventRecord(c.prof_ev[2 * slot], c.stream);
+    }
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(c.prof_ev[2 * slot + 1], c.stream);
+  }
 };
 
 // Host driver (solver.hip).

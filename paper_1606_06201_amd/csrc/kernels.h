@@ -31,57 +31,58 @@ __device__ inline double load_acquire(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Deterministic two-stage reduction of NV sums per thread (or mins if IS_MIN).
-// Every block publishes its partials; the last block to arrive sums all partials
-// in block order and returns true with the totals in tot[] (valid in all threads of
-// that block).  Other blocks return false.  The block must hold BS threads.
+// Deterministic two-stage reductions.  Stage 1 (inside a kernel): every block
+// reduces its threads' values in a fixed order and writes one partial per value
+// to red.partials[n * MAX_PARTIALS + block].  Stage 2 (a one-block finalize kernel
+// launched next on the same stream): sum_partials adds the partials in block
+// order.  Cross-block communication inside a kernel would need a device-scope
+// release per block, which on a multi-XCD GPU writes back each XCD's L2 and
+// serialises the blocks; the kernel boundary provides the visibility instead.
+__device__ inline unsigned block_id() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+
 template <int NV, bool IS_MIN = false>
-__device__ bool reduce_last(const double (&v)[NV], const Red& red, int ctr, double (&tot)[NV]) {
+__device__ void block_partials(const double (&v)[NV], const Red& red) {
   __shared__ double sh[NV][BS / 64];
-  __shared__ int is_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int n = 0; n < NV; ++n) {
-    double s = IS_MIN ? wave_min(v[n]) : wave_sum(v[n]);
+    const double s = IS_MIN ? wave_min(v[n]) : wave_sum(v[n]);
     if (lane == 0) sh[n][wid] = s;
   }
   __syncthreads();
-  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
-  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   if (threadIdx.x == 0) {
+    const unsigned bid = block_id();
 #pragma unroll
     for (int n = 0; n < NV; ++n) {
       double s = sh[n][0];
       for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh[n][w]) : s + sh[n][w];
       red.partials[(size_t)n * MAX_PARTIALS + bid] = s;
     }
-    __threadfence();
-    const unsigned prev = atomicAdd(&red.counter[ctr], 1u);
-    is_last = (prev == nblocks - 1) ? 1 : 0;
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  __shared__ double sh2[NV][BS / 64];
+}
+
+// Stage 2, called by all BS threads of a single block; totals valid in every thread.
+template <int NV, bool IS_MIN = false>
+__device__ void sum_partials(const Red& red, unsigned nblocks, double (&tot)[NV]) {
+  __shared__ double sh[NV][BS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int n = 0; n < NV; ++n) {
     double s = IS_MIN ? INFINITY : 0.0;
     for (unsigned b = threadIdx.x; b < nblocks; b += BS) {
-      const double p = load_acquire(&red.partials[(size_t)n * MAX_PARTIALS + b]);
+      const double p = red.partials[(size_t)n * MAX_PARTIALS + b];
       s = IS_MIN ? fmin(s, p) : s + p;
     }
     s = IS_MIN ? wave_min(s) : wave_sum(s);
-    if (lane == 0) sh2[n][wid] = s;
+    if (lane == 0) sh[n][wid] = s;
   }
   __syncthreads();
 #pragma unroll
   for (int n = 0; n < NV; ++n) {
-    double s = sh2[n][0];
-    for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh2[n][w]) : s + sh2[n][w];
+    double s = sh[n][0];
+    for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh[n][w]) : s + sh[n][w];
     tot[n] = s;
   }
-  if (threadIdx.x == 0) red.counter[ctr] = 0u;
-  return true;
 }
 
 // --------------------------------------------------------------- operators ----
@@ -276,23 +277,120 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 }
 
 // ------------------------------------------------------------ level kernels --
-enum LevelMode { M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5 };
+enum LevelMode {
+  M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5, M_JACOBI_BETA = 6
+};
+
+// Post-processing of the PCG ratio beta = r~'y~ / r'y (Algorithm PCG) by the
+// thread that owns the final sum.
+__device__ inline void finish_beta(double tot, const Red& red) {
+  if (!(tot > 0.0) || !isfinite(tot)) {
+    red.flags[F_DONE] = 2;
+    red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+  } else {
+    red.scal[S_BETA] = tot / red.scal[S_RHO];
+    red.scal[S_RHO] = tot;
+  }
+}
+
+// Per-node part of one pass over a level (see k_level).  Accumulates the border
+// dot b.v (augmented system) in bdot and the mode's reduction terms in red0/red1.
+template <int DIM, typename T, class Op, int MODE>
+__device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int k, const T* v, const T* r, T* out,
+                                  T omega, const T* augb, T vl, double pin, const double* dot64, double& bdot,
+                                  double& red0, double& red1) {
+  constexpr bool NEED_ROWS = MODE != M_JACOBI0;
+  const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+  T o[DIM];
+  if (i == 0) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) o[c] = T(0);
+  } else {
+    T acc[DIM], dg[DIM], vc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
+    T vn[Geo<DIM>::NB][DIM];
+    if constexpr (NEED_ROWS) {
+      load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
+      node_apply<DIM, T, Op, true, true>(op, d, i, j, k, vn, acc, dg);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
+      if (augb) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const T bc = augb[q * DIM + c];
+          acc[c] += bc * vl;
+          bdot += (double)bc * (double)vc[c];
+        }
+      }
+    } else {
+      node_apply<DIM, T, Op, false, true>(op, d, i, j, k, vn, acc, dg);
+    }
+    T rr[DIM];
+    if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA)
+      load_node<DIM, T>(r, q, rr);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      if constexpr (MODE == M_APPLY) o[c] = acc[c];
+      if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
+      if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) / dg[c];
+      if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] / dg[c];
+      if constexpr (MODE == M_POWER) {
+        o[c] = T(pin * (double)(acc[c] / dg[c]));
+        red0 += (double)o[c] * (double)o[c];
+      }
+      if constexpr (MODE == M_RAYLEIGH) {
+        red0 += (double)vc[c] * (double)acc[c];
+        red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
+      }
+      if constexpr (MODE == M_JACOBI_BETA) red0 += dot64[q * DIM + c] * (double)o[c];
+    }
+  }
+  if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+}
+
+// Lambda entry of a pass over an augmented level, given the border dot tot0 =
+// b.v_u and the node reductions tot1, tot2 (done by one thread).
+template <typename T, int MODE>
+__device__ inline void level_lambda(const T* v, const T* r, T* out, double omega, double c, int64_t n, double pin,
+                                    const double* dot64, double tot0, double tot1, double tot2, const Red& red,
+                                    int sidx) {
+  const double vl = (double)v[n];
+  const double rowl = tot0 + c * vl;   // (Z v)_lambda
+  if constexpr (MODE == M_APPLY) out[n] = T(rowl);
+  if constexpr (MODE == M_RESID) out[n] = T((double)r[n] - rowl);
+  if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) {
+    const T ol = T(vl + omega * ((double)r[n] - rowl) / c);
+    out[n] = ol;
+    if constexpr (MODE == M_JACOBI_BETA) finish_beta(tot1 + dot64[n] * (double)ol, red);
+  }
+  if constexpr (MODE == M_POWER) {
+    const double ol = pin * rowl / c;
+    out[n] = T(ol);
+    red.scal[sidx] = tot1 + ol * ol;
+  }
+  if constexpr (MODE == M_RAYLEIGH) {
+    red.scal[sidx] = tot1 + vl * rowl;
+    red.scal[sidx + 1] = tot2 + vl * c * vl;
+  }
+}
 
 // One pass over the nodes of a level.
-//   M_APPLY    out = A v
-//   M_RESID    out = r - A v
-//   M_JACOBI   out = v + omega D^-1 (r - A v)       (damped Jacobi sweep)
-//   M_JACOBI0  out = omega D^-1 r                   (first sweep from v = 0)
-//   M_POWER    out = D^-1 A v / ||v||, scal[sidx] = ||out||^2 (||v||^2 read from
-//              scal[sidx_in] when sidx_in >= 0, else taken as 1)
-//   M_RAYLEIGH scal[sidx] = v'Av, scal[sidx+1] = v'Dv
+//   M_APPLY       out = A v
+//   M_RESID       out = r - A v
+//   M_JACOBI      out = v + omega D^-1 (r - A v)       (damped Jacobi sweep)
+//   M_JACOBI0     out = omega D^-1 r                   (first sweep from v = 0)
+//   M_JACOBI_BETA M_JACOBI, then beta = dot64'out / rho (the PCG ratio) on the device
+//   M_POWER       out = D^-1 A v / ||v||, scal[sidx] = ||out||^2 (||v||^2 read from
+//                 scal[sidx_in] when sidx_in >= 0, else taken as 1)
+//   M_RAYLEIGH    scal[sidx] = v'Av, scal[sidx+1] = v'Dv
 // Clamped slots of out are written as 0.  With a border (aug.b != nullptr) the
 // lambda entry (index aug.n) is handled by the last block of a reduction.
 template <int DIM, typename T, class Op, int MODE>
 __global__ __launch_bounds__(BS) void k_level(Op op, Dims d, const T* __restrict__ v,
                                               const T* __restrict__ r, T* __restrict__ out,
                                               const double* __restrict__ omg, Aug<T> aug, Red red, int sidx,
-                                              int sidx_in, const int* gate) {
+                                              int sidx_in, const double* __restrict__ dot64, const int* gate) {
   if (gate && *gate) return;
   const T omega = omg ? T(*omg) : T(0);
   double pin = 1.0;
@@ -305,97 +403,155 @@ __global__ __launch_bounds__(BS) void k_level(Op op, Dims d, const T* __restrict
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
   const int k = blockIdx.z;
-  const bool active = i < d.nx1 && j < d.ny1;
-  constexpr bool NEED_ROWS = MODE != M_JACOBI0;
-  constexpr bool NEED_RED = MODE == M_POWER || MODE == M_RAYLEIGH;
-  double red0 = 0.0, red1 = 0.0;   // border dot b.v (aug) / mode reductions
-  double bdot = 0.0;
-  if (active) {
-    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
-    T o[DIM];
-    if (i == 0) {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) o[c] = T(0);
-    } else {
-      T acc[DIM], dg[DIM], vc[DIM];
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
-      if constexpr (NEED_ROWS) {
-        T vn[Geo<DIM>::NB][DIM];
-        load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
-        node_apply<DIM, T, Op, true, true>(op, d, i, j, k, vn, acc, dg);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
-        if (aug.b) {
-          const T vl = v[aug.n];
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) {
-            const T bc = aug.b[q * DIM + c];
-            acc[c] += bc * vl;
-            bdot += (double)bc * (double)vc[c];
-          }
-        }
-      } else {
-        T vn[Geo<DIM>::NB][DIM];
-        node_apply<DIM, T, Op, false, true>(op, d, i, j, k, vn, acc, dg);
-      }
-      T rr[DIM];
-      if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0)
-        load_node<DIM, T>(r, q, rr);
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if constexpr (MODE == M_APPLY) o[c] = acc[c];
-        if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
-        if constexpr (MODE == M_JACOBI) o[c] = vc[c] + omega * (rr[c] - acc[c]) / dg[c];
-        if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] / dg[c];
-        if constexpr (MODE == M_POWER) {
-          o[c] = T(pin * (double)(acc[c] / dg[c]));
-          red0 += (double)o[c] * (double)o[c];
-        }
-        if constexpr (MODE == M_RAYLEIGH) {
-          red0 += (double)vc[c] * (double)acc[c];
-          red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
-        }
-      }
-    }
-    if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
-  }
+  constexpr bool NEED_RED = MODE == M_POWER || MODE == M_RAYLEIGH || MODE == M_JACOBI_BETA;
+  double red0 = 0.0, red1 = 0.0, bdot = 0.0;
+  const T vl = (aug.b && MODE != M_JACOBI0) ? v[aug.n] : T(0);
+  if (i < d.nx1 && j < d.ny1)
+    level_node<DIM, T, Op, MODE>(op, d, i, j, k, v, r, out, omega, aug.b, vl, pin, dot64, bdot, red0, red1);
   if (aug.b) {
     if constexpr (MODE == M_JACOBI0) {
       if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
         out[aug.n] = T((double)omega * (double)r[aug.n] / aug.c);
     } else {
-      double vals[3] = {bdot, red0, red1};
-      double tot[3];
-      if (reduce_last<3>(vals, red, C_AUX, tot)) {
-        if (threadIdx.x == 0) {
-          const double vl = (double)v[aug.n];
-          const double rowl = tot[0] + aug.c * vl;   // (Z v)_lambda
-          if constexpr (MODE == M_APPLY) out[aug.n] = T(rowl);
-          if constexpr (MODE == M_RESID) out[aug.n] = T((double)r[aug.n] - rowl);
-          if constexpr (MODE == M_JACOBI)
-            out[aug.n] = T(vl + (double)omega * ((double)r[aug.n] - rowl) / aug.c);
-          if constexpr (MODE == M_POWER) {
-            const double ol = pin * rowl / aug.c;
-            out[aug.n] = T(ol);
-            red.scal[sidx] = tot[1] + ol * ol;
-          }
-          if constexpr (MODE == M_RAYLEIGH) {
-            red.scal[sidx] = tot[1] + vl * rowl;
-            red.scal[sidx + 1] = tot[2] + vl * aug.c * vl;
-          }
-        }
-      }
+      const double vals[3] = {bdot, red0, red1};
+      block_partials<3>(vals, red);
     }
   } else if constexpr (NEED_RED) {
-    double vals[2] = {red0, red1};
-    double tot[2];
-    if (reduce_last<2>(vals, red, C_AUX, tot)) {
-      if (threadIdx.x == 0) {
-        red.scal[sidx] = tot[0];
-        if constexpr (MODE == M_RAYLEIGH) red.scal[sidx + 1] = tot[1];
+    const double vals[3] = {red0, red1, 0.0};
+    block_partials<3>(vals, red);
+  }
+}
+
+// Finalize of a level pass that reduces (augmented border, M_POWER, M_RAYLEIGH,
+// M_JACOBI_BETA): one block of BS threads, launched right after k_level.
+template <typename T, int MODE>
+__global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const T* __restrict__ r,
+                                                  T* __restrict__ out, const double* __restrict__ omg, int aug,
+                                                  double c, int64_t n, const double* __restrict__ dot64, Red red,
+                                                  unsigned nblocks, int sidx, int sidx_in, const int* gate) {
+  if (gate && *gate) return;
+  double tot[3];
+  sum_partials<3>(red, nblocks, tot);
+  if (threadIdx.x != 0) return;
+  double pin = 1.0;
+  if constexpr (MODE == M_POWER) {
+    if (sidx_in >= 0) {
+      const double s = red.scal[sidx_in];
+      pin = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+    }
+  }
+  if (aug) {
+    level_lambda<T, MODE>(v, r, out, omg ? *omg : 0.0, c, n, pin, dot64, tot[0], tot[1], tot[2], red, sidx);
+  } else {
+    if constexpr (MODE == M_JACOBI_BETA) {
+      finish_beta(tot[0], red);
+    } else {
+      red.scal[sidx] = tot[0];
+      if constexpr (MODE == M_RAYLEIGH) red.scal[sidx + 1] = tot[1];
+    }
+  }
+}
+
+// First step of a PCG iteration, fused: p = -y + beta p_old (p_old, p in separate
+// buffers), q = A p with the FP64 finest-level operator, and alpha = r'y / p'q
+// (Algorithm PCG; the search direction uses the new preconditioned residual).
+// first != 0: beta = 0 (p = -y).
+template <int DIM, typename TY, class Op>
+__global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __restrict__ y,
+                                                  const double* __restrict__ pold, double* __restrict__ p,
+                                                  double* __restrict__ q, Aug<double> aug, Red red, int first,
+                                                  const int* gate) {
+  if (gate && *gate) return;
+  const double beta = first ? 0.0 : red.scal[S_BETA];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  double pq = 0.0, bdot = 0.0;
+  const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
+  if (i < d.nx1 && j < d.ny1) {
+    const int64_t qn = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    double o[DIM], pc[DIM];
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) { o[c] = 0.0; pc[c] = 0.0; }
+    } else {
+      double vn[Geo<DIM>::NB][DIM];
+#pragma unroll
+      for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int nb = nb_index<DIM>(dx, dy, dz);
+            const int ii = i + dx, jj = j + dy, kk = k + dz;
+            if (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1 && kk >= 0 && kk < d.nz1) {
+              const int64_t qq = ((int64_t)kk * d.ny1 + jj) * d.nx1 + ii;
+              TY yy[DIM];
+              load_node<DIM, TY>(y, qq, yy);
+              if (first) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) vn[nb][c] = -(double)yy[c];
+              } else {
+                double po[DIM];
+                load_node<DIM, double>(pold, qq, po);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) vn[nb][c] = -(double)yy[c] + beta * po[c];
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < DIM; ++c) vn[nb][c] = 0.0;
+            }
+          }
+      double acc[DIM], dg[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) { acc[c] = 0.0; dg[c] = 0.0; pc[c] = vn[nb_index<DIM>(0, 0, 0)][c]; }
+      node_apply<DIM, double, Op, true, false>(op, d, i, j, k, vn, acc, dg);
+      if (aug.b) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const double bc = aug.b[qn * DIM + c];
+          acc[c] += bc * pl;
+          bdot += bc * pc[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        o[c] = acc[c];
+        pq += pc[c] * acc[c];
       }
     }
+    store_node<DIM, double>(p, qn, pc);
+    store_node<DIM, double>(q, qn, o);
+  }
+  const double vals[2] = {pq, bdot};
+  block_partials<2>(vals, red);
+}
+
+// Finalize of k_dir_apply: lambda entries of p and q (augmented system) and
+// alpha = rho / p'q, with the breakdown test p'q > 0.
+template <typename TY>
+__global__ __launch_bounds__(BS) void k_dir_fin(const TY* __restrict__ y, const double* __restrict__ pold,
+                                                double* __restrict__ p, double* __restrict__ q, int aug, double c,
+                                                int64_t n, int first, Red red, unsigned nblocks, const int* gate) {
+  if (gate && *gate) return;
+  double tot[2];
+  sum_partials<2>(red, nblocks, tot);
+  if (threadIdx.x != 0) return;
+  double ptq = tot[0];
+  if (aug) {
+    const double beta = first ? 0.0 : red.scal[S_BETA];
+    const double pl = -(double)y[n] + (first ? 0.0 : beta * pold[n]);
+    const double ql = tot[1] + c * pl;
+    p[n] = pl;
+    q[n] = ql;
+    ptq += pl * ql;
+  }
+  red.scal[S_PQ] = ptq;
+  if (!(ptq > 0.0) || !isfinite(ptq)) {
+    red.flags[F_DONE] = 2;
+    red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+  } else {
+    red.scal[S_ALPHA] = red.scal[S_RHO] / ptq;
   }
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 #include "ctx.h"
 #include "kernels.h"
+#include "tail.h"
 
 namespace ipmg {
 
@@ -154,8 +155,14 @@ __global__ __launch_bounds__(BS) void k_ip_elements(Dims d, const double* __rest
     acc[0] = w; acc[1] = G3 * w; acc[2] = xe; acc[3] = G3 * G3;
     acc[4] = ph * ph; acc[5] = ps * ps; acc[6] = ph * xe + ps * xt;
   }
+  block_partials<7>(acc, red);
+}
+
+// Sums of k_ip_elements into scal[S_TMP0..6].
+static __global__ __launch_bounds__(BS) void k_ip_elements_fin(Red red, unsigned nblocks) {
   double tot[7];
-  if (reduce_last<7>(acc, red, C_AUX, tot) && threadIdx.x == 0)
+  sum_partials<7>(red, nblocks, tot);
+  if (threadIdx.x == 0)
     for (int n = 0; n < 7; ++n) red.scal[S_TMP0 + n] = tot[n];
 }
 
@@ -208,12 +215,18 @@ __global__ __launch_bounds__(BS) void k_ip_nodes(Dims d, const double* __restric
       acc[2] += fc * (i > 0 ? u[sl] : 0.0);
     }
   }
+  block_partials<3>(acc, red);
+}
+
+// Sums of k_ip_nodes into scal[S_MIN0..2] and the lambda entry of the right-hand side.
+static __global__ __launch_bounds__(BS) void k_ip_nodes_fin(Red red, unsigned nblocks, double V, double* rhs, int64_t n) {
   double tot[3];
-  if (reduce_last<3>(acc, red, C_AUX, tot) && threadIdx.x == 0) {
+  sum_partials<3>(red, nblocks, tot);
+  if (threadIdx.x == 0) {
     red.scal[S_MIN0] = tot[0];
     red.scal[S_MIN1] = tot[1];
     red.scal[S_MIN2] = tot[2];
-    rhs[d.nslots] = -(red.scal[S_TMP2] - V) + red.scal[S_TMP1];
+    rhs[n] = -(red.scal[S_TMP2] - V) + red.scal[S_TMP1];
   }
 }
 
@@ -251,8 +264,14 @@ __global__ __launch_bounds__(BS) void k_ip_recover(Dims d, const double* __restr
     if (ddphi < 0.0) mins[2] = -ph / ddphi;
     if (ddpsi < 0.0) mins[3] = -ps / ddpsi;
   }
+  block_partials<4, true>(mins, red);
+}
+
+// Step length from the minima of k_ip_recover.
+static __global__ __launch_bounds__(BS) void k_ip_recover_fin(Red red, unsigned nblocks, double frac, int all_blocks) {
   double tot[4];
-  if (reduce_last<4, true>(mins, red, C_AUX, tot) && threadIdx.x == 0) {
+  sum_partials<4, true>(red, nblocks, tot);
+  if (threadIdx.x == 0) {
     double a = fmin(1.0, fmin(frac * tot[0], frac * tot[1]));
     if (all_blocks) a = fmin(a, fmin(frac * tot[2], frac * tot[3]));
     red.scal[S_ALPHA] = a;
@@ -301,11 +320,19 @@ struct OpsImpl : Ops {
 
   template <typename T, class Op>
   void launch_level(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out,
-                    const double* omg, Aug<T> aug, int sidx, int sidx_in, const int* gate) {
+                    const double* omg, Aug<T> aug, int sidx, int sidx_in, const int* gate,
+                    const double* dot64 = nullptr) {
     const dim3 g = node_grid(d);
-    IPMG_REQUIRE((int64_t)g.x * g.y * g.z <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
-#define IPMG_LEVEL_CASE(M) \
-  case M: k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, gate); break;
+    const unsigned nb = g.x * g.y * g.z;
+    IPMG_REQUIRE((int64_t)nb <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+    const bool fin = (aug.b && mode != M_JACOBI0) || mode == M_POWER || mode == M_RAYLEIGH || mode == M_JACOBI_BETA;
+#define IPMG_LEVEL_CASE(M)                                                                                   \
+  case M:                                                                                                    \
+    k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, dot64, gate); \
+    if (fin)                                                                                                 \
+      k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb, \
+                                                 sidx, sidx_in, gate);                                      \
+    break;
     switch (mode) {
       IPMG_LEVEL_CASE(M_APPLY)
       IPMG_LEVEL_CASE(M_RESID)
@@ -313,6 +340,7 @@ struct OpsImpl : Ops {
       IPMG_LEVEL_CASE(M_JACOBI0)
       IPMG_LEVEL_CASE(M_POWER)
       IPMG_LEVEL_CASE(M_RAYLEIGH)
+      IPMG_LEVEL_CASE(M_JACOBI_BETA)
       default: throw Error(IPMG_E_INVALID, "bad level mode");
     }
 #undef IPMG_LEVEL_CASE
@@ -320,26 +348,51 @@ struct OpsImpl : Ops {
 
   template <typename T>
   void level_t(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out, const double* omg,
-               int sidx, int sidx_in, const int* gate) {
+               int sidx, int sidx_in, const int* gate, const double* dot64) {
     const Dims& d = c.lev[lev].d;
     Aug<T> aug{op == IPMG_OP_Z ? (const T*)c.lev[lev].bZ : nullptr, c.cZ, d.nslots};
     if (lev == c.L - 1) {
       if (op == IPMG_OP_K)
         launch_level<T>(c, d, OpFineK<DIM, T>{(const T*)c.xT, d.m}, mode, (const T*)v, (const T*)r, (T*)out, omg,
-                        aug, sidx, sidx_in, gate);
+                        aug, sidx, sidx_in, gate, dot64);
       else
         launch_level<T>(c, d, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, mode, (const T*)v, (const T*)r,
-                        (T*)out, omg, aug, sidx, sidx_in, gate);
+                        (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else {
       launch_level<T>(c, d, OpCoarse<DIM, T>{(const T*)c.lev[lev].E, d.m}, mode, (const T*)v, (const T*)r, (T*)out,
-                      omg, aug, sidx, sidx_in, gate);
+                      omg, aug, sidx, sidx_in, gate, dot64);
     }
   }
 
   void level(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out, const double* omg,
-             int sidx, int sidx_in, const int* gate) override {
-    if (c.fp32) level_t<float>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate);
-    else level_t<double>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate);
+             int sidx, int sidx_in, const int* gate, const double* dot64) override {
+    if (c.fp32) level_t<float>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate, dot64);
+    else level_t<double>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate, dot64);
+  }
+
+  template <typename TY, class Op>
+  void launch_dir_apply(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q,
+                        Aug<double> aug, int first, const int* gate) {
+    const Dims& d = c.fine();
+    const dim3 g = node_grid(d);
+    k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+    k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
+                                          g.x * g.y * g.z, gate);
+  }
+  void dir_apply(Ctx& c, int op, const void* y, const double* pold, double* p, double* q, int first,
+                 const int* gate) override {
+    const Dims& d = c.fine();
+    if (op == IPMG_OP_K) {
+      OpFineK<DIM, double> o{c.x64, d.m};
+      Aug<double> a{nullptr, 0.0, d.nslots};
+      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate);
+      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate);
+    } else {
+      OpFineZ<DIM, double> o{c.x64, c.h64, d.m};
+      Aug<double> a{c.bZ64, c.cZ, d.nslots};
+      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate);
+      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate);
+    }
   }
 
   void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) override {
@@ -361,15 +414,10 @@ struct OpsImpl : Ops {
     else
       k_restrict<DIM, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (double*)rc, aug, gate);
   }
-  void restrict64_to_T(Ctx& c, int lev_f, const void* rf, void* rc) override {
+  void restrict64(Ctx& c, int lev_f, const double* rf, double* rc) override {
     const Dims& f = c.lev[lev_f].d;
     const Dims& cd = c.lev[lev_f - 1].d;
-    if (c.fp32)
-      k_restrict<DIM, float, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (float*)rc, 0,
-                                                                          nullptr);
-    else
-      k_restrict<DIM, double, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, (const double*)rf, (double*)rc, 0,
-                                                                           nullptr);
+    k_restrict<DIM, double, double><<<node_grid(cd), BS, 0, c.stream>>>(f, cd, rf, rc, 0, nullptr);
   }
   void prolong_from(Ctx& c, int lev_f, void* z, const void* zc, int aug, const int* gate) override {
     const Dims& f = c.lev[lev_f].d;
@@ -380,30 +428,25 @@ struct OpsImpl : Ops {
       k_prolong<DIM, double><<<node_grid(f), BS, 0, c.stream>>>(f, cd, (double*)z, (const double*)zc, aug, gate);
   }
 
-  template <typename T, class Op>
-  void launch_galerkin(Ctx& c, const Op& op, const Dims& f, const Dims& cd, T* Ec) {
+  template <class Op>
+  void launch_galerkin(Ctx& c, const Op& op, const Dims& f, const Dims& cd, double* Ec) {
     constexpr int ND = Geo<DIM>::ND;
-    k_galerkin<DIM, T, Op><<<lin_grid(cd.m * ND), BS, 0, c.stream>>>(op, f, cd, Ec);
+    k_galerkin<DIM, double, Op><<<lin_grid(cd.m * ND), BS, 0, c.stream>>>(op, f, cd, Ec);
   }
-  template <typename T>
-  void galerkin_t(Ctx& c, int lev_f, int op) {
+  // E64 of level lev_f-1 from level lev_f, accumulated and stored in FP64.
+  void galerkin(Ctx& c, int lev_f, int op) override {
     const Dims& f = c.lev[lev_f].d;
     const Dims& cd = c.lev[lev_f - 1].d;
-    T* Ec = (T*)c.lev[lev_f - 1].E;
+    double* Ec = c.lev[lev_f - 1].E64;
     if (lev_f == c.L - 1) {
-      if (op == IPMG_OP_K) launch_galerkin<T>(c, OpFineK<DIM, double>{c.x64, f.m}, f, cd, Ec);
-      else launch_galerkin<T>(c, OpFineZ<DIM, double>{c.x64, c.h64, f.m}, f, cd, Ec);
+      if (op == IPMG_OP_K) launch_galerkin(c, OpFineK<DIM, double>{c.x64, f.m}, f, cd, Ec);
+      else launch_galerkin(c, OpFineZ<DIM, double>{c.x64, c.h64, f.m}, f, cd, Ec);
     } else {
-      launch_galerkin<T>(c, OpCoarse<DIM, T>{(const T*)c.lev[lev_f].E, f.m}, f, cd, Ec);
+      launch_galerkin(c, OpCoarse<DIM, double>{c.lev[lev_f].E64, f.m}, f, cd, Ec);
     }
   }
-  void galerkin(Ctx& c, int lev_f, int op) override {
-    if (c.fp32) galerkin_t<float>(c, lev_f, op);
-    else galerkin_t<double>(c, lev_f, op);
-  }
 
-  template <typename T>
-  void dense_t(Ctx& c, int op, double* A, int n) {
+  void dense_assemble(Ctx& c, int op, double* A, int n) override {
     const Dims& d = c.lev[0].d;
     const int aug = op == IPMG_OP_Z;
     const unsigned g = lin_grid(n);
@@ -415,13 +458,47 @@ struct OpsImpl : Ops {
         k_dense_assemble<DIM, OpFineZ<DIM, double>, double><<<g, BS, 0, c.stream>>>(
             OpFineZ<DIM, double>{c.x64, c.h64, d.m}, d, c.bZ64, c.cZ, aug, A, n);
     } else {
-      k_dense_assemble<DIM, OpCoarse<DIM, T>, T><<<g, BS, 0, c.stream>>>(
-          OpCoarse<DIM, T>{(const T*)c.lev[0].E, d.m}, d, (const T*)c.lev[0].bZ, c.cZ, aug, A, n);
+      k_dense_assemble<DIM, OpCoarse<DIM, double>, double><<<g, BS, 0, c.stream>>>(
+          OpCoarse<DIM, double>{c.lev[0].E64, d.m}, d, c.lev[0].bZ64, c.cZ, aug, A, n);
     }
   }
-  void dense_assemble(Ctx& c, int op, double* A, int n) override {
-    if (c.fp32) dense_t<float>(c, op, A, n);
-    else dense_t<double>(c, op, A, n);
+
+  template <typename T, class TopOp>
+  void launch_tail(Ctx& c, const TopOp& top, int top_is_fine, int op, const int* gate) {
+    TailArgs<T> a{};
+    a.nt = c.tail_top + 1;
+    int off = 0;
+    for (int k = 0; k < a.nt; ++k) {
+      TailLev<T>& L = a.lv[k];
+      L.d = c.lev[k].d;
+      L.E = (const T*)c.lev[k].E;
+      L.b = op == IPMG_OP_Z ? (const T*)c.lev[k].bZ : nullptr;
+      L.omg = c.omega_dev + k;
+      L.off = off;
+      off += 3 * (int)(L.d.nslots + 1);
+    }
+    a.rin = (const T*)c.lev[c.tail_top].r;
+    a.zout = (T*)c.lev[c.tail_top].z;
+    a.Ainv = c.dAi;
+    a.n0 = (int)c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);
+    a.c = c.cZ;
+    a.aug = op == IPMG_OP_Z;
+    a.nu1 = c.desc.nu_pre;
+    a.nu2 = c.desc.nu_post;
+    const size_t lds = sizeof(T) * (size_t)off;
+    k_tail<DIM, T, TopOp><<<1, TAIL_THREADS, lds, c.stream>>>(top, top_is_fine, a, gate);
+  }
+  template <typename T>
+  void tail_t(Ctx& c, int op, const int* gate) {
+    const bool fine = c.tail_top == c.L - 1;
+    const Dims& d = c.fine();
+    if (fine && op == IPMG_OP_K) launch_tail<T>(c, OpFineK<DIM, T>{(const T*)c.xT, d.m}, 1, op, gate);
+    else if (fine) launch_tail<T>(c, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, 1, op, gate);
+    else launch_tail<T>(c, OpCoarse<DIM, T>{nullptr, 0}, 0, op, gate);
+  }
+  void tail(Ctx& c, int op, const int* gate) override {
+    if (c.fp32) tail_t<float>(c, op, gate);
+    else tail_t<double>(c, op, gate);
   }
 
   void power_start(Ctx& c, int lev, int aug, void* v) override {
@@ -438,23 +515,27 @@ struct OpsImpl : Ops {
   void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi, double lam,
                    double s, double r, double xbar) override {
     const Dims& d = c.fine();
+    IPMG_REQUIRE(lin_grid(d.m) <= (unsigned)MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
     if (c.fp32)
       k_ip_elements<DIM, float><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, x, phi, psi, lam, s, r, xbar, c.ipG3,
                                                                      c.ipW, c.ipSW, c.h64, (float*)c.hT, c.red);
     else
       k_ip_elements<DIM, double><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, x, phi, psi, lam, s, r, xbar, c.ipG3,
                                                                       c.ipW, c.ipSW, c.h64, nullptr, c.red);
+    k_ip_elements_fin<<<1, BS, 0, c.stream>>>(c.red, lin_grid(d.m));
   }
   void ip_nodes(Ctx& c, const double* Ku, const double* f, const double* u, double* rhs) override {
     const Dims& d = c.fine();
-    k_ip_nodes<DIM><<<node_grid(d), BS, 0, c.stream>>>(d, Ku, f, u, c.ipG3, c.ipSW, c.h64, c.ipV, rhs, c.bZ64,
-                                                        c.red);
+    const dim3 g = node_grid(d);
+    k_ip_nodes<DIM><<<g, BS, 0, c.stream>>>(d, Ku, f, u, c.ipG3, c.ipSW, c.h64, c.ipV, rhs, c.bZ64, c.red);
+    k_ip_nodes_fin<<<1, BS, 0, c.stream>>>(c.red, g.x * g.y * g.z, c.ipV, rhs, d.nslots);
   }
   void ip_recover(Ctx& c, const double* du, const double* x, const double* phi, const double* psi, double s,
                   double r, double xbar, double frac, int all_blocks) override {
     const Dims& d = c.fine();
     k_ip_recover<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, du, x, phi, psi, c.ipG3, c.ipW, c.ipSW, c.h64, s, r,
                                                            xbar, frac, all_blocks, c.ipDx, c.ipDphi, c.ipDpsi, c.red);
+    k_ip_recover_fin<<<1, BS, 0, c.stream>>>(c.red, lin_grid(d.m), frac, all_blocks);
   }
   void ip_update(Ctx& c, double* u, const double* du, double* x, double* phi, double* psi) override {
     const Dims& d = c.fine();

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "ctx.h"
@@ -54,7 +55,13 @@ static void ensure_z_buffers(Ctx& c) {
   dalloc(c.bZ64, sizeof(double) * n1);
   if (c.fp32) dalloc(c.lev[c.L - 1].bZ, sizeof(float) * n1);
   else c.lev[c.L - 1].bZ = c.bZ64;
-  for (int k = 0; k < c.L - 1; ++k) dalloc(c.lev[k].bZ, c.tsz * ((size_t)c.lev[k].d.nslots + 1));
+  c.lev[c.L - 1].bZ64 = c.bZ64;
+  for (int k = 0; k < c.L - 1; ++k) {
+    const size_t nk = (size_t)c.lev[k].d.nslots + 1;
+    dalloc(c.lev[k].bZ64, sizeof(double) * nk);
+    if (c.fp32) dalloc(c.lev[k].bZ, sizeof(float) * nk);
+    else c.lev[k].bZ = c.lev[k].bZ64;
+  }
   dalloc(c.ipG3, sizeof(double) * m);
   dalloc(c.ipW, sizeof(double) * m);
   dalloc(c.ipSW, sizeof(double) * m);
@@ -93,6 +100,19 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   }
   const Dims& fd = c.fine();
   IPMG_REQUIRE(fd.nslots < ((int64_t)1 << 31), IPMG_E_INVALID, "grid too large");
+  // coarse tail: the lowest levels whose three vectors fit in 64 KB of LDS
+  {
+    size_t lds = 0;
+    c.tail_top = -1;
+    for (int k = 0; k < c.L && k < 12; ++k) {
+      lds += 3 * c.tsz * ((size_t)c.lev[k].d.nslots + 1);
+      if (lds > 64 * 1024 - 512 || c.lev[k].d.nnodes > 4096) break;
+      c.tail_top = k;
+    }
+    if (const char* e = std::getenv("IPMG_NO_TAIL")) {
+      if (e[0] == '1') c.tail_top = -1;
+    }
+  }
   c.ncoarse = (int)std::min<int64_t>(c.lev[0].d.nslots + 1, (int64_t)1 << 30);
 
   // reductions
@@ -121,7 +141,11 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
     dalloc(l.t, c.tsz * n1);
     IPMG_HIP(hipMemsetAsync(l.z, 0, c.tsz * n1, st));
     IPMG_HIP(hipMemsetAsync(l.z2, 0, c.tsz * n1, st));
-    if (k < c.L - 1) dalloc(l.E, c.tsz * (size_t)nsym * (size_t)l.d.m);
+    if (k < c.L - 1) {
+      dalloc(l.E64, sizeof(double) * (size_t)nsym * (size_t)l.d.m);
+      if (c.fp32) dalloc(l.E, sizeof(float) * (size_t)nsym * (size_t)l.d.m);
+      else l.E = l.E64;
+    }
   }
   dalloc(c.x64, sizeof(double) * fd.m);
   if (c.fp32) dalloc(c.xT, sizeof(float) * fd.m);
@@ -133,6 +157,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   dalloc(c.pt, sizeof(double) * n1);
   dalloc(c.pb, sizeof(double) * n1);
   dalloc(c.pu, sizeof(double) * n1);
+  dalloc(c.pp2, sizeof(double) * n1);
   dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
   vfill_small(st, c.omega_dev, c.L, d.omega);
 
@@ -150,16 +175,21 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
 void ctx_free(Ctx& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   for (auto& l : c.lev) {
-    dfree(l.r); dfree(l.z); dfree(l.z2); dfree(l.t); dfree(l.E);
-    if (l.bZ != (void*)c.bZ64) dfree(l.bZ);
+    dfree(l.r); dfree(l.z); dfree(l.z2); dfree(l.t);
+    if (l.E != (void*)l.E64) dfree(l.E);
+    l.E = nullptr;
+    dfree(l.E64);
+    if (l.bZ != (void*)l.bZ64 && l.bZ != (void*)c.bZ64) dfree(l.bZ);
     l.bZ = nullptr;
+    if (l.bZ64 != c.bZ64) dfree(l.bZ64);
+    l.bZ64 = nullptr;
   }
   if (c.xT != (void*)c.x64) dfree(c.xT);
   c.xT = nullptr;
   if (c.hT != (void*)c.h64) dfree(c.hT);
   c.hT = nullptr;
   dfree(c.x64); dfree(c.h64); dfree(c.bZ64);
-  dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu);
+  dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu); dfree(c.pp2);
   dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.omega_dev);
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
@@ -167,6 +197,8 @@ void ctx_free(Ctx& c) {
   if (c.hscal) (void)hipHostFree(c.hscal);
   if (c.hflags) (void)hipHostFree(c.hflags);
   c.hscal = nullptr; c.hflags = nullptr;
+  for (auto e : c.prof_ev) (void)hipEventDestroy(e);
+  c.prof_ev.clear();
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.ev1) (void)hipEventDestroy(c.ev1);
   c.ev0 = c.ev1 = nullptr;
@@ -224,11 +256,14 @@ void mg_setup(Ctx& c, int op, double* ms) {
   const int L = c.L;
   if (op == IPMG_OP_Z && c.fp32)
     vconvert<float, double>(c.stream, c.bZ64, (float*)c.lev[L - 1].bZ, c.fine().nslots, nullptr);
+  const int nsym = c.nd * (c.nd + 1) / 2;
   for (int k = L - 1; k >= 1; --k) {
-    c.ops->galerkin(c, k, op);
+    Level& lc = c.lev[k - 1];
+    c.ops->galerkin(c, k, op);                       // FP64 chain
+    if (c.fp32) vconvert<float, double>(c.stream, lc.E64, (float*)lc.E, (int64_t)nsym * lc.d.m, nullptr);
     if (op == IPMG_OP_Z) {
-      if (k == L - 1) c.ops->restrict64_to_T(c, k, c.bZ64, c.lev[k - 1].bZ);
-      else c.ops->restrict_to(c, k, c.lev[k].bZ, c.lev[k - 1].bZ, 0, nullptr);
+      c.ops->restrict64(c, k, c.lev[k].bZ64, lc.bZ64);
+      if (c.fp32) vconvert<float, double>(c.stream, lc.bZ64, (float*)lc.bZ, lc.d.nslots, nullptr);
     }
   }
   IPMG_HIP(hipGetLastError());
@@ -248,9 +283,15 @@ void mg_setup(Ctx& c, int op, double* ms) {
 }
 
 // V-cycle on level k: lev[k].r -> returned buffer (Algorithm MG, zero start).
-static void* vcycle_level(Ctx& c, int op, int k, const int* gate) {
+// beta64 (finest level only): if not null, the last post-smoothing sweep also
+// forms beta = beta64'y / rho of Algorithm PCG on the device.
+static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* beta64) {
   Level& l = c.lev[k];
   const int aug = op == IPMG_OP_Z;
+  if (k == c.tail_top) {
+    c.ops->tail(c, op, gate);
+    return l.z;
+  }
   if (k == 0) {
     const int n = l.d.nslots + aug;
     if (c.fp32) dense_solve<float>(c.stream, c.dAi, n, (const float*)l.r, (float*)l.z, gate);
@@ -260,23 +301,30 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate) {
   void* cur = l.z;
   void* nxt = l.z2;
   const double* w = c.omega_dev + k;
+  const bool fine = k == c.L - 1;
   c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);       // pre-smoothing
   for (int s = 1; s < c.desc.nu_pre; ++s) {
+    ProfScope ps(c, fine ? PC_FINE_JACOBI : -2);
     c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
     std::swap(cur, nxt);
   }
-  c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);       // restricted residual
+  {
+    ProfScope ps(c, fine ? PC_FINE_RESID : -2);
+    c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);     // restricted residual
+  }
   c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
-  void* vc = vcycle_level(c, op, k - 1, gate);                                // coarse correction
+  void* vc = vcycle_level(c, op, k - 1, gate, nullptr);                       // coarse correction
   c.ops->prolong_from(c, k, cur, vc, aug, gate);                              // solution update
   for (int s = 0; s < c.desc.nu_post; ++s) {                                  // post-smoothing
-    c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
+    ProfScope ps(c, fine ? PC_FINE_JACOBI : -2);
+    const bool last = beta64 && s == c.desc.nu_post - 1;
+    c.ops->level(c, k, op, last ? M_JACOBI_BETA : M_JACOBI, cur, l.r, nxt, w, 0, -1, gate, last ? beta64 : nullptr);
     std::swap(cur, nxt);
   }
   return cur;
 }
 
-void* vcycle(Ctx& c, int op, const int* gate) { return vcycle_level(c, op, c.L - 1, gate); }
+void* vcycle(Ctx& c, int op, const int* gate) { return vcycle_level(c, op, c.L - 1, gate, nullptr); }
 
 void vcycle64(Ctx& c, int op, const double* r, double* z) {
   IPMG_REQUIRE(c.hier_op == op, IPMG_E_STATE, "multigrid hierarchy not set up for this operator");
@@ -292,41 +340,45 @@ void vcycle64(Ctx& c, int op, const double* r, double* z) {
   sync(c);
 }
 
-// Enqueue one PCG iteration (all kernels gated on flags[F_DONE]).
-static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate) {
-  c.ops->fine_apply64(c, op, c.pp, c.pq, gate);                        // q = A p
-  vdot_alpha(c.stream, c.pp, c.pq, n, c.red, gate);                    // alpha = r'y / p'q
-  void* rT = c.lev[c.L - 1].r;
-  if (c.fp32)
-    vpcg_update<float>(c.stream, c.pu, c.pr, c.pp, c.pq, (float*)rT, n, c.red, gate);
-  else
-    vpcg_update<double>(c.stream, c.pu, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
-  void* y = vcycle(c, op, gate);                                        // y = M r
-  if (c.fp32) {
-    vdot_beta<float>(c.stream, c.pr, (const float*)y, n, c.red, gate);  // beta
-    vpcg_dir<float>(c.stream, c.pp, (const float*)y, n, c.red, 0, gate);
-  } else {
-    vdot_beta<double>(c.stream, c.pr, (const double*)y, n, c.red, gate);
-    vpcg_dir<double>(c.stream, c.pp, (const double*)y, n, c.red, 0, gate);
+// Enqueue one PCG iteration (all kernels gated on flags[F_DONE]):
+//   p = -y + beta p, q = A p, alpha      (one fused kernel)
+//   z += alpha p, r += alpha q, ||r||^2  (one fused kernel, sets the done flag)
+//   y = M r with beta = r'y / rho fused into the last smoothing sweep.
+// `first` selects beta = 0 (first step after a (re)start).
+static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first) {
+  {
+    ProfScope ps(c, PC_FINE_APPLY64);
+    c.ops->dir_apply(c, op, c.yT, c.pp, c.pp2, c.pq, first, gate);
   }
+  std::swap(c.pp, c.pp2);                                               // c.pp holds the new p
+  void* rT = c.lev[c.L - 1].r;
+  {
+    ProfScope ps(c, PC_PCG_UPDATE);
+    if (c.fp32)
+      vpcg_update<float>(c.stream, c.pu, c.pr, c.pp, c.pq, (float*)rT, n, c.red, gate);
+    else
+      vpcg_update<double>(c.stream, c.pu, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
+  }
+  const bool fused_beta = c.desc.nu_post >= 1 && c.tail_top < c.L - 1;
+  void* y = vcycle_level(c, op, c.L - 1, gate, fused_beta ? c.pr : nullptr);
+  if (!fused_beta) {
+    if (c.fp32) vdot_beta<float>(c.stream, c.pr, (const float*)y, n, c.red, gate);
+    else vdot_beta<double>(c.stream, c.pr, (const double*)y, n, c.red, gate);
+  }
+  c.yT = y;
 }
 
-// r (in c.pr) -> y = M r, rho = r'y, p = -y.
+// r (in c.pr) -> y = M r and rho = r'y; the next iteration starts with p = -y.
 static void pcg_restart_direction(Ctx& c, int op, int64_t n) {
   const int* gate = c.red.flags + F_DONE;
   void* rT = c.lev[c.L - 1].r;
   if (c.fp32) vconvert<float, double>(c.stream, c.pr, (float*)rT, n, nullptr);
   else vconvert<double, double>(c.stream, c.pr, (double*)rT, n, nullptr);
   void* y = vcycle(c, op, gate);
-  if (c.fp32) {
-    vdot_store<float>(c.stream, c.pr, (const float*)y, n, c.red, S_TMP0, gate);
-    vset_rho(c.stream, c.red, S_TMP0);
-    vpcg_dir<float>(c.stream, c.pp, (const float*)y, n, c.red, 1, gate);
-  } else {
-    vdot_store<double>(c.stream, c.pr, (const double*)y, n, c.red, S_TMP0, gate);
-    vset_rho(c.stream, c.red, S_TMP0);
-    vpcg_dir<double>(c.stream, c.pp, (const double*)y, n, c.red, 1, gate);
-  }
+  if (c.fp32) vdot_store<float>(c.stream, c.pr, (const float*)y, n, c.red, S_TMP0, gate);
+  else vdot_store<double>(c.stream, c.pr, (const double*)y, n, c.red, S_TMP0, gate);
+  vset_rho(c.stream, c.red, S_TMP0);
+  c.yT = y;
 }
 
 int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info) {
@@ -373,7 +425,7 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
     int slot = 0;
     enq = 0;
     while (iters_before + enq < maxit) {
-      pcg_iteration(c, op, n, gate);
+      pcg_iteration(c, op, n, gate, enq == 0 ? 1 : 0);
       IPMG_HIP(hipMemcpyAsync(c.hflags + F_COUNT * (1 + slot), c.red.flags, sizeof(int) * F_COUNT,
                               hipMemcpyDeviceToHost, c.stream));
       IPMG_HIP(hipEventRecord(slot ? c.ev1 : c.ev0, c.stream));

@@ -48,15 +48,23 @@ __device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
   }
 }
 
+// One-block finalize: sum the partials of the previous kernel and apply `fin`.
+__global__ __launch_bounds__(BS) void k_fin1(Red red, unsigned nblocks, int fin, int sidx, const int* gate) {
+  if (gate && *gate) return;
+  double tot[1];
+  sum_partials<1>(red, nblocks, tot);
+  if (threadIdx.x == 0) finish(fin, tot[0], red, sidx);
+}
+
 template <typename TA, typename TB>
 __global__ __launch_bounds__(BS) void k_dot(const TA* __restrict__ a, const TB* __restrict__ b, int64_t n,
-                                            Red red, int fin, int sidx, const int* gate) {
+                                            Red red, const int* gate) {
   if (gate && *gate) return;
   double s = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
     s += (double)a[t] * (double)b[t];
-  double v[1] = {s}, tot[1];
-  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) finish(fin, tot[0], red, sidx);
+  const double v[1] = {s};
+  block_partials<1>(v, red);
 }
 
 // z += alpha p; r += alpha q; rT = (T) r; ||r||^2 -> convergence flag.
@@ -74,8 +82,8 @@ __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, doubl
     if (rT) rT[t] = T(rn);
     s += rn * rn;
   }
-  double v[1] = {s}, tot[1];
-  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) finish(FIN_RN2, tot[0], red, 0);
+  const double v[1] = {s};
+  block_partials<1>(v, red);
 }
 
 // p = -y + beta p  (the reading p := -y~ + beta p of Algorithm PCG).
@@ -97,8 +105,8 @@ __global__ __launch_bounds__(BS) void k_sub_norm(const double* __restrict__ a, c
     out[t] = o;
     s += o * o;
   }
-  double v[1] = {s}, tot[1];
-  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) red.scal[sidx] = tot[0];
+  const double v[1] = {s};
+  block_partials<1>(v, red);
 }
 
 // dst = src with clamped slots (nodes with i == 0) zeroed; entries beyond the
@@ -115,8 +123,8 @@ __global__ __launch_bounds__(BS) void k_mask_copy(const double* __restrict__ src
     s += v * v;
   }
   if (bad) red.flags[F_BAD] = 1;
-  double v[1] = {s}, tot[1];
-  if (reduce_last<1>(v, red, C_MAIN, tot) && threadIdx.x == 0) red.scal[sidx] = tot[0];
+  const double v[1] = {s};
+  block_partials<1>(v, red);
 }
 
 __global__ __launch_bounds__(BS) void k_fill(double* __restrict__ dst, double value, int64_t n) {
@@ -258,23 +266,28 @@ __global__ __launch_bounds__(BS) void k_dense_solve(const double* __restrict__ A
 
 // ---------------------------------------------------------------- launchers --
 void vdot(hipStream_t st, const double* a, const double* b, int64_t n, const Red& red, int sidx, const int* gate) {
-  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(a, b, n, red, FIN_STORE, sidx, gate);
+  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(a, b, n, red, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_STORE, sidx, gate);
 }
 void vdot_alpha(hipStream_t st, const double* p, const double* q, int64_t n, const Red& red, const int* gate) {
-  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(p, q, n, red, FIN_ALPHA, 0, gate);
+  k_dot<double, double><<<vgrid(n), BS, 0, st>>>(p, q, n, red, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_ALPHA, 0, gate);
 }
 template <typename T>
 void vdot_beta(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, const int* gate) {
-  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, FIN_BETA, 0, gate);
+  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_BETA, 0, gate);
 }
 template <typename T>
 void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, int sidx, const int* gate) {
-  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, FIN_STORE, sidx, gate);
+  k_dot<double, T><<<vgrid(n), BS, 0, st>>>(r, y, n, red, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_STORE, sidx, gate);
 }
 template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
                  const Red& red, const int* gate) {
   k_pcg_update<T><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_RN2, 0, gate);
 }
 template <typename T>
 void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate) {
@@ -282,10 +295,12 @@ void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, 
 }
 void vsub_norm(hipStream_t st, const double* a, const double* b, double* out, int64_t n, const Red& red, int sidx) {
   k_sub_norm<<<vgrid(n), BS, 0, st>>>(a, b, out, n, red, sidx);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_STORE, sidx, nullptr);
 }
 void vmask_copy(hipStream_t st, const double* src, double* dst, int64_t n, int64_t nslots, int dim, int nx1,
                 const Red& red, int sidx) {
   k_mask_copy<<<vgrid(n), BS, 0, st>>>(src, dst, n, nslots, dim, nx1, red, sidx);
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_STORE, sidx, nullptr);
 }
 template <typename TD, typename TS>
 void vconvert(hipStream_t st, const TS* src, TD* dst, int64_t n, const int* gate) {

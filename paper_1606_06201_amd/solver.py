@@ -167,6 +167,20 @@ class Solver:
                    float(scale), self._ptr(out, self.m, "g"))
         return out
 
+    # ------------------------------------------------------------------ timing --
+    KERNEL_CLASSES = {"fine_jacobi": 0, "dir_apply": 1, "fine_resid": 2, "pcg_update": 3}
+
+    def profile_begin(self, kernel, max_launches=4096):
+        self._call(self.lib.ipmg_profile_begin, int(self.KERNEL_CLASSES[kernel]), int(max_launches))
+        self._prof_cap = int(max_launches)
+
+    def profile_end(self):
+        """Per-launch durations (ms) recorded since profile_begin."""
+        out = np.zeros(self._prof_cap)
+        n = C.c_int()
+        self._call(self.lib.ipmg_profile_end, out.ctypes.data_as(C.c_void_p), self._prof_cap, C.byref(n))
+        return out[: n.value].copy()
+
     # ------------------------------------------------------------ interior point --
     @staticmethod
     def ip_params(V, xbar=1.0, sigma=0.2, tau_nwt=0.1, pcg_rtol=1e-8, pcg_maxit=1000, frac=0.9,
