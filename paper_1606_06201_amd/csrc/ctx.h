@@ -66,6 +66,7 @@ struct Ctx {
   std::vector<Level> lev;      // lev[L-1] finest
   size_t tsz = 4;              // sizeof(T) of the V-cycle
   int tail_top = -1;           // highest level handled by the single-workgroup tail (-1: none)
+  bool coarse_from_x = true;   // 2D K: first coarse level evaluated from the fine densities
 
   double K0[576] = {0};        // host copy of the element matrix
   int nd = 8;                  // DOFs per element

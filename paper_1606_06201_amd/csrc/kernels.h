@@ -10,10 +10,17 @@ namespace ipmg {
 // (computed by k_element_stiffness below).  Row-major ND x ND.
 static __constant__ double cK0d[576];
 static __constant__ float cK0f[576];
+// Galerkin images G_q = W_q' K0 W_q of the unit element on the next coarser grid,
+// one 8x8 matrix per sub-element q of a coarse 2D element (row-major, q-major).
+static __constant__ double cG2d[256];
+static __constant__ float cG2f[256];
 
 template <typename T> __device__ inline T k0(int idx);
 template <> __device__ inline double k0<double>(int idx) { return cK0d[idx]; }
 template <> __device__ inline float k0<float>(int idx) { return cK0f[idx]; }
+template <typename T> __device__ inline T g2(int idx);
+template <> __device__ inline double g2<double>(int idx) { return cG2d[idx]; }
+template <> __device__ inline float g2<float>(int idx) { return cG2f[idx]; }
 
 // ------------------------------------------------------------------ reductions --
 __device__ inline double wave_sum(double v) {
@@ -29,6 +36,23 @@ __device__ inline double wave_min(double v) {
 
 __device__ inline double load_acquire(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// XCD-aware tile order.  The dispatcher deals workgroups round-robin over the
+// GPU's 8 XCDs, each with its own L2.  Mapping linear block b (XCD b % 8, local
+// index b / 8) to tile start(b % 8) + b / 8 gives every XCD a contiguous band of
+// tiles, so the halo rows a tile shares with the tile above were fetched into the
+// same L2 shortly before.  The map is a bijection on [0, nblocks).
+constexpr unsigned NXCD = 8;
+struct Tile { unsigned x, y, z; };
+__device__ inline Tile xcd_tile() {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned nb = gx * gy * gridDim.z;
+  const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned k = b % NXCD, l = b / NXCD;
+  const unsigned q = nb / NXCD, rem = nb % NXCD;
+  const unsigned t = k * q + (k < rem ? k : rem) + l;
+  return Tile{t % gx, (t / gx) % gy, t / (gx * gy)};
 }
 
 // Deterministic two-stage reductions.  Stage 1 (inside a kernel): every block
@@ -62,17 +86,41 @@ __device__ void block_partials(const double (&v)[NV], const Red& red) {
 }
 
 // Stage 2, called by all BS threads of a single block; totals valid in every thread.
+// Four independent accumulators per thread keep several loads in flight (the
+// partials come from other XCDs' L2s through memory, so latency dominates).
 template <int NV, bool IS_MIN = false>
 __device__ void sum_partials(const Red& red, unsigned nblocks, double (&tot)[NV]) {
   __shared__ double sh[NV][BS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double init = IS_MIN ? INFINITY : 0.0;
+  double acc[NV][4];
+#pragma unroll
+  for (int n = 0; n < NV; ++n)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[n][u] = init;
+  unsigned b = threadIdx.x;
+  for (; b + 3 * BS < nblocks; b += 4 * BS) {
+    double p[NV][4];
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[n][u] = red.partials[(size_t)n * MAX_PARTIALS + b + u * BS];
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[n][u] = IS_MIN ? fmin(acc[n][u], p[n][u]) : acc[n][u] + p[n][u];
+  }
+  for (; b < nblocks; b += BS) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      const double p = red.partials[(size_t)n * MAX_PARTIALS + b];
+      acc[n][0] = IS_MIN ? fmin(acc[n][0], p) : acc[n][0] + p;
+    }
+  }
 #pragma unroll
   for (int n = 0; n < NV; ++n) {
-    double s = IS_MIN ? INFINITY : 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += BS) {
-      const double p = red.partials[(size_t)n * MAX_PARTIALS + b];
-      s = IS_MIN ? fmin(s, p) : s + p;
-    }
+    double s = IS_MIN ? fmin(fmin(acc[n][0], acc[n][1]), fmin(acc[n][2], acc[n][3]))
+                      : (acc[n][0] + acc[n][1]) + (acc[n][2] + acc[n][3]);
     s = IS_MIN ? wave_min(s) : wave_sum(s);
     if (lane == 0) sh[n][wid] = s;
   }
@@ -94,7 +142,7 @@ template <int DIM, typename T>
 struct OpFineK {
   const T* x;
   int64_t m;
-  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+  __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
 #pragma unroll
@@ -106,7 +154,7 @@ struct OpFineK {
       acc[c] += xe * s;
     }
   }
-  __device__ inline void diag(int64_t e, int a, T* dg) const {
+  __device__ inline void diag(int64_t e, int, int, int, int a, T* dg) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
 #pragma unroll
@@ -125,7 +173,7 @@ struct OpFineZ {
   const T* x;
   const T* h;
   int64_t m;
-  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+  __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
     T hv = 0;
@@ -140,7 +188,7 @@ struct OpFineZ {
       acc[c] += xe * s + h[r * m + e] * hv;
     }
   }
-  __device__ inline void diag(int64_t e, int a, T* dg) const {
+  __device__ inline void diag(int64_t e, int, int, int, int a, T* dg) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
 #pragma unroll
@@ -162,7 +210,7 @@ template <int DIM, typename T>
 struct OpCoarse {
   const T* E;
   int64_t m;
-  __device__ inline void rows(int64_t e, int a, const T* ve, T* acc) const {
+  __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -173,7 +221,7 @@ struct OpCoarse {
       acc[c] += s;
     }
   }
-  __device__ inline void diag(int64_t e, int a, T* dg) const {
+  __device__ inline void diag(int64_t e, int, int, int, int a, T* dg) const {
     constexpr int ND = Geo<DIM>::ND;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -183,6 +231,52 @@ struct OpCoarse {
   }
   __device__ inline double entry(int64_t e, int r, int c) const {
     return (double)E[sym_index(r, c, Geo<DIM>::ND) * m + e];
+  }
+};
+
+// First coarse level of K(x) in 2D, evaluated from the finest densities instead
+// of stored element matrices: A_C = sum_q x_{e(C,q)} G_q over the four fine
+// elements of C (the Galerkin product of the x-scaled unit element).  Reads one
+// density per fine element instead of 36 matrix entries per coarse element.
+template <int DIM, typename T>
+struct OpCoarse2K {
+  const T* x;      // finest-level densities
+  int fnx;         // finest-level elements along x
+  __device__ inline void xs(int ei, int ej, T* xq) const {
+    const int64_t b = (int64_t)(2 * ej) * fnx + 2 * ei;
+    xq[0] = x[b];
+    xq[1] = x[b + 1];
+    xq[2] = x[b + fnx];
+    xq[3] = x[b + fnx + 1];
+  }
+  __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
+    T xq[4];
+    xs(ei, ej, xq);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T t = 0;
+#pragma unroll
+        for (int col = 0; col < 8; ++col) t += g2<T>(q * 64 + r * 8 + col) * ve[col];
+        s += xq[q] * t;
+      }
+      acc[c] += s;
+    }
+  }
+  __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
+    T xq[4];
+    xs(ei, ej, xq);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int r = a * DIM + c;
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += xq[q] * g2<T>(q * 64 + r * 8 + r);
+      dg[c] += s;
+    }
   }
 };
 
@@ -270,9 +364,9 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 #pragma unroll
         for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = vn[nb][c];
       }
-      op.rows(e, a, ve, acc);
+      op.rows(e, ei, ej, ek, a, ve, acc);
     }
-    if constexpr (DIAG) op.diag(e, a, dg);
+    if constexpr (DIAG) op.diag(e, ei, ej, ek, a, dg);
   }
 }
 
@@ -400,9 +494,10 @@ __global__ __launch_bounds__(BS) void k_level(Op op, Dims d, const T* __restrict
       pin = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
     }
   }
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
-  const int k = blockIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
   constexpr bool NEED_RED = MODE == M_POWER || MODE == M_RAYLEIGH || MODE == M_JACOBI_BETA;
   double red0 = 0.0, red1 = 0.0, bdot = 0.0;
   const T vl = (aug.b && MODE != M_JACOBI0) ? v[aug.n] : T(0);
@@ -463,9 +558,10 @@ __global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __res
                                                   const int* gate) {
   if (gate && *gate) return;
   const double beta = first ? 0.0 : red.scal[S_BETA];
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
-  const int k = blockIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
   double pq = 0.0, bdot = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   if (i < d.nx1 && j < d.ny1) {
@@ -565,9 +661,10 @@ template <int DIM, typename T, typename TS = T>
 __global__ __launch_bounds__(BS) void k_restrict(Dims f, Dims c, const TS* __restrict__ rf,
                                                  T* __restrict__ rc, int aug, const int* gate) {
   if (gate && *gate) return;
-  const int I = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int J = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
-  const int K = blockIdx.z;
+  const Tile tl = xcd_tile();
+  const int I = tl.x * 64 + (threadIdx.x & 63);
+  const int J = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int K = tl.z;
   if (aug && I == 0 && J == 0 && K == 0) rc[c.nslots] = T(rf[f.nslots]);
   if (I >= c.nx1 || J >= c.ny1) return;
   const int64_t qc = ((int64_t)K * c.ny1 + J) * c.nx1 + I;
@@ -599,9 +696,10 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(BS) void k_prolong(Dims f, Dims c, T* __restrict__ z,
                                                 const T* __restrict__ zc, int aug, const int* gate) {
   if (gate && *gate) return;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
-  const int k = blockIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
   if (aug && i == 0 && j == 0 && k == 0) z[f.nslots] += zc[c.nslots];
   if (i >= f.nx1 || j >= f.ny1 || i == 0) return;
   const int64_t q = ((int64_t)k * f.ny1 + j) * f.nx1 + i;
@@ -668,6 +766,27 @@ __global__ __launch_bounds__(BS) void k_galerkin(Op op, Dims f, Dims c, T* __res
     }
   }
   for (int col = R; col < ND; ++col) Ec[(int64_t)sym_index(R, col, ND) * c.m + C] = T(row[col]);
+}
+
+// G_q = W_q' K0 W_q for the four sub-elements q of a coarse 2D element (one
+// thread per entry), W_q the bilinear interpolation from the coarse corners to the
+// nodes of sub-element q.
+static __global__ void k_galerkin_images2d(const double* __restrict__ K0, double* __restrict__ G) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 256) return;
+  const int q = t / 64, r = (t / 8) % 8, cc = t % 8;
+  const int qx = q & 1, qy = q >> 1;
+  const int A = r / 2, ci = r % 2, B = cc / 2, cj = cc % 2;
+  double s = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    const double wa = (1.0 - fabs(0.5 * (qx + loc_x(a)) - loc_x(A))) * (1.0 - fabs(0.5 * (qy + loc_y(a)) - loc_y(A)));
+    if (wa == 0.0) continue;
+    for (int b = 0; b < 4; ++b) {
+      const double wb = (1.0 - fabs(0.5 * (qx + loc_x(b)) - loc_x(B))) * (1.0 - fabs(0.5 * (qy + loc_y(b)) - loc_y(B)));
+      s += wa * K0[(a * 2 + ci) * 8 + b * 2 + cj] * wb;
+    }
+  }
+  G[t] = s;
 }
 
 // ---------------------------------------------------------- coarsest solve --

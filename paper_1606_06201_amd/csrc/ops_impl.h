@@ -177,9 +177,10 @@ __global__ __launch_bounds__(BS) void k_ip_nodes(Dims d, const double* __restric
                                                  double V, double* __restrict__ rhs, double* __restrict__ bZ,
                                                  Red red) {
   constexpr int NN = Geo<DIM>::NN;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * (BS / 64) + (threadIdx.x >> 6);
-  const int k = blockIdx.z;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
   double acc[3] = {0, 0, 0};
   if (i < d.nx1 && j < d.ny1) {
     const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
@@ -316,6 +317,21 @@ struct OpsImpl : Ops {
     for (int t = 0; t < ND * ND; ++t) kf[t] = (float)K0[t];
     IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0d), K0, sizeof(double) * ND * ND));
     IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0f), kf, sizeof(float) * ND * ND));
+    if constexpr (DIM == 2) {
+      double *dK = nullptr, *dG = nullptr;
+      IPMG_HIP(hipMalloc((void**)&dK, sizeof(double) * 64));
+      IPMG_HIP(hipMalloc((void**)&dG, sizeof(double) * 256));
+      IPMG_HIP(hipMemcpy(dK, K0, sizeof(double) * 64, hipMemcpyHostToDevice));
+      k_galerkin_images2d<<<4, 64>>>(dK, dG);
+      double G[256];
+      float Gf[256];
+      IPMG_HIP(hipMemcpy(G, dG, sizeof(double) * 256, hipMemcpyDeviceToHost));
+      (void)hipFree(dK);
+      (void)hipFree(dG);
+      for (int t = 0; t < 256; ++t) Gf[t] = (float)G[t];
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG2d), G, sizeof(double) * 256));
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG2f), Gf, sizeof(float) * 256));
+    }
   }
 
   template <typename T, class Op>
@@ -358,6 +374,9 @@ struct OpsImpl : Ops {
       else
         launch_level<T>(c, d, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, mode, (const T*)v, (const T*)r,
                         (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
+    } else if (DIM == 2 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x) {
+      launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx}, mode, (const T*)v, (const T*)r,
+                      (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else {
       launch_level<T>(c, d, OpCoarse<DIM, T>{(const T*)c.lev[lev].E, d.m}, mode, (const T*)v, (const T*)r, (T*)out,
                       omg, aug, sidx, sidx_in, gate, dot64);

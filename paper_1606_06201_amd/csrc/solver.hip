@@ -100,17 +100,20 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   }
   const Dims& fd = c.fine();
   IPMG_REQUIRE(fd.nslots < ((int64_t)1 << 31), IPMG_E_INVALID, "grid too large");
-  // coarse tail: the lowest levels whose three vectors fit in 64 KB of LDS
-  {
-    size_t lds = 0;
-    c.tail_top = -1;
-    for (int k = 0; k < c.L && k < 12; ++k) {
-      lds += 3 * c.tsz * ((size_t)c.lev[k].d.nslots + 1);
-      if (lds > 64 * 1024 - 512 || c.lev[k].d.nnodes > 4096) break;
-      c.tail_top = k;
-    }
-    if (const char* e = std::getenv("IPMG_NO_TAIL")) {
-      if (e[0] == '1') c.tail_top = -1;
+  // Coarse tail (single-workgroup V-cycle of the lowest levels whose three vectors
+  // fit in 64 KB of LDS): opt-in with IPMG_TAIL=1.  Measured on MI355X it does not
+  // beat separate launches when the coarsest dense inverse is large (one CU reads
+  // it), so the default keeps one launch per pass.
+  if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
+  c.tail_top = -1;
+  if (const char* e = std::getenv("IPMG_TAIL")) {
+    if (e[0] == '1') {
+      size_t lds = 0;
+      for (int k = 0; k < c.L && k < 12; ++k) {
+        lds += 3 * c.tsz * ((size_t)c.lev[k].d.nslots + 1);
+        if (lds > 64 * 1024 - 512 || c.lev[k].d.nnodes > 4096) break;
+        c.tail_top = k;
+      }
     }
   }
   c.ncoarse = (int)std::min<int64_t>(c.lev[0].d.nslots + 1, (int64_t)1 << 30);

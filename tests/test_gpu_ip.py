@@ -124,3 +124,25 @@ def test_adjoint_gradient_matches_oracle(fp32):
     assert relerr(N(xt.grad), grad_o) < 1e-8
     # Euler identity on the GPU gradient: sum x_e dJ/dx_e = -J
     assert abs(float(np.dot(x, N(xt.grad))) + J_o) <= 1e-8 * abs(J_o)
+
+
+def test_z_vcycle_with_tail_matches_oracle(monkeypatch):
+    from paper_1606_06201_amd import Solver
+    nel, levels = (32, 16), 3
+    prob = _problem(nel)
+    g = prob.grid
+    st, u_slots = _state(prob)
+    Z, rhs, parts = prob.z_system(st)
+    monkeypatch.setenv("IPMG_TAIL", "1")
+    s = Solver(nel, levels, fp32=False)
+    monkeypatch.delenv("IPMG_TAIL")
+    params = s.ip_params(prob.V, prob.xbar)
+    s.ip_prepare(T(prob.f_slots), params, _gpu_state(s, st, u_slots))
+    s.mg_setup(1)
+    v = np.random.default_rng(3).standard_normal(g.nslots + 1)
+    v[:-1][g.clamped_mask()] = 0
+    free = g.free_to_slot()
+    H = mg.Hierarchy(g, Z, levels, augmented=True)
+    zc = N(s.vcycle(T(v), op=1))
+    zref = mg.vcycle(H, np.concatenate([v[:-1][free], v[-1:]]))
+    assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < 1e-9

@@ -173,3 +173,25 @@ def test_element_sensitivities_match_oracle():
     um[g.clamped_mask()] = 0
     ref = -0.5 * sens.element_products(g, K0, wm, um)
     assert relerr(gs, ref) < 1e-13
+
+
+@pytest.mark.parametrize("env", ["IPMG_TAIL", "IPMG_STORED_COARSE"])
+@pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
+                                                  ((8, 4, 4), 3, False, 1e-11)])
+def test_vcycle_alternative_paths_match_oracle(env, nel, levels, fp32, tol, monkeypatch):
+    # Opt-in execution paths (single-workgroup coarse tail; stored first coarse level)
+    # must give the same V-cycle as the default path and the oracle.
+    g, K0, x = _kproblem(nel)
+    H = mg.kstiffness_hierarchy(g, x, K0, levels)
+    r = np.random.default_rng(6).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    monkeypatch.setenv(env, "1")
+    s = _solver(nel, levels, fp32=fp32)
+    monkeypatch.delenv(env)
+    s.set_density(T(x))
+    s.mg_setup()
+    z = N(s.vcycle(T(r)))
+    assert relerr(fem.to_free(g, z), mg.vcycle(H, fem.to_free(g, r))) < tol
+    f = fem.load_vector(g, tip_load(nel))
+    u, info = s.pcg(T(f), rtol=1e-8)
+    assert info["true_relres"] <= 1e-8
