@@ -67,6 +67,8 @@ struct Ctx {
   size_t tsz = 4;              // sizeof(T) of the V-cycle
   int tail_top = -1;           // highest level handled by the single-workgroup tail (-1: none)
   bool coarse_from_x = true;   // 2D K: first coarse level evaluated from the fine densities
+  bool tiled2d = true;         // 2D level passes with register-blocked tiles
+  int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
 
   double K0[576] = {0};        // host copy of the element matrix
   int nd = 8;                  // DOFs per element

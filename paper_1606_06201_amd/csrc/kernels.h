@@ -249,22 +249,26 @@ struct OpCoarse2K {
     xq[2] = x[b + fnx];
     xq[3] = x[b + fnx + 1];
   }
+  // The sub-element loop stays rolled so that only the 16 constants of one G_q
+  // row block are live in scalar registers at a time.
   __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
-    T xq[4];
-    xs(ei, ej, xq);
+    const int64_t b = (int64_t)(2 * ej) * fnx + 2 * ei;
+    T s0 = 0, s1 = 0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      const T xq = x[b + (q >> 1) * fnx + (q & 1)];
+      const int r0 = q * 64 + (a * 2) * 8;
+      T t0 = 0, t1 = 0;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      const int r = a * DIM + c;
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T t = 0;
-#pragma unroll
-        for (int col = 0; col < 8; ++col) t += g2<T>(q * 64 + r * 8 + col) * ve[col];
-        s += xq[q] * t;
+      for (int col = 0; col < 8; ++col) {
+        t0 += g2<T>(r0 + col) * ve[col];
+        t1 += g2<T>(r0 + 8 + col) * ve[col];
       }
-      acc[c] += s;
+      s0 += xq * t0;
+      s1 += xq * t1;
     }
+    acc[0] += s0;
+    acc[1] += s1;
   }
   __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
     T xq[4];
@@ -342,7 +346,7 @@ __device__ inline void load_neighbourhood(const T* __restrict__ v, const Dims& d
 
 // acc += (A v) at node (i,j,k) and dg += diag(A) there, summing over the 2^dim
 // elements that share the node (gather form: no atomics, fixed order).
-template <int DIM, typename T, class Op, bool ROWS, bool DIAG>
+template <int DIM, typename T, class Op, bool ROWS, bool DIAG, bool INTERIOR = false>
 __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int k,
                                   const T (&vn)[Geo<DIM>::NB][DIM], T* acc, T* dg) {
   constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
@@ -350,9 +354,10 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
   for (int q = 0; q < NN; ++q) {
     const int ex = q & 1, ey = (q >> 1) & 1, ez = (q >> 2) & 1;
     const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
-    const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny &&
-                    (DIM == 2 || (ek >= 0 && ek < d.nz));
-    if (!ok) continue;
+    if constexpr (!INTERIOR) {
+      const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && (DIM == 2 || (ek >= 0 && ek < d.nz));
+      if (!ok) continue;
+    }
     const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
     const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
     if constexpr (ROWS) {
@@ -387,12 +392,19 @@ __device__ inline void finish_beta(double tot, const Red& red) {
   }
 }
 
-// Per-node part of one pass over a level (see k_level).  Accumulates the border
-// dot b.v (augmented system) in bdot and the mode's reduction terms in red0/red1.
-template <int DIM, typename T, class Op, int MODE>
-__device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int k, const T* v, const T* r, T* out,
-                                  T omega, const T* augb, T vl, double pin, const double* dot64, double& bdot,
-                                  double& red0, double& red1) {
+// Reciprocal of a Jacobi diagonal: the hardware reciprocal (about 1 ulp) in the
+// FP32 V-cycle, exact division in FP64.
+__device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double recip(double v) { return 1.0 / v; }
+
+// Per-node part of one pass over a level (see k_level), given the neighbourhood
+// vn of v (ignored for M_JACOBI0).  Accumulates the border dot b.v (augmented
+// system) in bdot and the mode's reduction terms in red0/red1.
+template <int DIM, typename T, class Op, int MODE, bool INTERIOR = false>
+__device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j, int k,
+                                       const T (&vn)[Geo<DIM>::NB][DIM], const T* r, T* out, T omega,
+                                       const T* augb, T vl, double pin, const double* dot64, double& bdot,
+                                       double& red0, double& red1) {
   constexpr bool NEED_ROWS = MODE != M_JACOBI0;
   const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
   T o[DIM];
@@ -403,10 +415,8 @@ __device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int
     T acc[DIM], dg[DIM], vc[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
-    T vn[Geo<DIM>::NB][DIM];
     if constexpr (NEED_ROWS) {
-      load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
-      node_apply<DIM, T, Op, true, true>(op, d, i, j, k, vn, acc, dg);
+      node_apply<DIM, T, Op, true, true, INTERIOR>(op, d, i, j, k, vn, acc, dg);
 #pragma unroll
       for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
       if (augb) {
@@ -418,7 +428,7 @@ __device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int
         }
       }
     } else {
-      node_apply<DIM, T, Op, false, true>(op, d, i, j, k, vn, acc, dg);
+      node_apply<DIM, T, Op, false, true, INTERIOR>(op, d, i, j, k, vn, acc, dg);
     }
     T rr[DIM];
     if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA)
@@ -427,8 +437,8 @@ __device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int
     for (int c = 0; c < DIM; ++c) {
       if constexpr (MODE == M_APPLY) o[c] = acc[c];
       if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
-      if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) / dg[c];
-      if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] / dg[c];
+      if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
+      if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
       if constexpr (MODE == M_POWER) {
         o[c] = T(pin * (double)(acc[c] / dg[c]));
         red0 += (double)o[c] * (double)o[c];
@@ -441,6 +451,16 @@ __device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int
     }
   }
   if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+}
+
+// Generic form: gathers the neighbourhood with bounds checks first.
+template <int DIM, typename T, class Op, int MODE>
+__device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int k, const T* v, const T* r, T* out,
+                                  T omega, const T* augb, T vl, double pin, const double* dot64, double& bdot,
+                                  double& red0, double& red1) {
+  T vn[Geo<DIM>::NB][DIM];
+  if constexpr (MODE != M_JACOBI0) load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
+  level_node_core<DIM, T, Op, MODE>(op, d, i, j, k, vn, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
 }
 
 // Lambda entry of a pass over an augmented level, given the border dot tot0 =
@@ -544,6 +564,75 @@ __global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const
       red.scal[sidx] = tot[0];
       if constexpr (MODE == M_RAYLEIGH) red.scal[sidx + 1] = tot[1];
     }
+  }
+}
+
+// 2D level pass with register blocking: each thread owns NJ consecutive nodes
+// along y of one column and loads the (NJ+2) x 3 window of neighbours once (rows
+// through one 32-bit offset each, x-neighbours at immediate offsets).  Tiles whose
+// nodes are all at least one node away from every boundary (and off the clamped
+// column) skip every bounds check; the others take the generic per-node path.
+// Modes as in k_level except M_POWER and M_RAYLEIGH.
+template <typename T, class Op, int MODE, int NJ>
+__global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restrict__ v,
+                                                const T* __restrict__ r, T* __restrict__ out,
+                                                const double* __restrict__ omg, Aug<T> aug, Red red,
+                                                const double* __restrict__ dot64, const int* gate) {
+  if (gate && *gate) return;
+  const T omega = omg ? T(*omg) : T(0);
+  const Tile tl = xcd_tile();
+  constexpr int RJ = (BS / 64) * NJ;               // node rows per tile
+  const int ti0 = tl.x * 64, tj0 = tl.y * RJ;
+  const int i = ti0 + (threadIdx.x & 63);
+  const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
+  const T vl = (aug.b && MODE != M_JACOBI0) ? v[aug.n] : T(0);
+  double bdot = 0.0, red0 = 0.0, red1 = 0.0;
+  const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
+  if (interior) {
+    T w[NJ + 2][3][2];
+    if constexpr (MODE != M_JACOBI0) {
+      const unsigned base = 2u * ((unsigned)(j0 - 1) * (unsigned)d.nx1 + (unsigned)i);
+      const unsigned stride = 2u * (unsigned)d.nx1;
+#pragma unroll
+      for (int rr = 0; rr < NJ + 2; ++rr) {
+        const T* p = v + (base + rr * stride);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          w[rr][cc][0] = p[2 * (cc - 1)];
+          w[rr][cc][1] = p[2 * (cc - 1) + 1];
+        }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      T vn[9][2];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          vn[nb_index<2>(dx, dy, 0)][0] = w[n + 1 + dy][dx + 1][0];
+          vn[nb_index<2>(dx, dy, 0)][1] = w[n + 1 + dy][dx + 1][1];
+        }
+      level_node_core<2, T, Op, MODE, true>(op, d, i, j0 + n, 0, vn, r, out, omega, aug.b, vl, 1.0, dot64, bdot,
+                                            red0, red1);
+    }
+  } else {
+#pragma unroll
+    for (int n = 0; n < NJ; ++n)
+      if (i < d.nx1 && j0 + n < d.ny1)
+        level_node<2, T, Op, MODE>(op, d, i, j0 + n, 0, v, r, out, omega, aug.b, vl, 1.0, dot64, bdot, red0, red1);
+  }
+  if (aug.b) {
+    if constexpr (MODE == M_JACOBI0) {
+      if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+        out[aug.n] = T((double)omega * (double)r[aug.n] / aug.c);
+    } else {
+      const double vals[3] = {bdot, red0, red1};
+      block_partials<3>(vals, red);
+    }
+  } else if constexpr (MODE == M_JACOBI_BETA) {
+    const double vals[3] = {red0, red1, 0.0};
+    block_partials<3>(vals, red);
   }
 }
 

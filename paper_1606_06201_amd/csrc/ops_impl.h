@@ -342,6 +342,31 @@ struct OpsImpl : Ops {
     const unsigned nb = g.x * g.y * g.z;
     IPMG_REQUIRE((int64_t)nb <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
     const bool fin = (aug.b && mode != M_JACOBI0) || mode == M_POWER || mode == M_RAYLEIGH || mode == M_JACOBI_BETA;
+    if constexpr (DIM == 2) {
+      // register-blocked tiles pay on large levels; small levels are latency-bound
+      // and need one node per thread
+      if (mode != M_POWER && mode != M_RAYLEIGH && c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
+        constexpr int NJ = sizeof(T) == 4 ? 4 : 2;
+        const dim3 g2((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
+        const unsigned nb2 = g2.x * g2.y;
+#define IPMG_L2D_CASE(M)                                                                                     \
+  case M:                                                                                                    \
+    k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);        \
+    if (fin)                                                                                                 \
+      k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
+                                                 sidx, sidx_in, gate);                                      \
+    return;
+        switch (mode) {
+          IPMG_L2D_CASE(M_APPLY)
+          IPMG_L2D_CASE(M_RESID)
+          IPMG_L2D_CASE(M_JACOBI)
+          IPMG_L2D_CASE(M_JACOBI0)
+          IPMG_L2D_CASE(M_JACOBI_BETA)
+          default: break;
+        }
+#undef IPMG_L2D_CASE
+      }
+    }
 #define IPMG_LEVEL_CASE(M)                                                                                   \
   case M:                                                                                                    \
     k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, dot64, gate); \

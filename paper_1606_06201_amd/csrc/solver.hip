@@ -105,6 +105,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   // beat separate launches when the coarsest dense inverse is large (one CU reads
   // it), so the default keeps one launch per pass.
   if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_TILED_MIN_NODES")) c.tiled_min_nodes = std::max<int64_t>(0, std::atoll(e));
   c.tail_top = -1;
   if (const char* e = std::getenv("IPMG_TAIL")) {
     if (e[0] == '1') {

@@ -126,16 +126,20 @@ def test_adjoint_gradient_matches_oracle(fp32):
     assert abs(float(np.dot(x, N(xt.grad))) + J_o) <= 1e-8 * abs(J_o)
 
 
-def test_z_vcycle_with_tail_matches_oracle(monkeypatch):
+@pytest.mark.parametrize("env,val,fp32", [("IPMG_TAIL", "1", False), ("IPMG_TILED_MIN_NODES", "0", False),
+                                          ("IPMG_TILED_MIN_NODES", "0", True)])
+def test_z_vcycle_alternative_paths_match_oracle(env, val, fp32, monkeypatch):
+    # Z V-cycle through the single-workgroup coarse tail, and through register-blocked
+    # 2D tiles on every level.
     from paper_1606_06201_amd import Solver
     nel, levels = (32, 16), 3
     prob = _problem(nel)
     g = prob.grid
     st, u_slots = _state(prob)
     Z, rhs, parts = prob.z_system(st)
-    monkeypatch.setenv("IPMG_TAIL", "1")
-    s = Solver(nel, levels, fp32=False)
-    monkeypatch.delenv("IPMG_TAIL")
+    monkeypatch.setenv(env, val)
+    s = Solver(nel, levels, fp32=fp32)
+    monkeypatch.delenv(env)
     params = s.ip_params(prob.V, prob.xbar)
     s.ip_prepare(T(prob.f_slots), params, _gpu_state(s, st, u_slots))
     s.mg_setup(1)
@@ -145,4 +149,4 @@ def test_z_vcycle_with_tail_matches_oracle(monkeypatch):
     H = mg.Hierarchy(g, Z, levels, augmented=True)
     zc = N(s.vcycle(T(v), op=1))
     zref = mg.vcycle(H, np.concatenate([v[:-1][free], v[-1:]]))
-    assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < 1e-9
+    assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < (2e-4 if fp32 else 1e-9)

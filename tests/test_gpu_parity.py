@@ -175,17 +175,19 @@ def test_element_sensitivities_match_oracle():
     assert relerr(gs, ref) < 1e-13
 
 
-@pytest.mark.parametrize("env", ["IPMG_TAIL", "IPMG_STORED_COARSE"])
+@pytest.mark.parametrize("env,val", [("IPMG_TAIL", "1"), ("IPMG_STORED_COARSE", "1"),
+                                     ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
                                                   ((8, 4, 4), 3, False, 1e-11)])
-def test_vcycle_alternative_paths_match_oracle(env, nel, levels, fp32, tol, monkeypatch):
-    # Opt-in execution paths (single-workgroup coarse tail; stored first coarse level)
-    # must give the same V-cycle as the default path and the oracle.
+def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol, monkeypatch):
+    # Opt-in execution paths (single-workgroup coarse tail; stored first coarse level;
+    # register-blocked 2D tiles on every level; one node per thread everywhere) must
+    # give the same V-cycle as the default path and the oracle.
     g, K0, x = _kproblem(nel)
     H = mg.kstiffness_hierarchy(g, x, K0, levels)
     r = np.random.default_rng(6).standard_normal(g.nslots)
     r[g.clamped_mask()] = 0
-    monkeypatch.setenv(env, "1")
+    monkeypatch.setenv(env, val)
     s = _solver(nel, levels, fp32=fp32)
     monkeypatch.delenv(env)
     s.set_density(T(x))
