@@ -11,7 +11,7 @@ residual) with x and f already resident in HBM.
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
 
 Prints one JSON line.  value = free DOFs x PCG iterations / wall time of the
-timed steps (setup included).
+timed steps (setup included); pcg_loop_dof_iters_per_s leaves the setup out.
 """
 import argparse
 import json
@@ -24,28 +24,78 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Sources whose text defines the timed kernels; the committed HBM counter summary
+# records their hash and is used only while it still matches.
+KERNEL_SOURCES = ["paper_1606_06201_amd/csrc/kernels.h", "paper_1606_06201_amd/csrc/ops_impl.h",
+                  "paper_1606_06201_amd/csrc/common.h", "paper_1606_06201_amd/csrc/vec.hip"]
+
+KERNEL_NAMES = {
+    "fine_jacobi": "k_level2d<float, OpFineK<2,float>, M_JACOBI, 4>: finest-level damped-Jacobi sweep",
+    "fine_jacobi0": "k_level2d<float, OpFineK<2,float>, M_JACOBI0, 4>: first sweep from a zero iterate",
+    "fine_jacobi_beta": "k_level2d<float, OpFineK<2,float>, M_JACOBI_BETA, 4>: last sweep + fused PCG ratio",
+    "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
+    "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
+                  "Galerkin element matrices formed from the fine densities on the fly",
+    "dir_apply": "k_dir_apply<2, float, OpFineK<2,double>>: p = -y + beta p, q = K p (FP64), p'q",
+    "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
+}
 
 
-def fine_kernel_bytes(nel, fp32, kind):
-    """Algorithmic HBM bytes of one launch of a finest-level kernel (2D):
-    each input / output vector once, one density per element."""
+def class_bytes(nel, fp32, kind):
+    """Algorithmic HBM bytes of one launch of a kernel class (2D): every input and
+    output vector once, one density per element of the grid it is read on."""
     nx, ny = nel
-    nodes = (nx + 1) * (ny + 1)
+    N = (nx + 1) * (ny + 1)                 # finest-level nodes (2 DOF slots each)
     m = nx * ny
-    w = 4 if fp32 else 8
-    if kind == "fine_jacobi":      # read z, r; write z'; read x
-        return 3 * 2 * w * nodes + w * m
-    if kind == "fine_resid":       # read z, r; write t; read x
-        return 3 * 2 * w * nodes + w * m
-    if kind == "dir_apply":        # read y (V-cycle precision), p_old; write p, q (FP64); read x
-        return 2 * nodes * (w + 3 * 8) + 8 * m
-    if kind == "pcg_update":       # read z, r, p, q; write z, r (FP64); write r (FP32)
-        n = 2 * nodes
-        return n * (6 * 8 + (4 if fp32 else 8))
+    Nc = (nx // 2 + 1) * (ny // 2 + 1)      # first coarse level nodes
+    w = 4 if fp32 else 8                    # V-cycle precision
+    if kind in ("fine_jacobi", "fine_resid"):   # read z, r; write z' (or t); read x
+        return 3 * 2 * w * N + w * m
+    if kind == "fine_jacobi0":                  # read r; write z; read x
+        return 2 * 2 * w * N + w * m
+    if kind == "fine_jacobi_beta":              # fine_jacobi + read FP64 r for the ratio
+        return 3 * 2 * w * N + w * m + 2 * 8 * N
+    if kind == "sub_jacobi":                    # read z, r; write z'; read the fine x (4 per coarse element)
+        return 3 * 2 * w * Nc + w * m
+    if kind == "dir_apply":                     # read y, p_old; write p, q (FP64); read x (FP64)
+        return 2 * N * (w + 3 * 8) + 8 * m
+    if kind == "pcg_update":                    # read z, r, p, q; write z, r (FP64); write r (V-cycle)
+        return 2 * N * (6 * 8 + w)
     raise ValueError(kind)
 
 
-def cpu_baseline(nel, levels, x, f, iters=5):
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload, kind):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):])
+    if rec is None:
+        return None, "no counter summary"
+    if rec.get("source_hash") != source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    k = rec.get("kernels", {}).get(kind)
+    if k is None:
+        return None, "kernel not in the counter summary"
+    return k["bytes_per_launch"], "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, copy-calibrated"
+
+
+def cpu_baseline(nel, levels, x, f, iters=40):
     """The oracle's FP64 MG-PCG on the same input, bounded to `iters` iterations
     after its hierarchy setup (scipy sparse kernels: one host core)."""
     import numpy as np
@@ -82,7 +132,8 @@ def main():
     ap.add_argument("--workload", default="thr2048x1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--roofline-kernel", default="fine_jacobi")
+    ap.add_argument("--roofline-kernel", default="auto",
+                    help="kernel class for the roofline; auto = largest total time in an untimed profiled solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -125,7 +176,7 @@ def main():
     def run(s, steps, profile=None):
         infos = []
         if profile:
-            s.profile_begin(profile, max_launches=8192)
+            s.profile_begin(profile, max_launches=20000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -137,14 +188,34 @@ def main():
         durs = s.profile_end() if profile else None
         return t1 - t0, infos, u, durs
 
-    # warmup
-    for _ in range(args.warmup):
-        run(s32, 1)
+    def avg_ms(d):
+        # launches skipped on device after convergence take near-zero time
+        d = np.asarray(d)
+        if len(d) == 0:
+            return float("nan"), 0
+        ran = d[d > 0.5 * float(np.median(d))]
+        return float(ran.mean()), int(len(ran))
+
+    # warmup; the first warmup solve times every kernel class (untimed)
+    classes = {}
+    for wi in range(max(args.warmup, 1)):
+        _, inf_w, _, dw = run(s32, 1, profile=list(KERNEL_NAMES) if wi == 0 else None)
+        if wi == 0:
+            for k, d in dw.items():
+                a, nrun = avg_ms(d)
+                b = class_bytes(nel, True, k)
+                classes[k] = {"avg_launch_us": 1000.0 * a, "launches_per_step": nrun,
+                              "ms_per_step": a * nrun, "bytes_per_launch": b,
+                              "GB_per_s": b / (a * 1e-3) / 1e9, "frac_hbm": b / (a * 1e-3) / 1e9 / HBM_PEAK_GBS}
     print("[bench] mixed warmup done", file=sys.stderr, flush=True)
-    t_mixed, inf_mixed, u_mixed, durs = run(s32, args.steps, profile=args.roofline_kernel)
+    kind = args.roofline_kernel
+    if kind == "auto":
+        kind = max(classes, key=lambda k: classes[k]["ms_per_step"])
+    t_mixed, inf_mixed, u_mixed, durs = run(s32, args.steps, profile=kind)
     iters = [i["iters"] for i in inf_mixed]
     print(f"[bench] mixed timed: {t_mixed:.3f}s, iterations {iters}", file=sys.stderr, flush=True)
     value = n_free * sum(iters) / t_mixed
+    setup_s = sum(i["setup_ms"] for i in inf_mixed) / 1000.0
     c_mixed = float(torch.dot(f, u_mixed))
 
     fp64 = None
@@ -166,20 +237,17 @@ def main():
         }
 
     # roofline of the dominant kernel: algorithmic bytes / average launch duration
-    durs = np.asarray(durs)
-    med = float(np.median(durs)) if len(durs) else 0.0
-    ran = durs[durs > 0.5 * med] if len(durs) else durs      # drop launches skipped after convergence
-    avg_ms = float(ran.mean()) if len(ran) else float("nan")
-    nbytes = fine_kernel_bytes(nel, True, args.roofline_kernel)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    # (HIP events around each launch on the solver's stream, timed region)
+    a_ms, n_ran = avg_ms(durs.get(kind, []))
+    nbytes = class_bytes(nel, True, kind)
+    achieved = nbytes / (a_ms * 1e-3) / 1e9
+    traffic, traffic_src = committed_traffic(args.workload, kind)
     roofline = {
-        "kernel": {"fine_jacobi": "k_level<2,float,OpFineK,M_JACOBI> (finest-level damped-Jacobi sweep)",
-                   "fine_resid": "k_level<2,float,OpFineK,M_RESID>",
-                   "dir_apply": "k_dir_apply<2,float,OpFineK<double>> (p = -y + beta p, q = K p, p'q)",
-                   "pcg_update": "k_pcg_update<float>"}[args.roofline_kernel],
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-        "bytes_per_launch": nbytes, "avg_launch_us": avg_ms * 1000.0, "launches_timed": int(len(ran)),
+        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "kernel": KERNEL_NAMES[kind], "class": kind, "bytes_per_launch": nbytes,
+        "avg_launch_us": a_ms * 1000.0, "launches_timed": n_ran, "traffic_source": traffic_src,
+        "dominant_by_total_time": max(classes, key=lambda k: classes[k]["ms_per_step"]) if classes else None,
     }
 
     cpu = None
@@ -210,7 +278,9 @@ def main():
         "mixed_speedup_vs_fp64": (fp64["time_to_1e-8_ms"] / (1000.0 * t_mixed / args.steps)) if fp64 else None,
         "compliance_rel_diff_mixed_vs_fp64": (abs(c_mixed - fp64["compliance"]) / abs(fp64["compliance"]))
         if fp64 else None,
+        "pcg_loop_dof_iters_per_s": n_free * sum(iters) / (t_mixed - setup_s),
         "roofline": roofline,
+        "kernel_classes": classes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

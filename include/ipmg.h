@@ -196,18 +196,25 @@ int ipmg_ip_prepare(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm,
 int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
                  ipmg_ip_info* info);
 
-/* Kernel timing for roofline measurements.  Between begin and end, every launch of
- * one kernel class is bracketed by a pair of HIP events on the context's stream:
- *   0: damped-Jacobi sweep on the finest level (V-cycle precision)
- *   1: FP64 operator apply on the finest level (PCG q = A p)
+/* Kernel timing for roofline measurements.  Between begin and end, the launch of
+ * the main kernel of every selected class (bit k of class_mask selects class k) is
+ * bracketed by a pair of HIP events on the context's stream; the one-block
+ * finalize kernels that follow some of them are not inside the bracket:
+ *   0: damped-Jacobi sweep on the finest level from a nonzero iterate (V-cycle precision)
+ *   1: FP64 finest-level apply of the PCG direction (p = -y + beta p, q = A p, p'q)
  *   2: residual pass on the finest level (V-cycle precision)
  *   3: fused PCG update (z += alpha p, r += alpha q, ||r||^2)
+ *   4: damped-Jacobi sweep on the first coarse level from a nonzero iterate
+ *   5: first damped-Jacobi sweep on the finest level (zero iterate)
+ *   6: last post-smoothing sweep on the finest level with the fused PCG ratio
  * Launches skipped on device after convergence are recorded too (with near-zero
  * duration).  max_launches: event pairs to keep (further launches are not timed).
- * durations_ms: [host] capacity entries, each launch's duration; launches: [host]
- * number recorded.  Both calls synchronise the stream. */
-int ipmg_profile_begin(ipmg_ctx* ctx, int kernel_class, int max_launches);
-int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int capacity, int* launches);
+ * durations_ms: [host] capacity entries, each launch's duration; classes: [host,
+ * nullable] capacity entries, each launch's class; launches: [host] number
+ * recorded.  Both calls synchronise the stream.  IPMG_E_INVALID for an empty or
+ * unknown mask or max_launches outside [1, 65536]. */
+int ipmg_profile_begin(ipmg_ctx* ctx, unsigned class_mask, int max_launches);
+int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int* classes, int capacity, int* launches);
 
 #ifdef __cplusplus
 }

@@ -65,8 +65,8 @@ SIGNATURES = {
                                   C.c_void_p]),
     "ipmg_ip_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.POINTER(IPState),
                                C.POINTER(IPInfo)]),
-    "ipmg_profile_begin": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
-    "ipmg_profile_end": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "ipmg_profile_begin": (C.c_int, [C.c_void_p, C.c_uint, C.c_int]),
+    "ipmg_profile_end": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
 }
 
 _lib = None

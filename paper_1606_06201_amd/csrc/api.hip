@@ -198,8 +198,9 @@ int ipmg_element_sens(ipmg_ctx* ctx, const double* w, const double* u, double sc
   });
 }
 
-int ipmg_profile_begin(ipmg_ctx* ctx, int kernel_class, int max_launches) {
-  if (kernel_class < 0 || kernel_class > 3 || max_launches < 1 || max_launches > (1 << 16)) return IPMG_E_INVALID;
+int ipmg_profile_begin(ipmg_ctx* ctx, unsigned class_mask, int max_launches) {
+  if (class_mask == 0 || class_mask >= (1u << ipmg::PC_COUNT) || max_launches < 1 || max_launches > (1 << 16))
+    return IPMG_E_INVALID;
   return guard(ctx, [&](Ctx& c) {
     ipmg::sync(c);
     while ((int)c.prof_ev.size() < 2 * max_launches) {
@@ -207,13 +208,14 @@ int ipmg_profile_begin(ipmg_ctx* ctx, int kernel_class, int max_launches) {
       IPMG_HIP(hipEventCreate(&e));
       c.prof_ev.push_back(e);
     }
-    c.prof_class = kernel_class;
+    c.prof_cls.assign(max_launches, -1);
+    c.prof_mask = class_mask;
     c.prof_used = 0;
     return IPMG_OK;
   });
 }
 
-int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int capacity, int* launches) {
+int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int* classes, int capacity, int* launches) {
   if (!launches || (capacity > 0 && !durations_ms)) return IPMG_E_INVALID;
   return guard(ctx, [&](Ctx& c) {
     ipmg::sync(c);
@@ -222,9 +224,10 @@ int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int capacity, int* lau
       float ms = 0.0f;
       IPMG_HIP(hipEventElapsedTime(&ms, c.prof_ev[2 * i], c.prof_ev[2 * i + 1]));
       durations_ms[i] = ms;
+      if (classes) classes[i] = c.prof_cls[i];
     }
     *launches = n;
-    c.prof_class = -1;
+    c.prof_mask = 0;
     c.prof_used = 0;
     return IPMG_OK;
   });

@@ -109,25 +109,48 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 
-  // kernel timing (ipmg_profile_*): HIP event pairs around every launch of one class
-  int prof_class = -1;
+  // kernel timing (ipmg_profile_*): HIP event pairs around every launch of the
+  // selected classes; prof_tag is the class of the next level pass
+  unsigned prof_mask = 0;
+  int prof_tag = -1;
   int prof_used = 0;
   std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_cls;
 
   const Dims& fine() const { return lev[L - 1].d; }
 };
 
-// Kernel classes timed by ipmg_profile_begin.
-enum ProfClass { PC_FINE_JACOBI = 0, PC_FINE_APPLY64 = 1, PC_FINE_RESID = 2, PC_PCG_UPDATE = 3 };
+// Kernel classes timed by ipmg_profile_begin (bit k of the mask selects class k).
+enum ProfClass {
+  PC_FINE_JACOBI = 0,       // finest level, damped-Jacobi sweep from a nonzero iterate
+  PC_DIR_APPLY = 1,         // FP64 finest-level apply of the PCG direction
+  PC_FINE_RESID = 2,        // finest level, residual pass
+  PC_PCG_UPDATE = 3,        // fused PCG vector update
+  PC_SUB_JACOBI = 4,        // first coarse level, damped-Jacobi sweep from a nonzero iterate
+  PC_FINE_JACOBI0 = 5,      // finest level, first sweep from a zero iterate
+  PC_FINE_JACOBI_BETA = 6,  // finest level, last sweep with the fused PCG ratio
+  PC_COUNT = 7
+};
 
+// Sets the class of the level passes enqueued in its scope.
+struct ProfTag {
+  Ctx& c;
+  int old;
+  ProfTag(Ctx& cc, int cls) : c(cc), old(cc.prof_tag) { c.prof_tag = cls; }
+  ~ProfTag() { c.prof_tag = old; }
+};
+
+// Brackets the launch of one main kernel with a pair of events when its class is
+// being timed (finalize kernels stay outside the bracket).
 struct ProfScope {
   Ctx& c;
   bool on;
   int slot;
   ProfScope(Ctx& cc, int cls) : c(cc), on(false), slot(0) {
-    if (c.prof_class == cls && 2 * (c.prof_used + 1) <= (int)c.prof_ev.size()) {
+    if (cls >= 0 && ((c.prof_mask >> cls) & 1u) && 2 * (c.prof_used + 1) <= (int)c.prof_ev.size()) {
       on = true;
       slot = c.prof_used++;
+      c.prof_cls[slot] = cls;
       (void)hipEventRecord(c.prof_ev[2 * slot], c.stream);
     }
   }

@@ -351,7 +351,10 @@ struct OpsImpl : Ops {
         const unsigned nb2 = g2.x * g2.y;
 #define IPMG_L2D_CASE(M)                                                                                     \
   case M:                                                                                                    \
-    k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);        \
+    {                                                                                                        \
+      ProfScope ps_(c, c.prof_tag);                                                                          \
+      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);      \
+    }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
                                                  sidx, sidx_in, gate);                                      \
@@ -369,7 +372,10 @@ struct OpsImpl : Ops {
     }
 #define IPMG_LEVEL_CASE(M)                                                                                   \
   case M:                                                                                                    \
-    k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, dot64, gate); \
+    {                                                                                                        \
+      ProfScope ps_(c, c.prof_tag);                                                                          \
+      k_level<DIM, T, Op, M><<<g, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, sidx, sidx_in, dot64, gate); \
+    }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb, \
                                                  sidx, sidx_in, gate);                                      \
@@ -419,7 +425,10 @@ struct OpsImpl : Ops {
                         Aug<double> aug, int first, const int* gate) {
     const Dims& d = c.fine();
     const dim3 g = node_grid(d);
-    k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+    {
+      ProfScope ps(c, PC_DIR_APPLY);
+      k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+    }
     k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
                                           g.x * g.y * g.z, gate);
   }

@@ -204,6 +204,7 @@ void ctx_free(Ctx& c) {
   c.hscal = nullptr; c.hflags = nullptr;
   for (auto e : c.prof_ev) (void)hipEventDestroy(e);
   c.prof_ev.clear();
+  c.prof_cls.clear();
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.ev1) (void)hipEventDestroy(c.ev1);
   c.ev0 = c.ev1 = nullptr;
@@ -307,22 +308,26 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   void* nxt = l.z2;
   const double* w = c.omega_dev + k;
   const bool fine = k == c.L - 1;
-  c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);       // pre-smoothing
+  const int jac = fine ? PC_FINE_JACOBI : (k == c.L - 2 ? PC_SUB_JACOBI : -1);
+  {
+    ProfTag pt(c, fine ? PC_FINE_JACOBI0 : -1);
+    c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);     // pre-smoothing
+  }
   for (int s = 1; s < c.desc.nu_pre; ++s) {
-    ProfScope ps(c, fine ? PC_FINE_JACOBI : -2);
+    ProfTag pt(c, jac);
     c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
     std::swap(cur, nxt);
   }
   {
-    ProfScope ps(c, fine ? PC_FINE_RESID : -2);
+    ProfTag pt(c, fine ? PC_FINE_RESID : -1);
     c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);     // restricted residual
   }
   c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
   void* vc = vcycle_level(c, op, k - 1, gate, nullptr);                       // coarse correction
   c.ops->prolong_from(c, k, cur, vc, aug, gate);                              // solution update
   for (int s = 0; s < c.desc.nu_post; ++s) {                                  // post-smoothing
-    ProfScope ps(c, fine ? PC_FINE_JACOBI : -2);
     const bool last = beta64 && s == c.desc.nu_post - 1;
+    ProfTag pt(c, last ? (fine ? PC_FINE_JACOBI_BETA : -1) : jac);
     c.ops->level(c, k, op, last ? M_JACOBI_BETA : M_JACOBI, cur, l.r, nxt, w, 0, -1, gate, last ? beta64 : nullptr);
     std::swap(cur, nxt);
   }
@@ -351,10 +356,7 @@ void vcycle64(Ctx& c, int op, const double* r, double* z) {
 //   y = M r with beta = r'y / rho fused into the last smoothing sweep.
 // `first` selects beta = 0 (first step after a (re)start).
 static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first) {
-  {
-    ProfScope ps(c, PC_FINE_APPLY64);
-    c.ops->dir_apply(c, op, c.yT, c.pp, c.pp2, c.pq, first, gate);
-  }
+  c.ops->dir_apply(c, op, c.yT, c.pp, c.pp2, c.pq, first, gate);
   std::swap(c.pp, c.pp2);                                               // c.pp holds the new p
   void* rT = c.lev[c.L - 1].r;
   {
@@ -364,6 +366,7 @@ static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first)
     else
       vpcg_update<double>(c.stream, c.pu, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
   }
+  vpcg_update_fin(c.stream, n, c.red, gate);
   const bool fused_beta = c.desc.nu_post >= 1 && c.tail_top < c.L - 1;
   void* y = vcycle_level(c, op, c.L - 1, gate, fused_beta ? c.pr : nullptr);
   if (!fused_beta) {

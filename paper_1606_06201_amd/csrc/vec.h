@@ -12,7 +12,8 @@ template <typename T>
 void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, int sidx, const int* gate);
 template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
-                 const Red& red, const int* gate);
+                 const Red& red, const int* gate);   // block partials of ||r||^2 ...
+void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate);   // ... summed, done flag
 template <typename T>
 void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate);
 void vsub_norm(hipStream_t st, const double* a, const double* b, double* out, int64_t n, const Red& red, int sidx);

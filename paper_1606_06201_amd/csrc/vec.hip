@@ -287,6 +287,8 @@ template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
                  const Red& red, const int* gate) {
   k_pcg_update<T><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+}
+void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate) {
   k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_RN2, 0, gate);
 }
 template <typename T>

@@ -168,18 +168,31 @@ class Solver:
         return out
 
     # ------------------------------------------------------------------ timing --
-    KERNEL_CLASSES = {"fine_jacobi": 0, "dir_apply": 1, "fine_resid": 2, "pcg_update": 3}
+    KERNEL_CLASSES = {"fine_jacobi": 0, "dir_apply": 1, "fine_resid": 2, "pcg_update": 3, "sub_jacobi": 4,
+                      "fine_jacobi0": 5, "fine_jacobi_beta": 6}
 
-    def profile_begin(self, kernel, max_launches=4096):
-        self._call(self.lib.ipmg_profile_begin, int(self.KERNEL_CLASSES[kernel]), int(max_launches))
+    def profile_begin(self, kernels, max_launches=4096):
+        """Time every launch of the named kernel classes (a name or a list)."""
+        names = [kernels] if isinstance(kernels, str) else list(kernels)
+        mask = 0
+        for k in names:
+            mask |= 1 << self.KERNEL_CLASSES[k]
+        self._call(self.lib.ipmg_profile_begin, mask, int(max_launches))
         self._prof_cap = int(max_launches)
 
     def profile_end(self):
-        """Per-launch durations (ms) recorded since profile_begin."""
+        """Per-launch durations (ms) recorded since profile_begin, grouped by class
+        name: {name: array of durations in launch order}."""
         out = np.zeros(self._prof_cap)
+        cls = np.full(self._prof_cap, -1, dtype=np.int32)
         n = C.c_int()
-        self._call(self.lib.ipmg_profile_end, out.ctypes.data_as(C.c_void_p), self._prof_cap, C.byref(n))
-        return out[: n.value].copy()
+        self._call(self.lib.ipmg_profile_end, out.ctypes.data_as(C.c_void_p), cls.ctypes.data_as(C.c_void_p),
+                   self._prof_cap, C.byref(n))
+        inv = {v: k for k, v in self.KERNEL_CLASSES.items()}
+        res = {}
+        for k in np.unique(cls[: n.value]):
+            res[inv[int(k)]] = out[: n.value][cls[: n.value] == k].copy()
+        return res
 
     # ------------------------------------------------------------ interior point --
     @staticmethod
