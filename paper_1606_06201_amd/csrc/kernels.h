@@ -19,6 +19,31 @@ template <typename T> __device__ inline T k0(int idx);
 template <> __device__ inline double k0<double>(int idx) { return cK0d[idx]; }
 template <> __device__ inline float k0<float>(int idx) { return cK0f[idx]; }
 template <typename T> __device__ inline T g2(int idx);
+// Square-element symmetry of the 2D Q1 element matrix (isotropic material, nodes
+// counter-clockwise, DOFs x/y interleaved): every entry is a signed copy of an
+// entry of the first row, K0[r][c] = sign * K0[0][t] with kSq2d[8r+c] = sign*(t+1).
+// Only six distinct values occur, so the 2D kernels keep six constants live instead
+// of 64.  Checked against the computed element matrix at set-up.
+constexpr signed char kSq2d[64] = { 1,  2,  3,  4,  5, -2,  7, -4,
+                                   2,  1, -4,  7, -2,  5,  4,  3,
+                                   3, -4,  1, -2,  7,  4,  5,  2,
+                                   4,  7, -2,  1, -4,  3,  2,  5,
+                                   5, -2,  7, -4,  1,  2,  3,  4,
+                                  -2,  5,  4,  3,  2,  1, -4,  7,
+                                   7,  4,  5,  2,  3, -4,  1, -2,
+                                  -4,  3,  2,  5,  4,  7, -2,  1};
+template <typename T>
+__device__ inline T k0sq(int r, int c) {
+  const int t = kSq2d[r * 8 + c];
+  return t > 0 ? k0<T>(t - 1) : -k0<T>(-t - 1);
+}
+// Entry (r, c) of the element matrix of the dimension.
+template <int DIM, typename T>
+__device__ inline T k0rc(int r, int c) {
+  if constexpr (DIM == 2) return k0sq<T>(r, c);
+  else return k0<T>(r * Geo<DIM>::ND + c);
+}
+
 template <> __device__ inline double g2<double>(int idx) { return cG2d[idx]; }
 template <> __device__ inline float g2<float>(int idx) { return cG2f[idx]; }
 
@@ -150,7 +175,7 @@ struct OpFineK {
       const int r = a * DIM + c;
       T s = 0;
 #pragma unroll
-      for (int col = 0; col < ND; ++col) s += k0<T>(r * ND + col) * ve[col];
+      for (int col = 0; col < ND; ++col) s += k0rc<DIM, T>(r, col) * ve[col];
       acc[c] += xe * s;
     }
   }
@@ -158,7 +183,7 @@ struct OpFineK {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) dg[c] += xe * k0<T>((a * DIM + c) * ND + a * DIM + c);
+    for (int c = 0; c < DIM; ++c) dg[c] += xe * k0rc<DIM, T>(a * DIM + c, a * DIM + c);
   }
   __device__ inline double entry(int64_t e, int r, int c) const {
     return (double)x[e] * (double)k0<T>(r * Geo<DIM>::ND + c);
@@ -184,7 +209,7 @@ struct OpFineZ {
       const int r = a * DIM + c;
       T s = 0;
 #pragma unroll
-      for (int col = 0; col < ND; ++col) s += k0<T>(r * ND + col) * ve[col];
+      for (int col = 0; col < ND; ++col) s += k0rc<DIM, T>(r, col) * ve[col];
       acc[c] += xe * s + h[r * m + e] * hv;
     }
   }
@@ -195,7 +220,7 @@ struct OpFineZ {
     for (int c = 0; c < DIM; ++c) {
       const int r = a * DIM + c;
       const T hr = h[r * m + e];
-      dg[c] += xe * k0<T>(r * ND + r) + hr * hr;
+      dg[c] += xe * k0rc<DIM, T>(r, r) + hr * hr;
     }
   }
   __device__ inline double entry(int64_t e, int r, int c) const {
@@ -397,9 +422,51 @@ __device__ inline void finish_beta(double tot, const Red& red) {
 __device__ inline float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ inline double recip(double v) { return 1.0 / v; }
 
+// Output of one node of a pass over a level (see k_level), given its row sums
+// acc = (A v)_node (without the border term), the diagonal dg and the centre
+// value vc (unused for M_JACOBI0).  Adds the border term b*v_lambda and
+// accumulates the border dot b.v (augmented system) in bdot and the mode's
+// reduction terms in red0/red1.
+template <int DIM, typename T, int MODE>
+__device__ inline void level_node_finish(int64_t q, T* acc, const T* dg, const T* vc, const T* r, T* out,
+                                         T omega, const T* augb, T vl, double pin, const double* dot64,
+                                         double& bdot, double& red0, double& red1) {
+  constexpr bool NEED_ROWS = MODE != M_JACOBI0;
+  T o[DIM];
+  if constexpr (NEED_ROWS) {
+    if (augb) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        const T bc = augb[q * DIM + c];
+        acc[c] += bc * vl;
+        bdot += (double)bc * (double)vc[c];
+      }
+    }
+  }
+  T rr[DIM];
+  if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA)
+    load_node<DIM, T>(r, q, rr);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if constexpr (MODE == M_APPLY) o[c] = acc[c];
+    if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
+    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
+    if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
+    if constexpr (MODE == M_POWER) {
+      o[c] = T(pin * (double)(acc[c] / dg[c]));
+      red0 += (double)o[c] * (double)o[c];
+    }
+    if constexpr (MODE == M_RAYLEIGH) {
+      red0 += (double)vc[c] * (double)acc[c];
+      red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
+    }
+    if constexpr (MODE == M_JACOBI_BETA) red0 += dot64[q * DIM + c] * (double)o[c];
+  }
+  if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+}
+
 // Per-node part of one pass over a level (see k_level), given the neighbourhood
-// vn of v (ignored for M_JACOBI0).  Accumulates the border dot b.v (augmented
-// system) in bdot and the mode's reduction terms in red0/red1.
+// vn of v (ignored for M_JACOBI0).
 template <int DIM, typename T, class Op, int MODE, bool INTERIOR = false>
 __device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j, int k,
                                        const T (&vn)[Geo<DIM>::NB][DIM], const T* r, T* out, T omega,
@@ -407,50 +474,22 @@ __device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j
                                        double& red0, double& red1) {
   constexpr bool NEED_ROWS = MODE != M_JACOBI0;
   const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
-  T o[DIM];
   if (i == 0) {
+    T o[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) o[c] = T(0);
-  } else {
-    T acc[DIM], dg[DIM], vc[DIM];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
-    if constexpr (NEED_ROWS) {
-      node_apply<DIM, T, Op, true, true, INTERIOR>(op, d, i, j, k, vn, acc, dg);
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
-      if (augb) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          const T bc = augb[q * DIM + c];
-          acc[c] += bc * vl;
-          bdot += (double)bc * (double)vc[c];
-        }
-      }
-    } else {
-      node_apply<DIM, T, Op, false, true, INTERIOR>(op, d, i, j, k, vn, acc, dg);
-    }
-    T rr[DIM];
-    if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA)
-      load_node<DIM, T>(r, q, rr);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      if constexpr (MODE == M_APPLY) o[c] = acc[c];
-      if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
-      if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
-      if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
-      if constexpr (MODE == M_POWER) {
-        o[c] = T(pin * (double)(acc[c] / dg[c]));
-        red0 += (double)o[c] * (double)o[c];
-      }
-      if constexpr (MODE == M_RAYLEIGH) {
-        red0 += (double)vc[c] * (double)acc[c];
-        red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
-      }
-      if constexpr (MODE == M_JACOBI_BETA) red0 += dot64[q * DIM + c] * (double)o[c];
-    }
+    if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+    return;
   }
-  if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+  T acc[DIM], dg[DIM], vc[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) { acc[c] = T(0); dg[c] = T(0); vc[c] = T(0); }
+  node_apply<DIM, T, Op, NEED_ROWS, true, INTERIOR>(op, d, i, j, k, vn, acc, dg);
+  if constexpr (NEED_ROWS) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) vc[c] = vn[nb_index<DIM>(0, 0, 0)][c];
+  }
+  level_node_finish<DIM, T, MODE>(q, acc, dg, vc, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
 }
 
 // Generic form: gathers the neighbourhood with bounds checks first.
@@ -567,11 +606,167 @@ __global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const
   }
 }
 
+// Row sums (A v) and diagonals of the NJ nodes (i, j0..j0+NJ-1) of one thread of
+// the tiled 2D pass.  w holds v on the nodes (i-1..i+1, j0-1..j0+NJ), zero outside
+// the grid and on clamped nodes: w[rr][cc] is node (i-1+cc, j0-1+rr).  The thread's
+// nodes touch the elements (i-1+ec, j0-1+er), er = 0..NJ, ec = 0..1; node n is
+// corner loc_index(1-ex, 1-ey) of element (ec, er) = (ex, n+ey).  EDGE: some of
+// these nodes or elements may lie outside the grid (elements outside contribute
+// nothing); otherwise all of them are inside.
+template <typename T, class Op, bool ROWS, int NJ>
+struct TileApply {
+  template <bool EDGE>
+  __device__ static inline void run(const Op& op, const Dims& d, int i, int j0, const T (&w)[NJ + 2][3][2],
+                                    T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      T vn[9][2];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          vn[nb_index<2>(dx, dy, 0)][0] = ROWS ? w[n + 1 + dy][dx + 1][0] : T(0);
+          vn[nb_index<2>(dx, dy, 0)][1] = ROWS ? w[n + 1 + dy][dx + 1][1] : T(0);
+        }
+      acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
+      node_apply<2, T, Op, ROWS, true, !EDGE>(op, d, i, j0 + n, 0, vn, acc[n], dg[n]);
+    }
+  }
+};
+
+// Element (ei, ej) of a 2D level lies inside the grid.
+__device__ inline bool elem_in(const Dims& d, int ei, int ej) { return ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny; }
+
+// Finest level: A_e = x_e K0.  The densities of the 2(NJ+1) elements are loaded up
+// front (zero outside the grid).
+template <typename T, bool ROWS, int NJ>
+struct TileApply<T, OpFineK<2, T>, ROWS, NJ> {
+  template <bool EDGE>
+  __device__ static inline void run(const OpFineK<2, T>& op, const Dims& d, int i, int j0,
+                                    const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+    T xe[NJ + 1][2];
+#pragma unroll
+    for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+      for (int ec = 0; ec < 2; ++ec) {
+        const int ei = i - 1 + ec, ej = j0 - 1 + er;
+        if (!EDGE || elem_in(d, ei, ej)) xe[er][ec] = op.x[(int64_t)ej * d.nx + ei];
+        else xe[er][ec] = T(0);
+      }
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+          const int er = n + ey, ec = ex;
+          const int a = loc_index(1 - ex, 1 - ey, 0);
+          const T x = xe[er][ec];
+          if constexpr (ROWS) {
+            const T ve[8] = {w[er][ec][0],         w[er][ec][1],         w[er][ec + 1][0], w[er][ec + 1][1],
+                             w[er + 1][ec + 1][0], w[er + 1][ec + 1][1], w[er + 1][ec][0], w[er + 1][ec][1]};
+            T t0 = 0, t1 = 0;
+#pragma unroll
+            for (int col = 0; col < 8; ++col) {
+              t0 += k0sq<T>(2 * a, col) * ve[col];
+              t1 += k0sq<T>(2 * a + 1, col) * ve[col];
+            }
+            acc[n][0] += x * t0;
+            acc[n][1] += x * t1;
+          }
+          dg[n][0] += x * k0sq<T>(2 * a, 2 * a);
+          dg[n][1] += x * k0sq<T>(2 * a + 1, 2 * a + 1);
+        }
+    }
+  }
+};
+
+// First coarse level formed on the fly: the element matrix of a coarse element is
+// sum_q x_q G_q over its four fine sub-elements q.  The densities of every element
+// the thread touches are loaded up front; the loop over q is the outer one, so one
+// G_q block (64 constants) is live at a time and no load waits inside it.
+template <typename T, bool ROWS, int NJ>
+struct TileApply<T, OpCoarse2K<2, T>, ROWS, NJ> {
+  template <bool EDGE>
+  __device__ static inline void run(const OpCoarse2K<2, T>& op, const Dims& d, int i, int j0,
+                                    const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+    T xs[NJ + 1][2][4];
+#pragma unroll
+    for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+      for (int ec = 0; ec < 2; ++ec) {
+        const int ei = i - 1 + ec, ej = j0 - 1 + er;
+        if (!EDGE || elem_in(d, ei, ej)) {
+          op.xs(ei, ej, xs[er][ec]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) xs[er][ec][t] = T(0);
+        }
+      }
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      T xq[NJ + 1][2];
+#pragma unroll
+      for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+        for (int ec = 0; ec < 2; ++ec)
+          xq[er][ec] = q == 0 ? xs[er][ec][0] : q == 1 ? xs[er][ec][1] : q == 2 ? xs[er][ec][2] : xs[er][ec][3];
+      const int gq = q * 64;
+#pragma unroll
+      for (int n = 0; n < NJ; ++n)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+          for (int ex = 0; ex < 2; ++ex) {
+            const int er = n + ey, ec = ex;
+            const int a = loc_index(1 - ex, 1 - ey, 0);
+            const T xe = xq[er][ec];
+            if constexpr (ROWS) {
+              const T ve[8] = {w[er][ec][0],         w[er][ec][1],         w[er][ec + 1][0], w[er][ec + 1][1],
+                               w[er + 1][ec + 1][0], w[er + 1][ec + 1][1], w[er + 1][ec][0], w[er + 1][ec][1]};
+              T t0 = 0, t1 = 0;
+#pragma unroll
+              for (int col = 0; col < 8; ++col) {
+                t0 += g2<T>(gq + (2 * a) * 8 + col) * ve[col];
+                t1 += g2<T>(gq + (2 * a + 1) * 8 + col) * ve[col];
+              }
+              acc[n][0] += xe * t0;
+              acc[n][1] += xe * t1;
+            }
+            dg[n][0] += xe * g2<T>(gq + (2 * a) * 9);
+            dg[n][1] += xe * g2<T>(gq + (2 * a + 1) * 9);
+          }
+    }
+  }
+};
+
+// v on the (NJ+2) x 3 node neighbourhood of a thread's column (see TileApply);
+// EDGE: nodes outside the grid and clamped nodes (i == 0) read as zero.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void load_tile(const T* __restrict__ v, const Dims& d, int i, int j0, T (&w)[NJ + 2][3][2]) {
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int ii = i - 1 + cc, jj = j0 - 1 + rr;
+      if (!EDGE || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1)) {
+        const unsigned o = 2u * ((unsigned)jj * (unsigned)d.nx1 + (unsigned)ii);
+        w[rr][cc][0] = v[o];
+        w[rr][cc][1] = v[o + 1];
+      } else {
+        w[rr][cc][0] = w[rr][cc][1] = T(0);
+      }
+    }
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
-// along y of one column and loads the (NJ+2) x 3 window of neighbours once (rows
-// through one 32-bit offset each, x-neighbours at immediate offsets).  Tiles whose
-// nodes are all at least one node away from every boundary (and off the clamped
-// column) skip every bounds check; the others take the generic per-node path.
+// along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
+// whose nodes are all at least one node away from every boundary (and off the
+// clamped column) skip every bounds check; the others run the same code with
+// masked loads, so that no block waits on a chain of per-node loads.
 // Modes as in k_level except M_POWER and M_RAYLEIGH.
 template <typename T, class Op, int MODE, int NJ>
 __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restrict__ v,
@@ -588,39 +783,28 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   const T vl = (aug.b && MODE != M_JACOBI0) ? v[aug.n] : T(0);
   double bdot = 0.0, red0 = 0.0, red1 = 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
+  constexpr bool ROWS = MODE != M_JACOBI0;
+  T w[NJ + 2][3][2];
+  T acc[NJ][2], dg[NJ][2];
   if (interior) {
-    T w[NJ + 2][3][2];
-    if constexpr (MODE != M_JACOBI0) {
-      const unsigned base = 2u * ((unsigned)(j0 - 1) * (unsigned)d.nx1 + (unsigned)i);
-      const unsigned stride = 2u * (unsigned)d.nx1;
-#pragma unroll
-      for (int rr = 0; rr < NJ + 2; ++rr) {
-        const T* p = v + (base + rr * stride);
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          w[rr][cc][0] = p[2 * (cc - 1)];
-          w[rr][cc][1] = p[2 * (cc - 1) + 1];
-        }
-      }
-    }
-#pragma unroll
-    for (int n = 0; n < NJ; ++n) {
-      T vn[9][2];
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          vn[nb_index<2>(dx, dy, 0)][0] = w[n + 1 + dy][dx + 1][0];
-          vn[nb_index<2>(dx, dy, 0)][1] = w[n + 1 + dy][dx + 1][1];
-        }
-      level_node_core<2, T, Op, MODE, true>(op, d, i, j0 + n, 0, vn, r, out, omega, aug.b, vl, 1.0, dot64, bdot,
-                                            red0, red1);
-    }
+    if constexpr (ROWS) load_tile<T, NJ, false>(v, d, i, j0, w);
+    TileApply<T, Op, ROWS, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
   } else {
+    if constexpr (ROWS) load_tile<T, NJ, true>(v, d, i, j0, w);
+    TileApply<T, Op, ROWS, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
+  }
 #pragma unroll
-    for (int n = 0; n < NJ; ++n)
-      if (i < d.nx1 && j0 + n < d.ny1)
-        level_node<2, T, Op, MODE>(op, d, i, j0 + n, 0, v, r, out, omega, aug.b, vl, 1.0, dot64, bdot, red0, red1);
+  for (int n = 0; n < NJ; ++n) {
+    const int j = j0 + n;
+    if (!interior && (i >= d.nx1 || j >= d.ny1)) continue;
+    const int64_t q = (int64_t)j * d.nx1 + i;
+    if (!interior && i == 0) {
+      const T z[2] = {T(0), T(0)};
+      store_node<2, T>(out, q, z);
+      continue;
+    }
+    const T vc[2] = {ROWS ? w[n + 1][1][0] : T(0), ROWS ? w[n + 1][1][1] : T(0)};
+    level_node_finish<2, T, MODE>(q, acc[n], dg[n], vc, r, out, omega, aug.b, vl, 1.0, dot64, bdot, red0, red1);
   }
   if (aug.b) {
     if constexpr (MODE == M_JACOBI0) {
@@ -707,6 +891,68 @@ __global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __res
     }
     store_node<DIM, double>(p, qn, pc);
     store_node<DIM, double>(q, qn, o);
+  }
+  const double vals[2] = {pq, bdot};
+  block_partials<2>(vals, red);
+}
+
+// 2D form of k_dir_apply with register-blocked tiles (as k_level2d): each thread
+// owns NJ nodes of one column, forms p = -y + beta p_old on the (NJ+2) x 3
+// neighbourhood once and reuses it for the NJ rows of q = A p.
+template <typename TY, class Op, int NJ>
+__global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __restrict__ y,
+                                                    const double* __restrict__ pold, double* __restrict__ p,
+                                                    double* __restrict__ q, Aug<double> aug, Red red, int first,
+                                                    const int* gate) {
+  if (gate && *gate) return;
+  const double beta = first ? 0.0 : red.scal[S_BETA];
+  const Tile tl = xcd_tile();
+  constexpr int RJ = (BS / 64) * NJ;
+  const int ti0 = tl.x * 64, tj0 = tl.y * RJ;
+  const int i = ti0 + (threadIdx.x & 63);
+  const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
+  double pq = 0.0, bdot = 0.0;
+  const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
+  const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
+  TY yw[NJ + 2][3][2];
+  double w[NJ + 2][3][2], acc[NJ][2], dg[NJ][2];
+  if (interior) {
+    load_tile<TY, NJ, false>(y, d, i, j0, yw);
+    if (!first) load_tile<double, NJ, false>(pold, d, i, j0, w);
+  } else {
+    load_tile<TY, NJ, true>(y, d, i, j0, yw);
+    if (!first) load_tile<double, NJ, true>(pold, d, i, j0, w);
+  }
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) w[rr][cc][c] = -(double)yw[rr][cc][c] + (first ? 0.0 : beta * w[rr][cc][c]);
+  if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
+  else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
+#pragma unroll
+  for (int n = 0; n < NJ; ++n) {
+    const int j = j0 + n;
+    if (!interior && (i >= d.nx1 || j >= d.ny1)) continue;
+    const int64_t qn = (int64_t)j * d.nx1 + i;
+    double o[2] = {acc[n][0], acc[n][1]};
+    double pc[2] = {w[n + 1][1][0], w[n + 1][1][1]};
+    if (!interior && i == 0) {
+      o[0] = o[1] = pc[0] = pc[1] = 0.0;
+    } else {
+      if (aug.b) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const double bc = aug.b[qn * 2 + c];
+          o[c] += bc * pl;
+          bdot += bc * pc[c];
+        }
+      }
+      pq += pc[0] * o[0] + pc[1] * o[1];
+    }
+    store_node<2, double>(p, qn, pc);
+    store_node<2, double>(q, qn, o);
   }
   const double vals[2] = {pq, bdot};
   block_partials<2>(vals, red);

@@ -1,6 +1,8 @@
 // Per-dimension kernel set: element stiffness, sensitivities, interior-point
 // element/node kernels and the dispatch of the level kernels (kernels.h).
 #pragma once
+#include <algorithm>
+#include <cmath>
 #include "ctx.h"
 #include "kernels.h"
 #include "tail.h"
@@ -313,6 +315,16 @@ struct OpsImpl : Ops {
   }
   void upload_k0(const double* K0) override {
     constexpr int ND = Geo<DIM>::ND;
+    if constexpr (DIM == 2) {
+      double kmax = 0.0;
+      for (int t = 0; t < 64; ++t) kmax = std::max(kmax, std::fabs(K0[t]));
+      for (int t = 0; t < 64; ++t) {
+        const int e = kSq2d[t];
+        const double want = e > 0 ? K0[e - 1] : -K0[-e - 1];
+        IPMG_REQUIRE(std::fabs(K0[t] - want) <= 1e-12 * kmax, IPMG_E_INVALID,
+                     "element matrix lacks the square-element symmetry");
+      }
+    }
     float kf[576];
     for (int t = 0; t < ND * ND; ++t) kf[t] = (float)K0[t];
     IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0d), K0, sizeof(double) * ND * ND));
@@ -424,7 +436,21 @@ struct OpsImpl : Ops {
   void launch_dir_apply(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q,
                         Aug<double> aug, int first, const int* gate) {
     const Dims& d = c.fine();
-    const dim3 g = node_grid(d);
+    dim3 g = node_grid(d);
+    if constexpr (DIM == 2) {
+      if (c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
+        constexpr int NJ = 2;
+        g = dim3((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
+        IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+        {
+          ProfScope ps(c, PC_DIR_APPLY);
+          k_dir_apply2d<TY, Op, NJ><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+        }
+        k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
+                                              g.x * g.y, gate);
+        return;
+      }
+    }
     {
       ProfScope ps(c, PC_DIR_APPLY);
       k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);

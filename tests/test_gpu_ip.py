@@ -55,7 +55,9 @@ def test_newton_system_and_z_operator(nel, levels, fp32):
     assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < tol
 
 
-def test_newton_step_matches_oracle():
+@pytest.mark.parametrize("tiled", [False, True])
+def test_newton_step_matches_oracle(tiled, monkeypatch):
+    # tiled: register-blocked 2D kernels on every level (Z operator and PCG direction)
     from paper_1606_06201_amd import Solver
     nel, levels = (32, 16), 3
     prob = _problem(nel)
@@ -63,7 +65,10 @@ def test_newton_step_matches_oracle():
     params_o = oip.IPParams(solver="mg", levels=levels, pcg_rtol=1e-10)
     st0, _ = oip.initial_state(prob, params_o)
     st1, alpha, _ = oip.newton_step(prob, st0, params_o)
+    if tiled:
+        monkeypatch.setenv("IPMG_TILED_MIN_NODES", "0")
     s = Solver(nel, levels, fp32=False)
+    monkeypatch.delenv("IPMG_TILED_MIN_NODES", raising=False)
     params = s.ip_params(prob.V, prob.xbar, pcg_rtol=1e-10)
     gst, init = s.ip_init(T(prob.f_slots), params)
     assert relerr(fem.to_free(g, N(gst["u"])), st0.u) < 1e-8
