@@ -195,57 +195,222 @@ __global__ __launch_bounds__(BS) void k_normalize(T* __restrict__ x, int64_t n, 
     x[t] = T((double)x[t] * inv);
 }
 
-// ------------------------------------------------------------- dense coarse ---
-// In-place lower Cholesky factor of the n x n row-major SPD matrix A (one block).
-// flags[F_BAD] = 1 if a pivot is not positive.
-__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n, Red red) {
-  __shared__ double piv;
-  for (int j = 0; j < n; ++j) {
+// ------------------------------------------------ dense coarsest-level solve --
+// Blocked Cholesky A = L L' (lower, row-major n x n, in place) and explicit inverse
+// A^-1 = L^-T L^-1 on CT x CT tiles, FP64.  Only the lower triangle of A is read;
+// the strict upper triangles of L and of the tiles of L^-1 are written as zero.
+constexpr int CT = 32;
+constexpr int CTT = 256;   // threads per tile kernel
+
+__device__ inline int tile_rows(int n, int t0) { return n - t0 < CT ? n - t0 : CT; }
+
+// Lower-triangular factor of the kb x kb tile in LDS (right-looking); a pivot that
+// is not positive sets the breakdown flag and continues with 1.
+__device__ void tile_cholesky(double (&D)[CT][CT + 1], int kb, const Red& red) {
+  for (int j = 0; j < kb; ++j) {
     if (threadIdx.x == 0) {
-      double d = A[(int64_t)j * n + j];
-      if (!(d > 0.0)) { red.flags[F_BAD] = 1; d = 1.0; }
-      d = sqrt(d);
-      A[(int64_t)j * n + j] = d;
-      piv = d;
+      double d = D[j][j];
+      if (!(d > 0.0) || !isfinite(d)) { red.flags[F_BAD] = 1; d = 1.0; }
+      D[j][j] = sqrt(d);
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(int64_t)i * n + j] /= piv;
+    for (int r = j + 1 + threadIdx.x; r < kb; r += CTT) D[r][j] /= D[j][j];
     __syncthreads();
-    const int m = n - j - 1;                      // trailing lower triangle, m(m+1)/2 entries
-    const int64_t cnt = (int64_t)m * (m + 1) / 2;
-    for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
-      // t -> (ii, kk) with 0 <= kk <= ii < m
-      int ii = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-      while ((int64_t)ii * (ii + 1) / 2 > t) --ii;
-      while ((int64_t)(ii + 1) * (ii + 2) / 2 <= t) ++ii;
-      const int kk = (int)(t - (int64_t)ii * (ii + 1) / 2);
-      const int gi = j + 1 + ii, gk = j + 1 + kk;
-      A[(int64_t)gi * n + gk] -= A[(int64_t)gi * n + j] * A[(int64_t)gk * n + j];
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c = t % CT;
+      if (r > j && c > j && c <= r && r < kb) D[r][c] -= D[r][j] * D[c][j];
     }
     __syncthreads();
   }
 }
 
-// Column j of L^-1 by forward substitution (one thread per column).
-__global__ __launch_bounds__(BS) void k_tri_inverse(const double* __restrict__ L, double* __restrict__ Li, int n) {
-  const int j = blockIdx.x * BS + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < j; ++i) Li[(int64_t)i * n + j] = 0.0;
-  for (int i = j; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = j; k < i; ++k) s -= L[(int64_t)i * n + k] * Li[(int64_t)k * n + j];
-    Li[(int64_t)i * n + j] = s / L[(int64_t)i * n + i];
+// Block column starting at k0: factor the diagonal tile (every block, redundantly,
+// in LDS); block 0 stores it, block b > 0 solves its panel tile X L_kk' = A_ik.
+__global__ __launch_bounds__(CTT) void k_chol_panel(double* __restrict__ A, int n, int k0, Red red) {
+  __shared__ double D[CT][CT + 1];
+  __shared__ double P[CT][CT + 1];
+  const int kb = tile_rows(n, k0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    D[r][c] = (r < kb && c <= r) ? A[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  tile_cholesky(D, kb, red);
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c = t % CT;
+      if (r < kb && c < kb) A[(int64_t)(k0 + r) * n + k0 + c] = c <= r ? D[r][c] : 0.0;
+    }
+    return;
+  }
+  const int i0 = k0 + kb + (blockIdx.x - 1) * CT;
+  const int ib = tile_rows(n, i0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    P[r][c] = (r < ib && c < kb) ? A[(int64_t)(i0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < kb; ++c) {                 // column-oriented forward substitution
+    for (int r = threadIdx.x; r < ib; r += CTT) P[r][c] /= D[c][c];
+    __syncthreads();
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c2 = t % CT;
+      if (r < ib && c2 > c && c2 < kb) P[r][c2] -= P[r][c] * D[c2][c];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    if (r < ib && c < kb) A[(int64_t)(i0 + r) * n + k0 + c] = P[r][c];
   }
 }
 
-// A^-1 = L^-T L^-1, one thread per entry.
-__global__ __launch_bounds__(BS) void k_inv_product(const double* __restrict__ Li, double* __restrict__ Ai, int n) {
-  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (t >= (int64_t)n * n) return;
-  const int r = (int)(t / n), c = (int)(t % n);
-  double s = 0.0;
-  for (int k = r > c ? r : c; k < n; ++k) s += Li[(int64_t)k * n + r] * Li[(int64_t)k * n + c];
-  Ai[t] = s;
+// Tile index pair (I, J), 0 <= J <= I, of the t-th tile of a lower block triangle.
+__device__ inline void tri_pair(int t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+// Trailing update after block column k0: A_IJ -= L_Ik L_Jk' for the tiles of the
+// lower triangle below and right of it (one block per tile).
+__global__ __launch_bounds__(CTT) void k_chol_update(double* __restrict__ A, int n, int k0) {
+  __shared__ double Li[CT][CT + 1];
+  __shared__ double Lj[CT][CT + 1];
+  int I, J;
+  tri_pair((int)blockIdx.x, I, J);
+  const int kb = tile_rows(n, k0);
+  const int s0 = k0 + kb;
+  const int i0 = s0 + I * CT, j0 = s0 + J * CT;
+  const int ib = tile_rows(n, i0), jb = tile_rows(n, j0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    Li[r][c] = (r < ib && c < kb) ? A[(int64_t)(i0 + r) * n + k0 + c] : 0.0;
+    Lj[r][c] = (r < jb && c < kb) ? A[(int64_t)(j0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    if (r >= ib || c >= jb || (I == J && c > r)) continue;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < CT; ++k) s += Li[r][k] * Lj[c][k];
+    A[(int64_t)(i0 + r) * n + j0 + c] -= s;
+  }
+}
+
+// X_ii = L_ii^-1 for every diagonal tile (one block per tile; zero above the diagonal).
+__global__ __launch_bounds__(CTT) void k_tri_inv_diag(const double* __restrict__ L, double* __restrict__ X, int n) {
+  __shared__ double D[CT][CT + 1];
+  __shared__ double Y[CT][CT + 1];
+  const int i0 = blockIdx.x * CT, ib = tile_rows(n, i0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    D[r][c] = (r < ib && c < ib) ? L[(int64_t)(i0 + r) * n + i0 + c] : 0.0;
+    Y[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < ib; ++k) {                 // column-oriented forward substitution on all columns
+    for (int c = threadIdx.x; c < ib; c += CTT) Y[k][c] /= D[k][k];
+    __syncthreads();
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c = t % CT;
+      if (r > k && r < ib && c < ib) Y[r][c] -= D[r][k] * Y[k][c];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    if (r < ib && c < ib) X[(int64_t)(i0 + r) * n + i0 + c] = c <= r ? Y[r][c] : 0.0;
+  }
+}
+
+// Tile row I of X = L^-1 below the diagonal: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ
+// (one block per J < I; tile rows above I are complete).
+__global__ __launch_bounds__(CTT) void k_tri_inv_row(const double* __restrict__ L, double* __restrict__ X, int n,
+                                                     int I) {
+  __shared__ double Ta[CT][CT + 1];
+  __shared__ double Tb[CT][CT + 1];
+  const int J = blockIdx.x;
+  const int i0 = I * CT, j0 = J * CT;
+  const int ib = tile_rows(n, i0);
+  double acc[CT * CT / CTT];
+#pragma unroll
+  for (int u = 0; u < CT * CT / CTT; ++u) acc[u] = 0.0;
+  for (int K = J; K < I; ++K) {
+    const int k0 = K * CT;
+    __syncthreads();
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c = t % CT;
+      Ta[r][c] = (r < ib) ? L[(int64_t)(i0 + r) * n + k0 + c] : 0.0;   // L_IK (K < I: full tile)
+      Tb[r][c] = X[(int64_t)(k0 + r) * n + j0 + c];                     // X_KJ (K, J < I: full tile)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CT * CT / CTT; ++u) {
+      const int t = threadIdx.x + u * CTT, r = t / CT, c = t % CT;
+      double s = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < CT; ++k) s += Ta[r][k] * Tb[k][c];
+      acc[u] += s;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    Ta[r][c] = (r < ib && c < ib) ? X[(int64_t)(i0 + r) * n + i0 + c] : 0.0;   // X_II
+  }
+#pragma unroll
+  for (int u = 0; u < CT * CT / CTT; ++u) {
+    const int t = threadIdx.x + u * CTT;
+    Tb[t / CT][t % CT] = acc[u];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    if (r >= ib) continue;
+    double s = 0.0;
+    for (int k = 0; k <= r; ++k) s += Ta[r][k] * Tb[k][c];
+    X[(int64_t)(i0 + r) * n + j0 + c] = -s;
+  }
+}
+
+// A^-1 = X' X with X = L^-1 lower triangular: tile (I, J) = sum_{K >= max(I,J)} X_KI' X_KJ.
+__global__ __launch_bounds__(CTT) void k_inv_product(const double* __restrict__ X, double* __restrict__ Ai, int n) {
+  __shared__ double Ta[CT][CT + 1];
+  __shared__ double Tb[CT][CT + 1];
+  const int nt = (n + CT - 1) / CT;
+  const int I = blockIdx.x % nt, J = blockIdx.x / nt;
+  const int i0 = I * CT, j0 = J * CT;
+  const int ib = tile_rows(n, i0), jb = tile_rows(n, j0);
+  double acc[CT * CT / CTT];
+#pragma unroll
+  for (int u = 0; u < CT * CT / CTT; ++u) acc[u] = 0.0;
+  for (int K = I > J ? I : J; K < nt; ++K) {
+    const int k0 = K * CT, kb = tile_rows(n, k0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+      const int r = t / CT, c = t % CT;
+      Ta[r][c] = (r < kb && c < ib) ? X[(int64_t)(k0 + r) * n + i0 + c] : 0.0;   // X_KI
+      Tb[r][c] = (r < kb && c < jb) ? X[(int64_t)(k0 + r) * n + j0 + c] : 0.0;   // X_KJ
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CT * CT / CTT; ++u) {
+      const int t = threadIdx.x + u * CTT, r = t / CT, c = t % CT;
+      double s = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < CT; ++k) s += Ta[k][r] * Tb[k][c];
+      acc[u] += s;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CT * CT / CTT; ++u) {
+    const int t = threadIdx.x + u * CTT, r = t / CT, c = t % CT;
+    if (r < ib && c < jb) Ai[(int64_t)(i0 + r) * n + j0 + c] = acc[u];
+  }
 }
 
 // zc = A^-1 rc, one wavefront per row.
@@ -323,11 +488,19 @@ void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_va
   k_set_omega<<<1, 64, 0, st>>>(red, w, rho, s_vav, s_vdv, omega, product);
 }
 void vfill_small(hipStream_t st, double* w, int n, double value) { k_fill_value<<<1, 64, 0, st>>>(w, n, value); }
-void dense_cholesky(hipStream_t st, double* A, int n, const Red& red) { k_cholesky<<<1, 1024, 0, st>>>(A, n, red); }
+void dense_cholesky(hipStream_t st, double* A, int n, const Red& red) {
+  for (int k0 = 0; k0 < n; k0 += CT) {
+    const int kb = n - k0 < CT ? n - k0 : CT;
+    const int m = (n - k0 - kb + CT - 1) / CT;          // tile rows below the diagonal tile
+    k_chol_panel<<<1 + m, CTT, 0, st>>>(A, n, k0, red);
+    if (m > 0) k_chol_update<<<m * (m + 1) / 2, CTT, 0, st>>>(A, n, k0);
+  }
+}
 void dense_inverse(hipStream_t st, const double* L, double* Li, double* Ai, int n) {
-  k_tri_inverse<<<(n + BS - 1) / BS, BS, 0, st>>>(L, Li, n);
-  const int64_t nn = (int64_t)n * n;
-  k_inv_product<<<(unsigned)((nn + BS - 1) / BS), BS, 0, st>>>(Li, Ai, n);
+  const int nt = (n + CT - 1) / CT;
+  k_tri_inv_diag<<<nt, CTT, 0, st>>>(L, Li, n);
+  for (int I = 1; I < nt; ++I) k_tri_inv_row<<<I, CTT, 0, st>>>(L, Li, n, I);
+  k_inv_product<<<nt * nt, CTT, 0, st>>>(Li, Ai, n);
 }
 template <typename T>
 void dense_solve(hipStream_t st, const double* Ai, int n, const T* rc, T* zc, const int* gate) {

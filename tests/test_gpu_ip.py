@@ -55,6 +55,27 @@ def test_newton_system_and_z_operator(nel, levels, fp32):
     assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < tol
 
 
+def test_z_dense_coarse_solve_many_tiles():
+    # One-level hierarchy of the augmented system: 529 unknowns (17 tiles, ragged),
+    # the V-cycle is the exact solve with Z.
+    from paper_1606_06201_amd import Solver
+    nel = (24, 10)
+    prob = _problem(nel)
+    g = prob.grid
+    st, u_slots = _state(prob)
+    Z, rhs, parts = prob.z_system(st)
+    s = Solver(nel, 1, fp32=False)
+    params = s.ip_params(prob.V, prob.xbar)
+    s.ip_prepare(T(prob.f_slots), params, _gpu_state(s, st, u_slots))
+    s.mg_setup(1)
+    v = np.random.default_rng(4).standard_normal(g.nslots + 1)
+    v[:-1][g.clamped_mask()] = 0
+    free = g.free_to_slot()
+    zc = N(s.vcycle(T(v), op=1))
+    ref = np.linalg.solve(Z.toarray() if hasattr(Z, "toarray") else Z, np.concatenate([v[:-1][free], v[-1:]]))
+    assert relerr(np.concatenate([zc[free], zc[-1:]]), ref) < 1e-9
+
+
 @pytest.mark.parametrize("tiled", [False, True])
 def test_newton_step_matches_oracle(tiled, monkeypatch):
     # tiled: register-blocked 2D kernels on every level (Z operator and PCG direction)

@@ -80,6 +80,26 @@ def test_vcycle_matches_oracle(nel, levels, fp32, tol):
     assert np.array_equal(z, z2)
 
 
+@pytest.mark.parametrize("nel,levels", [((40, 18), 1), ((80, 36), 2), ((8, 4, 4), 1)])
+def test_dense_coarse_solve_many_tiles(nel, levels):
+    # The coarsest-level factorization and explicit inverse run on 32 x 32 tiles:
+    # sizes of 1520 (2D) and 600 (3D) unknowns span many tiles and end in a ragged one.
+    g, K0, x = _kproblem(nel)
+    s = _solver(nel, levels)
+    s.set_density(T(x))
+    s.mg_setup()
+    r = np.random.default_rng(8).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    z = fem.to_free(g, N(s.vcycle(T(r))))
+    if levels == 1:     # one level: the V-cycle is the exact solve
+        K = fem.stiffness_free(g, x, K0)
+        ref = spla.spsolve(K.tocsc(), fem.to_free(g, r))
+        assert relerr(z, ref) < 1e-9
+    else:
+        H = mg.kstiffness_hierarchy(g, x, K0, levels)
+        assert relerr(z, mg.vcycle(H, fem.to_free(g, r))) < 1e-10
+
+
 @pytest.mark.parametrize("nel,levels,fp32", [((64, 32), 4, False), ((64, 32), 4, True),
                                              ((16, 8, 8), 3, False), ((16, 8, 8), 3, True)])
 def test_pcg_matches_direct_solve(nel, levels, fp32):
