@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--workload", default="thr2048x1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--flexible", type=int, default=0, choices=(0, 1),
+                    help="PCG ratio: 0 = Algorithm PCG, 1 = Polak-Ribiere form (both precisions)")
     ap.add_argument("--roofline-kernel", default="auto",
                     help="kernel class for the roofline; auto = largest total time in an untimed profiled solve")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -164,7 +166,7 @@ def main():
     print(f"[bench] workload {args.workload} nel={nel} levels={levels}", file=sys.stderr, flush=True)
 
     def make(fp32):
-        s = Solver(nel, levels, fp32=fp32, device=dev)
+        s = Solver(nel, levels, fp32=fp32, flexible=bool(args.flexible), device=dev)
         return s
 
     s32 = make(True)
@@ -271,6 +273,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "elements": list(nel), "free_dofs": n_free,
                    "levels": levels, "smoother": "damped Jacobi 2+2", "rtol": 1e-8,
+                   "pcg_beta": "Polak-Ribiere" if args.flexible else "Fletcher-Reeves (Algorithm PCG)",
                    "density": "band-connected random field thresholded to {1e-6, 1}, ~40% solid"},
         "mixed": {"time_to_1e-8_ms": 1000.0 * t_mixed / args.steps, "iters": inf["iters"],
                   "setup_ms": inf["setup_ms"], "true_relres": inf["true_relres"], "compliance": c_mixed},

@@ -64,6 +64,10 @@ typedef struct {
                        coarsest solve and PCG in FP64; 0: everything FP64          */
   int nu_pre, nu_post; /* damped-Jacobi sweeps before / after the coarse correction */
   double omega;     /* Jacobi damping (0.6)                                       */
+  int pcg_flexible; /* 0: PCG ratio beta = r~'y~ / r'y (Algorithm PCG, Sec. 6);
+                       1: Polak-Ribiere form r~'(y~ - y) / r'y, the same in exact
+                       arithmetic with a fixed preconditioner and more robust when
+                       the preconditioner varies between steps (FP32 V-cycle)      */
 } ipmg_desc;
 
 typedef struct {

@@ -32,9 +32,11 @@ class PCGResult:
 
 def pcg(apply_A, b, precond, rtol=1e-8, maxit=1000, z0=None, flexible=False):
     """flexible=True replaces the ratio r~'y~ / r'y by the Polak-Ribiere form
-    r~'(y~ - y) / r'y, which keeps conjugacy when the preconditioner varies
-    slightly between applications (a V-cycle evaluated in reduced precision);
-    in exact arithmetic with a fixed preconditioner both forms coincide."""
+    r~'(y~ - y) / r'y (inexact / flexible PCG, an option beyond the paper's
+    Algorithm PCG for a preconditioner that varies slightly between applications,
+    such as a V-cycle evaluated in reduced precision).  In exact arithmetic with a
+    fixed symmetric preconditioner both forms coincide (pinned); the varying case
+    has no closed form to pin against (parity unpinned)."""
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
     z = np.zeros_like(b) if z0 is None else np.array(z0, dtype=np.float64)

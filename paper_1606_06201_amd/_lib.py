@@ -13,7 +13,7 @@ OP_K, OP_Z = 0, 1
 class Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("nel", C.c_int * 3), ("levels", C.c_int), ("E", C.c_double),
                 ("nu", C.c_double), ("vcycle_fp32", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("pcg_flexible", C.c_int)]
 
 
 class PCGInfo(C.Structure):

@@ -76,7 +76,10 @@ inline Dims make_dims(int dim, int nx, int ny, int nz) {
 // Indices into the FP64 device scalar array.
 enum Scal {
   S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RN2, S_BN2, S_TOL2, S_RHONEW, S_TMP0, S_TMP1, S_TMP2,
-  S_TMP3, S_TMP4, S_TMP5, S_TMP6, S_TMP7, S_MIN0, S_MIN1, S_MIN2, S_MIN3, S_COUNT = 32
+  S_TMP3, S_TMP4, S_TMP5, S_TMP6, S_TMP7, S_MIN0, S_MIN1, S_MIN2, S_MIN3,
+  S_QY,    // q'y of the current PCG step (q = A p, y the preconditioned residual)
+  S_FLEX,  // 1: Polak-Ribiere ratio in PCG, 0: the ratio of Algorithm PCG
+  S_COUNT = 32
 };
 // Indices into the int device flag array.
 enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_COUNT = 8 };

@@ -405,14 +405,19 @@ enum LevelMode {
   M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5, M_JACOBI_BETA = 6
 };
 
-// Post-processing of the PCG ratio beta = r~'y~ / r'y (Algorithm PCG) by the
-// thread that owns the final sum.
+// Post-processing of the PCG ratio by the thread that owns the final sum
+// tot = r~'y~: beta = r~'y~ / r'y (Algorithm PCG) or, with scal[S_FLEX] set, the
+// Polak-Ribiere form r~'(y~ - y) / r'y, which stays effective when the
+// preconditioner varies slightly between steps (an FP32 V-cycle).  r~'y follows
+// from r~ = r + alpha q: r~'y = r'y + alpha q'y.
 __device__ inline void finish_beta(double tot, const Red& red) {
   if (!(tot > 0.0) || !isfinite(tot)) {
     red.flags[F_DONE] = 2;
     red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
   } else {
-    red.scal[S_BETA] = tot / red.scal[S_RHO];
+    const double rho = red.scal[S_RHO];
+    const double num = red.scal[S_FLEX] != 0.0 ? tot - (rho + red.scal[S_ALPHA] * red.scal[S_QY]) : tot;
+    red.scal[S_BETA] = num / rho;
     red.scal[S_RHO] = tot;
   }
 }
@@ -835,7 +840,7 @@ __global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __res
   const int i = tl.x * 64 + (threadIdx.x & 63);
   const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
   const int k = tl.z;
-  double pq = 0.0, bdot = 0.0;
+  double pq = 0.0, bdot = 0.0, qy = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   if (i < d.nx1 && j < d.ny1) {
     const int64_t qn = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
@@ -883,17 +888,20 @@ __global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __res
           bdot += bc * pc[c];
         }
       }
+      TY yc[DIM];
+      load_node<DIM, TY>(y, qn, yc);
 #pragma unroll
       for (int c = 0; c < DIM; ++c) {
         o[c] = acc[c];
         pq += pc[c] * acc[c];
+        qy += acc[c] * (double)yc[c];
       }
     }
     store_node<DIM, double>(p, qn, pc);
     store_node<DIM, double>(q, qn, o);
   }
-  const double vals[2] = {pq, bdot};
-  block_partials<2>(vals, red);
+  const double vals[3] = {pq, bdot, qy};
+  block_partials<3>(vals, red);
 }
 
 // 2D form of k_dir_apply with register-blocked tiles (as k_level2d): each thread
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
   const int ti0 = tl.x * 64, tj0 = tl.y * RJ;
   const int i = ti0 + (threadIdx.x & 63);
   const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
-  double pq = 0.0, bdot = 0.0;
+  double pq = 0.0, bdot = 0.0, qy = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
   TY yw[NJ + 2][3][2];
@@ -950,12 +958,13 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
         }
       }
       pq += pc[0] * o[0] + pc[1] * o[1];
+      qy += o[0] * (double)yw[n + 1][1][0] + o[1] * (double)yw[n + 1][1][1];
     }
     store_node<2, double>(p, qn, pc);
     store_node<2, double>(q, qn, o);
   }
-  const double vals[2] = {pq, bdot};
-  block_partials<2>(vals, red);
+  const double vals[3] = {pq, bdot, qy};
+  block_partials<3>(vals, red);
 }
 
 // Finalize of k_dir_apply: lambda entries of p and q (augmented system) and
@@ -965,10 +974,10 @@ __global__ __launch_bounds__(BS) void k_dir_fin(const TY* __restrict__ y, const 
                                                 double* __restrict__ p, double* __restrict__ q, int aug, double c,
                                                 int64_t n, int first, Red red, unsigned nblocks, const int* gate) {
   if (gate && *gate) return;
-  double tot[2];
-  sum_partials<2>(red, nblocks, tot);
+  double tot[3];
+  sum_partials<3>(red, nblocks, tot);
   if (threadIdx.x != 0) return;
-  double ptq = tot[0];
+  double ptq = tot[0], qy = tot[2];
   if (aug) {
     const double beta = first ? 0.0 : red.scal[S_BETA];
     const double pl = -(double)y[n] + (first ? 0.0 : beta * pold[n]);
@@ -976,8 +985,10 @@ __global__ __launch_bounds__(BS) void k_dir_fin(const TY* __restrict__ y, const 
     p[n] = pl;
     q[n] = ql;
     ptq += pl * ql;
+    qy += ql * (double)y[n];
   }
   red.scal[S_PQ] = ptq;
+  red.scal[S_QY] = qy;
   if (!(ptq > 0.0) || !isfinite(ptq)) {
     red.flags[F_DONE] = 2;
     red.flags[F_STATUS] = IPMG_E_BREAKDOWN;

@@ -79,6 +79,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   IPMG_REQUIRE(d.nu_pre >= 1 && d.nu_post >= 0 && d.nu_pre <= 64 && d.nu_post <= 64, IPMG_E_INVALID,
                "sweeps: need 1 <= nu_pre <= 64, 0 <= nu_post <= 64");
   IPMG_REQUIRE(d.omega > 0.0 && d.omega < 2.0, IPMG_E_INVALID, "omega must be in (0, 2)");
+  IPMG_REQUIRE(d.pcg_flexible == 0 || d.pcg_flexible == 1, IPMG_E_INVALID, "pcg_flexible must be 0 or 1");
   IPMG_REQUIRE(d.E > 0.0 && d.nu > -1.0 && d.nu < 0.5, IPMG_E_INVALID, "material: E > 0, -1 < nu < 0.5");
   const int f = 1 << (d.levels - 1);
   for (int a = 0; a < d.dim; ++a) {
@@ -416,6 +417,7 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
   c.ops->fine_apply64(c, op, c.pu, c.pq, nullptr);
   vsub_norm(c.stream, c.pq, c.pb, c.pr, n, c.red, S_RN2);
   vset_tol(c.stream, c.red, rtol);
+  vfill_small(c.stream, c.red.scal + S_FLEX, 1, c.desc.pcg_flexible ? 1.0 : 0.0);
   read_scalars(c);
   int status = IPMG_OK;
   int restarts = 0;

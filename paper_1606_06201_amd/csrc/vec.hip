@@ -37,12 +37,14 @@ __device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
     } else if (tot <= red.scal[S_TOL2]) {
       red.flags[F_DONE] = 1;
     }
-  } else if (fin == FIN_BETA) {                  // beta = r~'y~ / r'y
+  } else if (fin == FIN_BETA) {                  // beta = r~'y~ / r'y (or Polak-Ribiere)
     if (!(tot > 0.0) || !isfinite(tot)) {
       red.flags[F_DONE] = 2;
       red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
     } else {
-      red.scal[S_BETA] = tot / red.scal[S_RHO];
+      const double rho = red.scal[S_RHO];
+      const double num = red.scal[S_FLEX] != 0.0 ? tot - (rho + red.scal[S_ALPHA] * red.scal[S_QY]) : tot;
+      red.scal[S_BETA] = num / rho;
       red.scal[S_RHO] = tot;
     }
   }

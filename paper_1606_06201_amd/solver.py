@@ -22,7 +22,7 @@ class Solver:
     system Z) for a structured Q1 grid of nel = (nx, ny[, nz]) unit elements."""
 
     def __init__(self, nel, levels, fp32=True, E=1.0, nu=0.3, nu_pre=2, nu_post=2, omega=0.6,
-                 device="cuda:0"):
+                 flexible=False, device="cuda:0"):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -34,6 +34,7 @@ class Solver:
             d.nel[a] = nel[a] if a < len(nel) else 1
         d.levels, d.E, d.nu = int(levels), float(E), float(nu)
         d.vcycle_fp32, d.nu_pre, d.nu_post, d.omega = int(bool(fp32)), int(nu_pre), int(nu_post), float(omega)
+        d.pcg_flexible = int(bool(flexible))
         self.nel, self.dim, self.levels, self.fp32 = nel, len(nel), int(levels), bool(fp32)
         h = C.c_void_p()
         with torch.cuda.device(self.device):

@@ -100,12 +100,14 @@ def test_dense_coarse_solve_many_tiles(nel, levels):
         assert relerr(z, mg.vcycle(H, fem.to_free(g, r))) < 1e-10
 
 
-@pytest.mark.parametrize("nel,levels,fp32", [((64, 32), 4, False), ((64, 32), 4, True),
-                                             ((16, 8, 8), 3, False), ((16, 8, 8), 3, True)])
-def test_pcg_matches_direct_solve(nel, levels, fp32):
+@pytest.mark.parametrize("nel,levels,fp32,flexible", [((64, 32), 4, False, False), ((64, 32), 4, True, False),
+                                                      ((16, 8, 8), 3, False, False), ((16, 8, 8), 3, True, False),
+                                                      ((64, 32), 4, False, True), ((64, 32), 4, True, True),
+                                                      ((16, 8, 8), 3, True, True)])
+def test_pcg_matches_direct_solve(nel, levels, fp32, flexible):
     g, K0, x = _kproblem(nel, lo=1e-3)
     f = fem.load_vector(g, tip_load(nel))
-    s = _solver(nel, levels, fp32=fp32)
+    s = _solver(nel, levels, fp32=fp32, flexible=flexible)
     s.set_density(T(x))
     u, info = s.pcg(T(f), rtol=1e-8)
     u = N(u)
@@ -120,7 +122,7 @@ def test_pcg_matches_direct_solve(nel, levels, fp32):
     assert abs(c_gpu - c_ref) <= 1e-6 * abs(c_ref)
     # same iteration count as the oracle's FP64 MG-PCG (mixed precision within a few)
     H = mg.kstiffness_hierarchy(g, x, K0, levels)
-    ref = opcg.mg_pcg(H, fem.to_free(g, f), rtol=1e-8)
+    ref = opcg.mg_pcg(H, fem.to_free(g, f), rtol=1e-8, flexible=flexible)
     assert abs(info["iters"] - ref.iters) <= (0 if not fp32 else 2), (info["iters"], ref.iters)
 
 

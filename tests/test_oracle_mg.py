@@ -101,6 +101,23 @@ def test_pcg_identity_preconditioner_textbook_cg():
     assert res.converged
 
 
+def test_flexible_ratio_equals_standard_with_fixed_preconditioner():
+    # With one fixed symmetric preconditioner, r~'y = 0 (conjugacy of successive
+    # residuals in the M inner product), so the Polak-Ribiere ratio reproduces the
+    # iterates of Algorithm PCG up to rounding.  (With a preconditioner that varies
+    # between steps the two differ; that case has no closed form: parity unpinned.)
+    g, K0, x = _setup((32, 16))
+    A = fem.stiffness_free(g, x, K0)
+    H = mg.Hierarchy(g, A, 3)
+    b = np.random.default_rng(10).standard_normal(A.shape[0])
+    std = pcg.mg_pcg(H, b, rtol=1e-10)
+    flex = pcg.mg_pcg(H, b, rtol=1e-10, flexible=True)
+    assert std.converged and flex.converged and std.iters == flex.iters
+    np.testing.assert_allclose(flex.z, std.z, rtol=1e-8)
+    # the correction term it subtracts is at rounding level here
+    np.testing.assert_allclose(flex.history, std.history, rtol=1e-6)
+
+
 @pytest.mark.parametrize("nel,levels", [((32, 16), 4), ((8, 4, 4), 3)])
 def test_mg_pcg_matches_direct_within_bound(nel, levels):
     g, K0, x = _setup(nel, lo=1e-3)
