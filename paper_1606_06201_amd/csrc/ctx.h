@@ -43,6 +43,12 @@ struct Ops {
   // Levels 0..tail_top of the V-cycle in one single-workgroup launch:
   // lev[tail_top].r -> lev[tail_top].z.
   virtual void tail(Ctx& c, int op, const int* gate) = 0;
+  // Fused passes of level lev (see fused2d.h): false when they do not apply.
+  //   down: lev.r -> z2 (into z), coarse residual (into lev-1 .r)
+  //   up:   z2 (in z), coarse correction zc -> out
+  virtual bool fused_applies(const Ctx& c, int lev, int op) const = 0;
+  virtual void fused_down(Ctx& c, int lev, const int* gate) = 0;
+  virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
   // Interior point kernels (FP64).
   virtual void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi,
@@ -69,6 +75,7 @@ struct Ctx {
   bool coarse_from_x = true;   // 2D K: first coarse level evaluated from the fine densities
   bool tiled2d = true;         // 2D level passes with register-blocked tiles
   int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
+  bool fused2d = true;         // 2D K levels with stored operators: two fused launches per level
 
   double K0[576] = {0};        // host copy of the element matrix
   int nd = 8;                  // DOFs per element

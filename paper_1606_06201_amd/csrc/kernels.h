@@ -378,10 +378,16 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 #pragma unroll
   for (int q = 0; q < NN; ++q) {
     const int ex = q & 1, ey = (q >> 1) & 1, ez = (q >> 2) & 1;
-    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    // Elements outside the grid contribute nothing.  Off the interior they are
+    // replaced by element 0 with zero vertex values and a masked diagonal, so the
+    // loads of all elements are issued without branches.
+    bool ok = true;
     if constexpr (!INTERIOR) {
-      const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && (DIM == 2 || (ek >= 0 && ek < d.nz));
-      if (!ok) continue;
+      ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && (DIM == 2 || (ek >= 0 && ek < d.nz));
+      ei = ok ? ei : 0;
+      ej = ok ? ej : 0;
+      ek = ok ? ek : 0;
     }
     const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
     const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
@@ -392,11 +398,22 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
         const int nb = nb_index<DIM>(ex + loc_x(b) - 1, ey + loc_y(b) - 1,
                                      DIM == 3 ? ez + loc_z(b) - 1 : 0);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = vn[nb][c];
+        for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = ok ? vn[nb][c] : T(0);
       }
       op.rows(e, ei, ej, ek, a, ve, acc);
     }
-    if constexpr (DIAG) op.diag(e, ei, ej, ek, a, dg);
+    if constexpr (DIAG) {
+      if constexpr (INTERIOR) {
+        op.diag(e, ei, ej, ek, a, dg);
+      } else {
+        T dt[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) dt[c] = T(0);
+        op.diag(e, ei, ej, ek, a, dt);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) dg[c] += ok ? dt[c] : T(0);
+      }
+    }
   }
 }
 

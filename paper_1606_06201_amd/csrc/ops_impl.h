@@ -6,6 +6,7 @@
 #include "ctx.h"
 #include "kernels.h"
 #include "tail.h"
+#include "fused2d.h"
 
 namespace ipmg {
 
@@ -505,6 +506,45 @@ struct OpsImpl : Ops {
       k_prolong<DIM, float><<<node_grid(f), BS, 0, c.stream>>>(f, cd, (float*)z, (const float*)zc, aug, gate);
     else
       k_prolong<DIM, double><<<node_grid(f), BS, 0, c.stream>>>(f, cd, (double*)z, (const double*)zc, aug, gate);
+  }
+
+  bool fused_applies(const Ctx& c, int lev, int op) const override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      return c.fused2d && op == IPMG_OP_K && c.desc.nu_pre == 2 && c.desc.nu_post == 2 && lev >= 1 &&
+             lev < c.L - 1 && !(lev == c.L - 2 && c.coarse_from_x) && lev > c.tail_top;
+    }
+  }
+  template <typename T>
+  void fused_down_t(Ctx& c, int lev, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
+    k_down2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
+                                                           (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
+                                                           (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+  }
+  template <typename T>
+  void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
+    k_up2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
+                                                         (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
+                                                         (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+  }
+  void fused_down(Ctx& c, int lev, const int* gate) override {
+    if constexpr (DIM == 2) {
+      if (c.fp32) fused_down_t<float>(c, lev, gate);
+      else fused_down_t<double>(c, lev, gate);
+    }
+  }
+  void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) override {
+    if constexpr (DIM == 2) {
+      if (c.fp32) fused_up_t<float>(c, lev, zc, out, gate);
+      else fused_up_t<double>(c, lev, zc, out, gate);
+    }
   }
 
   template <class Op>

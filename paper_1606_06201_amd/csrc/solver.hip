@@ -107,6 +107,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   // it), so the default keeps one launch per pass.
   if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_TILED_MIN_NODES")) c.tiled_min_nodes = std::max<int64_t>(0, std::atoll(e));
   c.tail_top = -1;
   if (const char* e = std::getenv("IPMG_TAIL")) {
@@ -304,6 +305,12 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
     if (c.fp32) dense_solve<float>(c.stream, c.dAi, n, (const float*)l.r, (float*)l.z, gate);
     else dense_solve<double>(c.stream, c.dAi, n, (const double*)l.r, (double*)l.z, gate);
     return l.z;
+  }
+  if (!beta64 && c.ops->fused_applies(c, k, op)) {
+    c.ops->fused_down(c, k, gate);                                            // two sweeps, residual, P'
+    void* vc = vcycle_level(c, op, k - 1, gate, nullptr);
+    c.ops->fused_up(c, k, vc, l.z2, gate);                                    // P, two sweeps
+    return l.z2;
   }
   void* cur = l.z;
   void* nxt = l.z2;

@@ -58,8 +58,12 @@ def _kproblem(nel, seed=5, lo=1e-2):
 
 
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 3, False, 1e-11), ((8, 4, 4), 2, False, 1e-11),
-                                                  ((32, 16), 4, True, 2e-4), ((8, 8, 4), 3, True, 2e-4)])
+                                                  ((32, 16), 4, True, 2e-4), ((8, 8, 4), 3, True, 2e-4),
+                                                  ((128, 64), 4, False, 1e-11), ((128, 64), 5, True, 2e-4),
+                                                  ((96, 48), 4, False, 1e-11)])
 def test_vcycle_matches_oracle(nel, levels, fp32, tol):
+    # (128, 64) and (96, 48): the fused passes of the stored 2D levels run on several
+    # tiles per level with ragged last tiles.
     g, K0, x = _kproblem(nel)
     H = mg.kstiffness_hierarchy(g, x, K0, levels)
     r = np.random.default_rng(6).standard_normal(g.nslots)
@@ -198,9 +202,10 @@ def test_element_sensitivities_match_oracle():
 
 
 @pytest.mark.parametrize("env,val", [("IPMG_TAIL", "1"), ("IPMG_STORED_COARSE", "1"),
-                                     ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1")])
+                                     ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
-                                                  ((8, 4, 4), 3, False, 1e-11)])
+                                                  ((8, 4, 4), 3, False, 1e-11), ((128, 64), 4, False, 1e-11),
+                                                  ((128, 64), 4, True, 2e-4)])
 def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol, monkeypatch):
     # Opt-in execution paths (single-workgroup coarse tail; stored first coarse level;
     # register-blocked 2D tiles on every level; one node per thread everywhere) must
