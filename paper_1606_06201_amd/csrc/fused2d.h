@@ -1,4 +1,5 @@
-// Fused passes of the 2D V-cycle on a level k with stored coarse operators, for
+// Fused passes of the 2D V-cycle on a coarse level k (stored operators, or the
+// first coarse level formed from the densities), for
 // Algorithm MG with two pre- and two post-smoothing sweeps of damped Jacobi
 // (Sec. 5.1, Sec. 7):
 //   k_down2d: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1), t = r - A z2, rc = P' t

@@ -274,14 +274,16 @@ struct OpCoarse2K {
     xq[2] = x[b + fnx];
     xq[3] = x[b + fnx + 1];
   }
-  // The sub-element loop stays rolled so that only the 16 constants of one G_q
-  // row block are live in scalar registers at a time.
+  // The four densities are loaded before the sub-element loop, which stays rolled
+  // so that only the 16 constants of one G_q row block are live in scalar
+  // registers at a time.
   __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
-    const int64_t b = (int64_t)(2 * ej) * fnx + 2 * ei;
+    T xv[4];
+    xs(ei, ej, xv);
     T s0 = 0, s1 = 0;
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
-      const T xq = x[b + (q >> 1) * fnx + (q & 1)];
+      const T xq = q == 0 ? xv[0] : q == 1 ? xv[1] : q == 2 ? xv[2] : xv[3];
       const int r0 = q * 64 + (a * 2) * 8;
       T t0 = 0, t1 = 0;
 #pragma unroll

@@ -512,8 +512,11 @@ struct OpsImpl : Ops {
     if constexpr (DIM != 2) {
       return false;
     } else {
+      // The first coarse level formed from the densities is VALU-bound: fused (with
+      // its recomputed halos) it pays in FP32 only.
+      const bool from_x = lev == c.L - 2 && c.coarse_from_x;
       return c.fused2d && op == IPMG_OP_K && c.desc.nu_pre == 2 && c.desc.nu_post == 2 && lev >= 1 &&
-             lev < c.L - 1 && !(lev == c.L - 2 && c.coarse_from_x) && lev > c.tail_top;
+             lev < c.L - 1 && lev > c.tail_top && (!from_x || c.fp32);
     }
   }
   template <typename T>
@@ -521,18 +524,28 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
-    k_down2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
-                                                           (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
-                                                           (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+    if (lev == c.L - 2 && c.coarse_from_x)
+      k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
+                                                               (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
+                                                               (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+    else
+      k_down2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
+                                                             (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
+                                                             (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
   }
   template <typename T>
   void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
-    k_up2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
-                                                         (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
-                                                         (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+    if (lev == c.L - 2 && c.coarse_from_x)
+      k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
+                                                             (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
+                                                             (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+    else
+      k_up2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
+                                                           (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
+                                                           (const T*)zc, (T*)out, c.omega_dev + lev, gate);
   }
   void fused_down(Ctx& c, int lev, const int* gate) override {
     if constexpr (DIM == 2) {
