@@ -111,7 +111,9 @@ typedef struct {
   double volume_res;  /* sum x - V after the step                                  */
   double compliance;  /* f'u after the step                                        */
   int pcg_iters;      /* PCG iterations of the Newton system                       */
-  int pcg_status;
+  int pcg_status;     /* IPMG_OK, or IPMG_E_NOT_CONVERGED / IPMG_E_BREAKDOWN when the
+                         solve stopped early: the step then used the last PCG
+                         iterate as an inexact Newton direction                     */
   int barrier_updated;/* 1 if s, r were multiplied by sigma after this step        */
   int converged;      /* 1 if the stop rule holds                                  */
   double setup_ms, solve_ms;
@@ -196,6 +198,7 @@ int ipmg_ip_prepare(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm,
 /* One Newton step (Sec. 3.1 steps 1-4): prepare, MG-PCG on Z, recovery of d_x,
  * d_phi, d_psi, step length (Sec. 3.3), update, Newton test and barrier update
  * (Sec. 3.2, 3.4), stop rule.  Updates st in place.  info: [host] may be NULL.
+ * A Newton solve that stops early does not fail the step (see pcg_status).
  * Returns IPMG_OK, IPMG_E_STALLED, IPMG_E_DOMAIN (non-finite iterate) or an error. */
 int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
                  ipmg_ip_info* info);

@@ -24,9 +24,13 @@ Readings where the paper is silent (shared with the GPU path):
     rho near 4).  Every non-coarsest level therefore uses
     omega_k = min(omega, SAFE_PRODUCT / rho_k), rho_k the Rayleigh-quotient
     estimate of the largest eigenvalue of D_k^-1 A_k after POWER_STEPS power
-    iterations from the vector (-1)^(i+j+k) (1 + c) on DOF component c of node
-    (i, j, k) (and 1 on lambda).  For 2D K(x), rho stays near 2.2-2.6, so
-    omega = 0.6 is kept there.
+    iterations (POWER_STEPS_Z for the augmented system) from the vector
+    (-1)^(i+j+k) (1 + c) on DOF component c of node (i, j, k) (and 1 on lambda).
+    For 2D K(x), rho stays near 2.2-2.6, so omega = 0.6 is kept there.  The top
+    of the spectrum of D^-1 Z late in a 3D interior-point run is a cluster of
+    element-local modes of the rank-one terms, which power iteration approaches
+    slowly from below: 12 steps gave rho = 6.2 where the value is about 7.9, so
+    omega * rho > 2 and PCG broke down; 30 steps stay within SAFE_PRODUCT / 2.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -71,6 +75,7 @@ def prolongation_free(fine, coarse):
 
 SAFE_PRODUCT = 1.6
 POWER_STEPS = 12
+POWER_STEPS_Z = 30
 
 
 def power_start(grid, augmented):
@@ -125,7 +130,8 @@ class Hierarchy:
         self.rho = [None] * levels
         if safeguard:
             for k in range(1, levels):
-                self.rho[k] = jacobi_radius(A[k], self.diag[k], power_start(grids[k], augmented))
+                self.rho[k] = jacobi_radius(A[k], self.diag[k], power_start(grids[k], augmented),
+                                            POWER_STEPS_Z if augmented else POWER_STEPS)
                 self.omega[k] = min(omega, SAFE_PRODUCT / self.rho[k])
 
 

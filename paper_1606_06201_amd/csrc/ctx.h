@@ -76,6 +76,8 @@ struct Ctx {
   bool tiled2d = true;         // 2D level passes with register-blocked tiles
   int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
   bool fused2d = true;         // 2D K levels with stored operators: two fused launches per level
+  int power_steps = 12;        // power iterations of the damping estimate (K)
+  int power_steps_z = 30;      // ... (augmented system Z)
 
   double K0[576] = {0};        // host copy of the element matrix
   int nd = 8;                  // DOFs per element

@@ -34,6 +34,11 @@ void dfree(P*& p) {
 // elasticity and on the augmented system Z late in the interior-point run.
 constexpr double SAFE_PRODUCT = 1.6;
 constexpr int POWER_STEPS = 12;
+// The augmented system Z: the top of the spectrum of D^-1 Z late in a 3D
+// interior-point run is a cluster of element-local modes of the rank-one terms,
+// which power iteration approaches slowly from below (12 steps: rho = 6.2 where
+// it is about 7.9, so omega * rho > 2 and PCG broke down).
+constexpr int POWER_STEPS_Z = 30;
 
 }  // namespace
 
@@ -108,6 +113,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
+  c.power_steps = POWER_STEPS;
+  c.power_steps_z = POWER_STEPS_Z;
   if (const char* e = std::getenv("IPMG_TILED_MIN_NODES")) c.tiled_min_nodes = std::max<int64_t>(0, std::atoll(e));
   c.tail_top = -1;
   if (const char* e = std::getenv("IPMG_TAIL")) {
@@ -238,7 +245,8 @@ static void jacobi_damping(Ctx& c, int k, int op) {
   void* v = l.z;
   void* w = l.z2;
   int sin = -1, sout = S_TMP4;
-  for (int it = 0; it < POWER_STEPS; ++it) {
+  const int steps = op == IPMG_OP_Z ? c.power_steps_z : c.power_steps;
+  for (int it = 0; it < steps; ++it) {
     c.ops->level(c, k, op, M_POWER, v, nullptr, w, nullptr, sout, sin, nullptr);
     std::swap(v, w);
     sin = sout;
@@ -526,8 +534,10 @@ int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st,
   mg_setup(c, IPMG_OP_Z, &setup_ms);
   IPMG_HIP(hipMemsetAsync(c.ipD, 0, sizeof(double) * (d.nslots + 1), c.stream));
   ipmg_pcg_info pin{};
+  // A solve that stops early (iteration limit, or a breakdown of the recurrence)
+  // leaves its last iterate in ipD: an inexact Newton direction, which the step
+  // length and the following steps accept (Sec. 6, stopping rule).
   const int ps = pcg(c, IPMG_OP_Z, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, &pin);
-  if (ps == IPMG_E_BREAKDOWN) return ps;
   inf.pcg_iters = pin.iters;
   inf.pcg_status = ps;
   inf.setup_ms = setup_ms;

@@ -1,0 +1,151 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (default solver settings, same level counts and
+inputs).  The oracle checks what it can afford at these sizes: its own assembled
+operator applied to the GPU results (residual certificates), its FP64 MG-PCG at
+1024x512, its direct-solve adjoint gradient at 512x256, and properties of the
+V-cycle that hold at any size."""
+import numpy as np
+import pytest
+
+from oracle import fem, mg, pcg as opcg, sens
+from tests.gpu_util import T, N, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(workload):
+    from paper_1606_06201_amd import inputs
+    w = inputs.WORKLOADS[workload]
+    nel, levels = w["nel"], w["levels"]
+    g = fem.Grid(nel)
+    K0 = fem.element_stiffness(2)
+    x = inputs.density_for(workload)
+    f = fem.load_vector(g, inputs.point_load(nel))
+    return nel, levels, g, K0, x, f
+
+
+def _certificate(K, g, f, u):
+    ff = fem.to_free(g, f)
+    return float(np.linalg.norm(ff - K @ fem.to_free(g, u)) / np.linalg.norm(ff))
+
+
+def test_fp64_solve_1024x512_matches_oracle_mg_pcg():
+    # 1024x512 Q1 cantilever, Gaussian-random-field densities in [1e-3, 1], 7 levels.
+    from paper_1606_06201_amd import Solver
+    nel, levels, g, K0, x, f = _setup("grf1024x512")
+    s = Solver(nel, levels, fp32=False)
+    s.set_density(T(x))
+    u, info = s.pcg(T(f), rtol=1e-8)
+    u = N(u)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-8
+    K = fem.stiffness_free(g, x, K0)
+    assert _certificate(K, g, f, u) <= 1.01e-8
+    H = mg.Hierarchy(g, K, levels)
+    ref = opcg.mg_pcg(H, fem.to_free(g, f), rtol=1e-8)
+    assert ref.converged
+    assert abs(info["iters"] - ref.iters) <= 1, (info["iters"], ref.iters)
+    c, c_ref = float(f @ u), float(fem.to_free(g, f) @ ref.z)
+    assert abs(c - c_ref) <= 1e-7 * abs(c_ref)
+
+
+def test_mixed_and_fp64_2048x1024_certified():
+    # The benchmark workload: 2048x1024, thresholded {1e-6, 1} densities, 8 levels.
+    from paper_1606_06201_amd import Solver
+    nel, levels, g, K0, x, f = _setup("thr2048x1024")
+    K = fem.stiffness_free(g, x, K0)
+    res = {}
+    for fp32 in (True, False):
+        s = Solver(nel, levels, fp32=fp32)
+        s.set_density(T(x))
+        u, info = s.pcg(T(f), rtol=1e-8, maxit=1000)
+        u = N(u)
+        assert info["status"] == 0 and info["true_relres"] <= 1e-8, info
+        assert _certificate(K, g, f, u) <= 1.01e-8
+        res[fp32] = (u, float(f @ u))
+        if not fp32:
+            # operator apply at full size against the oracle's assembled K
+            v = np.random.default_rng(21).standard_normal(g.nslots)
+            v[g.clamped_mask()] = 0
+            y = N(s.apply_K(T(v)))
+            assert relerr(fem.to_free(g, y), K @ fem.to_free(g, v)) < 1e-13
+    # compliance of the mixed-precision solve within 1e-6 of the FP64 one
+    assert abs(res[True][1] - res[False][1]) <= 1e-6 * abs(res[False][1])
+    assert relerr(res[True][0], res[False][0]) < 1e-5
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_vcycle_properties_2048x1024(fp32):
+    # Properties of Algorithm MG with R = P', equal pre/post sweeps and an exact
+    # coarse solve, at the benchmark size: the V-cycle is a symmetric positive
+    # definite operator (FP64 to rounding; FP32 to its precision), linear, and the
+    # FP32 V-cycle approximates the FP64 one.
+    from paper_1606_06201_amd import Solver
+    nel, levels, g, K0, x, f = _setup("thr2048x1024")
+    s = Solver(nel, levels, fp32=fp32)
+    s.set_density(T(x))
+    s.mg_setup()
+    rng = np.random.default_rng(22)
+    r1, r2 = rng.standard_normal(g.nslots), rng.standard_normal(g.nslots)
+    r1[g.clamped_mask()] = 0
+    r2[g.clamped_mask()] = 0
+    z1, z2 = N(s.vcycle(T(r1))), N(s.vcycle(T(r2)))
+    z12 = N(s.vcycle(T(r1 + 2.0 * r2)))
+    a, b = float(r2 @ z1), float(r1 @ z2)
+    tol = 1e-10 if not fp32 else 1e-4
+    assert abs(a - b) <= tol * np.sqrt(abs(float(r1 @ z1)) * abs(float(r2 @ z2)))
+    assert float(r1 @ z1) > 0 and float(r2 @ z2) > 0
+    assert relerr(z12, z1 + 2.0 * z2) < (1e-12 if not fp32 else 1e-5)
+    assert np.all(z1[g.clamped_mask()] == 0)
+    if fp32:
+        s64 = Solver(nel, levels, fp32=False)
+        s64.set_density(T(x))
+        s64.mg_setup()
+        assert relerr(z1, N(s64.vcycle(T(r1)))) < 1e-3
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_adjoint_gradient_512x256(fp32):
+    # J = g'u + f'u on 512x256 with uniform densities in [0.01, 1]: the GPU
+    # gradient against the oracle's direct-solve adjoint gradient, and central
+    # finite differences on 32 sampled elements.  FP64 PCG attains a true relative
+    # residual near 1e-11 at this size (1e-12 is out of reach), so J carries noise
+    # of that relative size and a difference quotient with step h carries noise
+    # proportional to 1/h: measured 4e-3 of the largest gradient entry at
+    # h = 1e-6 and 2.4e-5 at h = 1e-4 (truncation error O(h^2) is below both).
+    # h = 1e-6 is checked at 1e-2, h = 1e-4 at 1e-4.
+    import torch
+    from paper_1606_06201_amd import Solver, solve_K, inputs
+    nel, levels = (512, 256), 6
+    g = fem.Grid(nel)
+    K0 = fem.element_stiffness(2)
+    x = inputs.density_uniform(nel, seed=3)
+    f = fem.load_vector(g, inputs.point_load(nel))
+    gv = inputs.normal_slots(g.nslots, seed=33)
+    gv[g.clamped_mask()] = 0
+    s = Solver(nel, levels, fp32=fp32)
+    xt = T(x).requires_grad_(True)
+    u = solve_K(xt, T(f), s, rtol=1e-11)
+    J = torch.dot(T(gv), u) + torch.dot(T(f), u)
+    J.backward()
+    grad = N(xt.grad)
+    J_o, grad_o, _, _ = sens.linear_objective_gradient(g, x, K0, f, gv)
+    assert abs(float(J) - J_o) <= 1e-9 * abs(J_o)
+    assert relerr(grad, grad_o) < 1e-7
+    # Euler identity sum_e x_e dJ/dx_e = -(g'u + f'u) (J is homogeneous of degree -1 in x)
+    assert abs(float(np.dot(x, grad)) + J_o) <= 1e-8 * abs(J_o)
+    picks = inputs.sample_elements(g.m, 32, seed=333)
+
+    def J_at(xv):
+        s.set_density(T(xv))
+        uu, _ = s.pcg(T(f), rtol=1e-11)
+        return float(np.dot(gv + f, N(uu)))
+
+    scale = np.max(np.abs(grad[picks]))
+    for h, tol in ((1e-6, 1e-2), (1e-4, 1e-4)):
+        fd = []
+        for e in picks:
+            xp, xm = x.copy(), x.copy()
+            xp[e] += h
+            xm[e] -= h
+            fd.append((J_at(xp) - J_at(xm)) / (2 * h))
+        assert np.max(np.abs(np.array(fd) - grad[picks])) <= tol * scale, h
