@@ -101,16 +101,22 @@ class Problem:
         ue = self.elem(u)
         return np.einsum("ei,ij,ej->e", ue, self.K0, ue)
 
-    def residuals(self, st):
-        F1 = self.K(st.x) @ st.u - self.f
+    def residuals(self, st, matrix_free=False):
+        """F1..F5 (Sec. 2).  matrix_free: K(x) u element by element instead of the
+        assembled matrix (same sum; for grids too large to assemble)."""
+        if matrix_free:
+            Ku = fem.apply_free_masked(self.grid, st.x, self.K0, fem.to_slots(self.grid, st.u))
+            F1 = fem.to_free(self.grid, Ku) - self.f
+        else:
+            F1 = self.K(st.x) @ st.u - self.f
         F2 = float(st.x.sum() - self.V)
         F3 = -0.5 * self.energies(st.u) - st.lam - st.phi + st.psi
         F4 = st.phi * st.x - st.s
         F5 = st.psi * (self.xbar - st.x) - st.r
         return F1, F2, F3, F4, F5
 
-    def measures(self, st):
-        F1, F2, F3, F4, F5 = self.residuals(st)
+    def measures(self, st, matrix_free=False):
+        F1, F2, F3, F4, F5 = self.residuals(st, matrix_free)
         xt = self.xbar - st.x
         G3 = F3 + F4 / st.x - F5 / xt
         nphi, npsi = np.linalg.norm(st.phi), np.linalg.norm(st.psi)

@@ -197,3 +197,18 @@ def test_ip_64x32_mg_matches_direct():
     assert abs(out["mg"][0] - out["direct"][0]) <= 1
     assert out["mg"][1] == out["direct"][1]
     assert abs(out["mg"][2] - out["direct"][2]) <= 1e-6 * out["direct"][2]
+
+
+def test_matrix_free_measures_equal_assembled():
+    # The element-by-element residual (for grids too large to assemble) equals
+    # the assembled one.
+    from paper_1606_06201_amd import inputs
+    nel = (6, 4, 4)
+    g = fem.Grid(nel)
+    K0 = fem.element_stiffness(3)
+    prob = ip.Problem(g, K0, fem.load_vector(g, inputs.point_load(nel)), 0.3 * g.m, 1.0)
+    rng = np.random.default_rng(4)
+    st = ip.IPState(rng.standard_normal(len(prob.f)), 0.4, rng.uniform(0.1, 0.9, g.m),
+                     rng.uniform(0.5, 2, g.m), rng.uniform(0.5, 2, g.m), 0.1, 0.1)
+    a, b = prob.measures(st), prob.measures(st, matrix_free=True)
+    np.testing.assert_allclose(a, b, rtol=1e-13)
