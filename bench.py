@@ -124,6 +124,63 @@ def cpu_baseline(nel, levels, x, f, iters=40):
     }
 
 
+def bench_secondary(args, w, dev):
+    """Interior-point runs (kind "ip") and adjoint gradients (kind "adjoint"): the
+    FP32 V-cycle against the plain FP64 path, one JSON line.  The roofline and
+    the oracle baseline belong to the MG-PCG workload and are null here."""
+    import numpy as np
+    import torch
+    from paper_1606_06201_amd import Solver, inputs, solve_K
+    nel, levels = w["nel"], w["levels"]
+    res = {}
+    for fp32 in (True, False):
+        s = Solver(nel, levels, fp32=fp32, device=dev)
+        f = s.load_vector(inputs.point_load(nel))
+        n_free = s.n_free
+        times, info = [], None
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if w["kind"] == "ip":
+                params = s.ip_params(w["vfrac"] * s.m, w["xbar"], stop="kkt", kkt_tol=1e-6)
+                gst, log = s.ip_run(f, params)
+                info = {"newton": log["newton"], "barrier_updates": log["barrier_updates"],
+                        "pcg_iters": int(sum(log["pcg_iters"])), "status": log["status"],
+                        "compliance": float(torch.dot(f, gst["u"]))}
+            else:
+                x = torch.from_numpy(inputs.density_for(args.workload)).to(dev).requires_grad_(True)
+                gv = torch.from_numpy(inputs.normal_slots(s.n_slots, seed=33)).to(dev)
+                u = solve_K(x, f, s, rtol=1e-8)
+                J = torch.dot(gv, u) + torch.dot(f, u)
+                J.backward()
+                info = {"J": float(J)}
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+            print(f"[bench] {args.workload} {'mixed' if fp32 else 'fp64'} run {rep}: "
+                  f"{time.perf_counter() - t0:.3f}s {info}", file=sys.stderr, flush=True)
+        info["seconds"] = float(np.mean(times))
+        res["mixed" if fp32 else "fp64"] = info
+    mixed, fp64 = res["mixed"], res["fp64"]
+    if w["kind"] == "ip":
+        metric = "interior-point run to KKT 1e-6: PCG DOF-iters/s (FP32 V-cycle vs FP64)"
+        value = n_free * mixed["pcg_iters"] / mixed["seconds"]
+        unit = "DOF-iters/s"
+    else:
+        metric = "adjoint gradient evaluations/s (solve + adjoint solve + sensitivities, rtol 1e-8)"
+        value = 1.0 / mixed["seconds"]
+        unit = "gradients/s"
+    out = {
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * mixed["seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": args.workload, "elements": list(nel), "free_dofs": n_free, "levels": levels},
+        "mixed": mixed, "fp64": fp64, "mixed_speedup_vs_fp64": fp64["seconds"] / mixed["seconds"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +217,9 @@ def main():
         return
 
     w = inputs.WORKLOADS[args.workload]
+    if w["kind"] in ("ip", "adjoint"):
+        bench_secondary(args, w, dev)
+        return
     nel, levels = w["nel"], w["levels"]
     x_h = inputs.density_for(args.workload)
     f_h = None
