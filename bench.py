@@ -36,8 +36,12 @@ KERNEL_NAMES = {
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
                   "Galerkin element matrices formed from the fine densities on the fly",
-    "dir_apply": "k_dir_apply<2, float, OpFineK<2,double>>: p = -y + beta p, q = K p (FP64), p'q",
+    "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 2>: p = -y + beta p, q = K p (FP64), p'q",
     "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
+    "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
+                "restriction in one LDS-tiled pass",
+    "sub_up": "k_up2d<float, OpCoarse2K<2,float>>: first coarse level, prolongation and two Jacobi sweeps in "
+              "one LDS-tiled pass",
 }
 
 
@@ -57,6 +61,11 @@ def class_bytes(nel, fp32, kind):
         return 3 * 2 * w * N + w * m + 2 * 8 * N
     if kind == "sub_jacobi":                    # read z, r; write z'; read the fine x (4 per coarse element)
         return 3 * 2 * w * Nc + w * m
+    Nc2 = (nx // 4 + 1) * (ny // 4 + 1)    # second coarse level nodes
+    if kind == "sub_down":                      # read r, fine x; write z2, coarse residual
+        return 2 * w * Nc + w * m + 2 * w * Nc + 2 * w * Nc2
+    if kind == "sub_up":                        # read z2, r, coarse correction, fine x; write z
+        return 3 * 2 * w * Nc + 2 * w * Nc2 + w * m
     if kind == "dir_apply":                     # read y, p_old; write p, q (FP64); read x (FP64)
         return 2 * N * (w + 3 * 8) + 8 * m
     if kind == "pcg_update":                    # read z, r, p, q; write z, r (FP64); write r (V-cycle)

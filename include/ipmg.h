@@ -214,6 +214,8 @@ int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg
  *   4: damped-Jacobi sweep on the first coarse level from a nonzero iterate
  *   5: first damped-Jacobi sweep on the finest level (zero iterate)
  *   6: last post-smoothing sweep on the finest level with the fused PCG ratio
+ *   7: fused pre-smoothing, residual and restriction on the first coarse level
+ *   8: fused prolongation and post-smoothing on the first coarse level
  * Launches skipped on device after convergence are recorded too (with near-zero
  * duration).  max_launches: event pairs to keep (further launches are not timed).
  * durations_ms: [host] capacity entries, each launch's duration; classes: [host,

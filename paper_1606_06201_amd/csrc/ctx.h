@@ -138,7 +138,9 @@ enum ProfClass {
   PC_SUB_JACOBI = 4,        // first coarse level, damped-Jacobi sweep from a nonzero iterate
   PC_FINE_JACOBI0 = 5,      // finest level, first sweep from a zero iterate
   PC_FINE_JACOBI_BETA = 6,  // finest level, last sweep with the fused PCG ratio
-  PC_COUNT = 7
+  PC_SUB_DOWN = 7,          // first coarse level, fused pre-smoothing + residual + restriction
+  PC_SUB_UP = 8,            // first coarse level, fused prolongation + post-smoothing
+  PC_COUNT = 9
 };
 
 // Sets the class of the level passes enqueued in its scope.

@@ -524,6 +524,7 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
+    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
     if (lev == c.L - 2 && c.coarse_from_x)
       k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
                                                                (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
@@ -538,6 +539,7 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
+    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
     if (lev == c.L - 2 && c.coarse_from_x)
       k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
                                                              (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
