@@ -75,7 +75,10 @@ struct Ctx {
   bool coarse_from_x = true;   // 2D K: first coarse level evaluated from the fine densities
   bool tiled2d = true;         // 2D level passes with register-blocked tiles
   int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
+  int nj32 = 4, nj64 = 2, nj_dir = 4;          // nodes per thread of the tiled passes
   bool fused2d = true;         // 2D K levels with stored operators: two fused launches per level
+  bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32; stored levels
+  int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
   int power_steps = 12;        // power iterations of the damping estimate (K)
   int power_steps_z = 30;      // ... (augmented system Z)
 

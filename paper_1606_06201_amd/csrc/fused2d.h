@@ -1,13 +1,19 @@
 // Fused passes of the 2D V-cycle on a coarse level k (stored operators, or the
-// first coarse level formed from the densities), for
-// Algorithm MG with two pre- and two post-smoothing sweeps of damped Jacobi
-// (Sec. 5.1, Sec. 7):
-//   k_down2d: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1), t = r - A z2, rc = P' t
-//   k_up2d:   z = z2 + P zc, z3 = z + w D^-1 (r - A z), out = z3 + w D^-1 (r - A z3)
+// first coarse level formed from the densities), for Algorithm MG with two pre-
+// and two post-smoothing sweeps of damped Jacobi (Sec. 5.1, Sec. 7):
+//   down: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1), t = r - A z2, rc = P' t
+//   up:   z = z2 + P zc, z3 = z + w D^-1 (r - A z), out = z3 + w D^-1 (r - A z3)
 // Each workgroup computes one tile of the level in LDS together with the halo
 // each later step needs (recomputed by neighbouring tiles), so the two launches
 // replace seven on levels where a launch costs more than the work.  Arithmetic per
 // node is that of k_level (same operator rows, diagonal and reciprocal).
+//   k_down2d / k_up2d: any operator, read from global memory (16x8 coarse-node
+//     and 32x16 fine-node tiles, 1024 threads: every phase is one pass);
+//   k_down2d_staged / k_up2d_staged: the FP32 element matrices of the tile's
+//     elements placed in LDS first (copied from the stored ones, or formed from the
+//     densities on the first coarse level), so the phases wait on LDS only and, on
+//     the first coarse level, each element matrix is formed once per tile instead
+//     of once per node evaluation (8x4 and 16x8 tiles, 256 threads).
 #pragma once
 #include "kernels.h"
 
@@ -15,7 +21,10 @@ namespace ipmg {
 
 constexpr int FCX = 16, FCY = 8;    // coarse nodes per k_down2d tile
 constexpr int FTX = 32, FTY = 16;   // fine nodes per k_up2d tile
-constexpr int FBS = 1024;   // every phase of a tile is one pass of the workgroup
+constexpr int FBS = 1024;           // every phase of a tile is one pass of the workgroup
+constexpr int SCX = 8, SCY = 4;     // coarse nodes per k_down2d_staged tile
+constexpr int STX = 16, STY = 8;    // fine nodes per k_up2d_staged tile
+constexpr int SBS = 256;
 
 __device__ inline bool node_free(const Dims& d, int i, int j) { return i >= 1 && i < d.nx1 && j >= 0 && j < d.ny1; }
 
@@ -32,21 +41,105 @@ __device__ inline void lds_neighbourhood(const T* s, int W, int li, int lj, T (&
     }
 }
 
-// Grid: (ceil(dc.nx1 / FCX), ceil(dc.ny1 / FCY)); d is level k, dc level k-1.
-template <typename T, class Op>
-__global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
-                                                T* __restrict__ z2out, T* __restrict__ rc,
-                                                const double* __restrict__ omg, const int* gate) {
-  if (gate && *gate) return;
-  constexpr int W1 = 2 * FCX + 5, H1 = 2 * FCY + 5;   // region of r, D and z1
-  constexpr int W2 = W1 - 2, H2 = H1 - 2;             // region of z2
-  constexpr int W3 = W1 - 4, H3 = H1 - 4;             // region of t
-  __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
-  const T omega = T(*omg);
-  const Tile tl = xcd_tile();
-  const int CI0 = (int)tl.x * FCX, CJ0 = (int)tl.y * FCY;
-  const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;      // origin of region 1 (fine node indices)
-  for (int t = threadIdx.x; t < W1 * H1; t += FBS) {
+// Stored element matrices of a block of elements held in LDS: E[sym * ne + le],
+// le = (ej - ey0) * lw + (ei - ex0).  Elements outside the block (which the masked
+// element loop of node_apply only produces for elements outside the grid) read a
+// clamped local index; their contribution is masked there.
+template <typename T>
+struct OpCoarseLDS {
+  const T* E;
+  int ex0, ey0, lw, ne;
+  __device__ inline int local(int ei, int ej) const {
+    const int le = (ej - ey0) * lw + (ei - ex0);
+    return le < 0 ? 0 : (le >= ne ? ne - 1 : le);
+  }
+  __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
+    const int le = local(ei, ej);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int r = a * 2 + c;
+      T s = 0;
+#pragma unroll
+      for (int col = 0; col < 8; ++col) s += E[sym_index(r, col, 8) * ne + le] * ve[col];
+      acc[c] += s;
+    }
+  }
+  __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
+    const int le = local(ei, ej);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) dg[c] += E[sym_index(a * 2 + c, a * 2 + c, 8) * ne + le];
+  }
+};
+
+// Copies the stored matrices of elements [ex0, ex0+LW) x [ey0, ey0+LH) of a level
+// into LDS (zero outside the grid).  Every thread issues all of its loads before
+// its first LDS store, so the copy costs one memory latency.
+template <typename T, int NT, int LW, int LH>
+__device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, int ex0, int ey0, T* El) {
+  constexpr int NE = LW * LH, TOTAL = 36 * NE, PER = (TOTAL + NT - 1) / NT;
+  T v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * NT;
+    const int s = t / NE, le = t % NE;
+    const int ei = ex0 + le % LW, ej = ey0 + le / LW;
+    const bool in = t < TOTAL && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+    v[u] = in ? Eg[(int64_t)s * d.m + (int64_t)ej * d.nx + ei] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t < TOTAL) El[t] = v[u];
+  }
+}
+
+// Element matrices of the first coarse level formed from the finest densities
+// (A_C = sum_q x_q G_q over the four fine sub-elements, Sec. 5.1 Galerkin product
+// of the x-scaled unit element) for the elements [ex0, ex0+LW) x [ey0, ey0+LH),
+// written to LDS packed as stage_elements does (zero outside the grid).  One
+// thread per element: four density loads, then 36 entries of 4 FMAs each with the
+// G_q constants.
+template <int NT, int LW, int LH>
+__device__ inline void stage_from_x(const float* __restrict__ x, int fnx, const Dims& d, int ex0, int ey0,
+                                    float* El) {
+  constexpr int NE = LW * LH, PER = (NE + NT - 1) / NT;
+  float xs[PER][4];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int le = threadIdx.x + u * NT;
+    const int ei = ex0 + le % LW, ej = ey0 + le / LW;
+    const bool in = le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+    const int64_t b = in ? (int64_t)(2 * ej) * fnx + 2 * ei : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xs[u][q] = in ? x[b + (q >> 1) * fnx + (q & 1)] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int le = threadIdx.x + u * NT;
+    if (le >= NE) continue;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c = r; c < 8; ++c) {
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += xs[u][q] * g2<float>(q * 64 + r * 8 + c);
+        El[sym_index(r, c, 8) * NE + le] = s;
+      }
+  }
+}
+
+// Down pass of one tile of CX x CY coarse nodes with corner (CI0, CJ0).  LDS:
+// sr, sd, s1 over region 1 ((2CX+5) x (2CY+5) fine nodes from (2CI0-3, 2CJ0-3)),
+// s2 over region 2 (one node inside), s3 over region 3 (two nodes inside).
+template <typename T, class Op, int CX, int CY, int NT>
+__device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, int CI0, int CJ0, const T* r,
+                                 T* z2out, T* rc, T omega, T* sr, T* sd, T* s1, T* s2, T* s3) {
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5;
+  constexpr int W2 = W1 - 2, H2 = H1 - 2;
+  constexpr int W3 = W1 - 4, H3 = H1 - 4;
+  const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
+  for (int t = threadIdx.x; t < W1 * H1; t += NT) {
     const int gi = ox + t % W1, gj = oy + t / W1;
     T rr[2] = {T(0), T(0)}, dg[2] = {T(0), T(0)}, o[2] = {T(0), T(0)};
     if (node_free(d, gi, gj)) {
@@ -60,7 +153,7 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
     for (int c = 0; c < 2; ++c) { sr[2 * t + c] = rr[c]; sd[2 * t + c] = dg[c]; s1[2 * t + c] = o[c]; }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < W2 * H2; t += FBS) {
+  for (int t = threadIdx.x; t < W2 * H2; t += NT) {
     const int li = t % W2 + 1, lj = t / W2 + 1;        // position in region 1
     const int gi = ox + li, gj = oy + lj;
     T o[2] = {T(0), T(0)};
@@ -76,7 +169,7 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
     s2[2 * t + 1] = o[1];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < W3 * H3; t += FBS) {
+  for (int t = threadIdx.x; t < W3 * H3; t += NT) {
     const int li = t % W3 + 1, lj = t / W3 + 1;        // position in region 2
     const int gi = ox + 1 + li, gj = oy + 1 + lj;
     T o[2] = {T(0), T(0)};
@@ -92,8 +185,8 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
     s3[2 * t + 1] = o[1];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < FCX * FCY; t += FBS) {  // rc = P' t on the tile's coarse nodes
-    const int I = CI0 + t % FCX, J = CJ0 + t / FCX;
+  for (int t = threadIdx.x; t < CX * CY; t += NT) {     // rc = P' t on the tile's coarse nodes
+    const int I = CI0 + t % CX, J = CJ0 + t / CX;
     if (I >= dc.nx1 || J >= dc.ny1) continue;
     T acc[2] = {T(0), T(0)};
     if (I > 0) {
@@ -109,8 +202,8 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
     }
     store_node<2, T>(rc, (int64_t)J * dc.nx1 + I, acc);
   }
-  for (int t = threadIdx.x; t < 4 * FCX * FCY; t += FBS) {   // z2 on the fine nodes the tile owns
-    const int gi = 2 * CI0 + t % (2 * FCX), gj = 2 * CJ0 + t / (2 * FCX);
+  for (int t = threadIdx.x; t < 4 * CX * CY; t += NT) {   // z2 on the fine nodes the tile owns
+    const int gi = 2 * CI0 + t % (2 * CX), gj = 2 * CJ0 + t / (2 * CX);
     if (gi >= d.nx1 || gj >= d.ny1) continue;
     const int q = 2 * ((gj - oy - 1) * W2 + gi - ox - 1);
     const T o[2] = {s2[q], s2[q + 1]};
@@ -118,20 +211,15 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
   }
 }
 
-// Grid: (ceil(d.nx1 / FTX), ceil(d.ny1 / FTY)).
-template <typename T, class Op>
-__global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
-                                              const T* __restrict__ z2, const T* __restrict__ zc,
-                                              T* __restrict__ out, const double* __restrict__ omg,
-                                              const int* gate) {
-  if (gate && *gate) return;
-  constexpr int W0 = FTX + 4, H0 = FTY + 4;           // region of z2 + P zc
-  constexpr int W1 = FTX + 2, H1 = FTY + 2;           // region of r, D and z3
-  __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
-  const T omega = T(*omg);
-  const Tile tl = xcd_tile();
-  const int I0 = (int)tl.x * FTX, J0 = (int)tl.y * FTY;
-  for (int t = threadIdx.x; t < W0 * H0; t += FBS) {
+// Up pass of one tile of TX x TY fine nodes with corner (I0, J0).  LDS: s0 over
+// region 0 ((TX+4) x (TY+4) nodes from (I0-2, J0-2)); sr, sd, s1 over region 1
+// (one node inside).
+template <typename T, class Op, int TX, int TY, int NT>
+__device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0, const T* r, const T* z2,
+                               const T* zc, T* out, T omega, T* s0, T* sr, T* sd, T* s1) {
+  constexpr int W0 = TX + 4, H0 = TY + 4;
+  constexpr int W1 = TX + 2, H1 = TY + 2;
+  for (int t = threadIdx.x; t < W0 * H0; t += NT) {
     const int gi = I0 - 2 + t % W0, gj = J0 - 2 + t / W0;
     T o[2] = {T(0), T(0)};
     if (node_free(d, gi, gj)) {
@@ -151,7 +239,7 @@ __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* _
     s0[2 * t + 1] = o[1];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < W1 * H1; t += FBS) {
+  for (int t = threadIdx.x; t < W1 * H1; t += NT) {
     const int li = t % W1, lj = t / W1;                 // position in region 1
     const int gi = I0 - 1 + li, gj = J0 - 1 + lj;
     T rr[2] = {T(0), T(0)}, dg[2] = {T(0), T(0)}, o[2] = {T(0), T(0)};
@@ -168,8 +256,8 @@ __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* _
     for (int c = 0; c < 2; ++c) { sr[2 * t + c] = rr[c]; sd[2 * t + c] = dg[c]; s1[2 * t + c] = o[c]; }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < FTX * FTY; t += FBS) {
-    const int gi = I0 + t % FTX, gj = J0 + t / FTX;
+  for (int t = threadIdx.x; t < TX * TY; t += NT) {
+    const int gi = I0 + t % TX, gj = J0 + t / TX;
     if (gi >= d.nx1 || gj >= d.ny1) continue;
     T o[2] = {T(0), T(0)};
     if (gi >= 1) {
@@ -183,6 +271,82 @@ __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* _
     }
     store_node<2, T>(out, (int64_t)gj * d.nx1 + gi, o);
   }
+}
+
+// Grid: (ceil(dc.nx1 / FCX), ceil(dc.ny1 / FCY)); d is level k, dc level k-1.
+template <typename T, class Op>
+__global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
+                                                T* __restrict__ z2out, T* __restrict__ rc,
+                                                const double* __restrict__ omg, const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W1 = 2 * FCX + 5, H1 = 2 * FCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
+  const Tile tl = xcd_tile();
+  down_tile<T, Op, FCX, FCY, FBS>(op, d, dc, (int)tl.x * FCX, (int)tl.y * FCY, r, z2out, rc, T(*omg), sr, sd, s1,
+                                  s2, s3);
+}
+
+// Grid: (ceil(d.nx1 / FTX), ceil(d.ny1 / FTY)).
+template <typename T, class Op>
+__global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
+                                              const T* __restrict__ z2, const T* __restrict__ zc,
+                                              T* __restrict__ out, const double* __restrict__ omg,
+                                              const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W0 = FTX + 4, H0 = FTY + 4, W1 = FTX + 2, H1 = FTY + 2;
+  __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
+  const Tile tl = xcd_tile();
+  up_tile<T, Op, FTX, FTY, FBS>(op, d, dc, (int)tl.x * FTX, (int)tl.y * FTY, r, z2, zc, out, T(*omg), s0, sr, sd,
+                                s1);
+}
+
+// Stored FP32 element matrices staged in LDS.  Grid: (ceil(dc.nx1 / SCX), ceil(dc.ny1 / SCY)).
+// Region 1 of a tile has nodes (2CI0-3 .. 2CI0+2SCX+1); the elements around them
+// are (2CI0-4 .. 2CI0+2SCX+1) x (2CJ0-4 .. 2CJ0+2SCY+1).
+// FROM_X: the level is the first coarse level formed from the densities x (fnx
+// finest elements along x) instead of stored matrices Eg.
+template <bool FROM_X>
+__global__ __launch_bounds__(SBS) void k_down2d_staged(const float* __restrict__ Eg, const float* __restrict__ x,
+                                                       int fnx, Dims d, Dims dc, const float* __restrict__ r,
+                                                       float* __restrict__ z2out, float* __restrict__ rc,
+                                                       const double* __restrict__ omg, const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W1 = 2 * SCX + 5, H1 = 2 * SCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ float El[36 * LW * LH];
+  __shared__ float sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
+  const Tile tl = xcd_tile();
+  const int CI0 = (int)tl.x * SCX, CJ0 = (int)tl.y * SCY;
+  const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
+  if constexpr (FROM_X) stage_from_x<SBS, LW, LH>(x, fnx, d, ex0, ey0, El);
+  else stage_elements<float, SBS, LW, LH>(Eg, d, ex0, ey0, El);
+  __syncthreads();
+  const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
+  down_tile<float, OpCoarseLDS<float>, SCX, SCY, SBS>(op, d, dc, CI0, CJ0, r, z2out, rc, float(*omg), sr, sd, s1,
+                                                      s2, s3);
+}
+
+// Grid: (ceil(d.nx1 / STX), ceil(d.ny1 / STY)).  Region 1 has nodes
+// (I0-1 .. I0+STX); the elements around them are (I0-2 .. I0+STX) x (J0-2 .. J0+STY).
+template <bool FROM_X>
+__global__ __launch_bounds__(SBS) void k_up2d_staged(const float* __restrict__ Eg, const float* __restrict__ x, int fnx,
+                                                     Dims d, Dims dc, const float* __restrict__ r,
+                                                     const float* __restrict__ z2, const float* __restrict__ zc,
+                                                     float* __restrict__ out, const double* __restrict__ omg,
+                                                     const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W0 = STX + 4, H0 = STY + 4, W1 = STX + 2, H1 = STY + 2;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ float El[36 * LW * LH];
+  __shared__ float s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
+  const Tile tl = xcd_tile();
+  const int I0 = (int)tl.x * STX, J0 = (int)tl.y * STY;
+  const int ex0 = I0 - 2, ey0 = J0 - 2;
+  if constexpr (FROM_X) stage_from_x<SBS, LW, LH>(x, fnx, d, ex0, ey0, El);
+  else stage_elements<float, SBS, LW, LH>(Eg, d, ex0, ey0, El);
+  __syncthreads();
+  const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
+  up_tile<float, OpCoarseLDS<float>, STX, STY, SBS>(op, d, dc, I0, J0, r, z2, zc, out, float(*omg), s0, sr, sd, s1);
 }
 
 }  // namespace ipmg

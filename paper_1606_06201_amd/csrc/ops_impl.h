@@ -3,6 +3,7 @@
 #pragma once
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include "ctx.h"
 #include "kernels.h"
 #include "tail.h"
@@ -347,6 +348,34 @@ struct OpsImpl : Ops {
     }
   }
 
+  // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes.
+  template <typename T, class Op, int NJ>
+  void launch_l2d(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out, const double* omg,
+                  Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64, bool fin) {
+    const dim3 g2((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
+    const unsigned nb2 = g2.x * g2.y;
+    IPMG_REQUIRE((int64_t)nb2 <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+#define IPMG_L2D_CASE(M)                                                                                     \
+  case M:                                                                                                    \
+    {                                                                                                        \
+      ProfScope ps_(c, c.prof_tag);                                                                          \
+      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);      \
+    }                                                                                                        \
+    if (fin)                                                                                                 \
+      k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
+                                                 sidx, sidx_in, gate);                                      \
+    return;
+    switch (mode) {
+      IPMG_L2D_CASE(M_APPLY)
+      IPMG_L2D_CASE(M_RESID)
+      IPMG_L2D_CASE(M_JACOBI)
+      IPMG_L2D_CASE(M_JACOBI0)
+      IPMG_L2D_CASE(M_JACOBI_BETA)
+      default: break;
+    }
+#undef IPMG_L2D_CASE
+  }
+
   template <typename T, class Op>
   void launch_level(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out,
                     const double* omg, Aug<T> aug, int sidx, int sidx_in, const int* gate,
@@ -359,28 +388,11 @@ struct OpsImpl : Ops {
       // register-blocked tiles pay on large levels; small levels are latency-bound
       // and need one node per thread
       if (mode != M_POWER && mode != M_RAYLEIGH && c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
-        constexpr int NJ = sizeof(T) == 4 ? 4 : 2;
-        const dim3 g2((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
-        const unsigned nb2 = g2.x * g2.y;
-#define IPMG_L2D_CASE(M)                                                                                     \
-  case M:                                                                                                    \
-    {                                                                                                        \
-      ProfScope ps_(c, c.prof_tag);                                                                          \
-      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);      \
-    }                                                                                                        \
-    if (fin)                                                                                                 \
-      k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
-                                                 sidx, sidx_in, gate);                                      \
-    return;
-        switch (mode) {
-          IPMG_L2D_CASE(M_APPLY)
-          IPMG_L2D_CASE(M_RESID)
-          IPMG_L2D_CASE(M_JACOBI)
-          IPMG_L2D_CASE(M_JACOBI0)
-          IPMG_L2D_CASE(M_JACOBI_BETA)
-          default: break;
-        }
-#undef IPMG_L2D_CASE
+        const int nj = sizeof(T) == 4 ? c.nj32 : c.nj64;
+        if (nj == 1) return launch_l2d<T, Op, 1>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin);
+        if (nj == 2) return launch_l2d<T, Op, 2>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin);
+        if (nj == 8) return launch_l2d<T, Op, 8>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin);
+        return launch_l2d<T, Op, 4>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin);
       }
     }
 #define IPMG_LEVEL_CASE(M)                                                                                   \
@@ -433,6 +445,19 @@ struct OpsImpl : Ops {
     else level_t<double>(c, lev, op, mode, v, r, out, omg, sidx, sidx_in, gate, dot64);
   }
 
+  template <typename TY, class Op, int NJ>
+  void launch_dir2d(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q, Aug<double> aug,
+                    int first, const int* gate) {
+    const Dims& d = c.fine();
+    const dim3 g((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
+    IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+    {
+      ProfScope ps(c, PC_DIR_APPLY);
+      k_dir_apply2d<TY, Op, NJ><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+    }
+    k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
+                                          g.x * g.y, gate);
+  }
   template <typename TY, class Op>
   void launch_dir_apply(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q,
                         Aug<double> aug, int first, const int* gate) {
@@ -440,16 +465,9 @@ struct OpsImpl : Ops {
     dim3 g = node_grid(d);
     if constexpr (DIM == 2) {
       if (c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
-        constexpr int NJ = 2;
-        g = dim3((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
-        IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
-        {
-          ProfScope ps(c, PC_DIR_APPLY);
-          k_dir_apply2d<TY, Op, NJ><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
-        }
-        k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
-                                              g.x * g.y, gate);
-        return;
+        if (c.nj_dir == 1) return launch_dir2d<TY, Op, 1>(c, op, y, pold, p, q, aug, first, gate);
+        if (c.nj_dir == 4) return launch_dir2d<TY, Op, 4>(c, op, y, pold, p, q, aug, first, gate);
+        return launch_dir2d<TY, Op, 2>(c, op, y, pold, p, q, aug, first, gate);
       }
     }
     {
@@ -525,6 +543,18 @@ struct OpsImpl : Ops {
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
+    if constexpr (std::is_same<T, float>::value) {
+      // measured: the down pass of the first coarse level is faster unstaged (its
+      // small staged tiles form each halo element matrix again)
+      const bool from_x = lev == c.L - 2 && c.coarse_from_x;
+      if (c.fused_staged && !from_x && d.nnodes < c.staged_max_nodes) {
+        const dim3 gs((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
+        k_down2d_staged<false><<<gs, SBS, 0, c.stream>>>((const float*)c.lev[lev].E, nullptr, 0, d, dc,
+                                                         (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
+                                                         (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+        return;
+      }
+    }
     if (lev == c.L - 2 && c.coarse_from_x)
       k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
                                                                (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
@@ -540,6 +570,23 @@ struct OpsImpl : Ops {
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
+    if constexpr (std::is_same<T, float>::value) {
+      const bool from_x = lev == c.L - 2 && c.coarse_from_x;
+      if (c.fused_staged && (from_x || d.nnodes < c.staged_max_nodes)) {
+        const dim3 gs((unsigned)((d.nx1 + STX - 1) / STX), (unsigned)((d.ny1 + STY - 1) / STY), 1);
+        const float* E = (const float*)c.lev[lev].E;
+        const float* x = (const float*)c.xT;
+        if (from_x)
+          k_up2d_staged<true><<<gs, SBS, 0, c.stream>>>(E, x, c.fine().nx, d, dc, (const float*)c.lev[lev].r,
+                                                        (const float*)c.lev[lev].z, (const float*)zc, (float*)out,
+                                                        c.omega_dev + lev, gate);
+        else
+          k_up2d_staged<false><<<gs, SBS, 0, c.stream>>>(E, x, c.fine().nx, d, dc, (const float*)c.lev[lev].r,
+                                                         (const float*)c.lev[lev].z, (const float*)zc, (float*)out,
+                                                         c.omega_dev + lev, gate);
+        return;
+      }
+    }
     if (lev == c.L - 2 && c.coarse_from_x)
       k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
                                                              (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,

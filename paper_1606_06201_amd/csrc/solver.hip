@@ -113,6 +113,10 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_UNSTAGED")) c.fused_staged = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
+  if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
+  if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);
   c.power_steps = POWER_STEPS;
   c.power_steps_z = POWER_STEPS_Z;
   if (const char* e = std::getenv("IPMG_TILED_MIN_NODES")) c.tiled_min_nodes = std::max<int64_t>(0, std::atoll(e));

@@ -202,7 +202,8 @@ def test_element_sensitivities_match_oracle():
 
 
 @pytest.mark.parametrize("env,val", [("IPMG_TAIL", "1"), ("IPMG_STORED_COARSE", "1"),
-                                     ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1")])
+                                     ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
+                                     ("IPMG_UNSTAGED", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
                                                   ((8, 4, 4), 3, False, 1e-11), ((128, 64), 4, False, 1e-11),
                                                   ((128, 64), 4, True, 2e-4)])
