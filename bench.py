@@ -40,8 +40,12 @@ KERNEL_NAMES = {
     "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
     "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
                 "restriction in one LDS-tiled pass",
-    "sub_up": "k_up2d<float, OpCoarse2K<2,float>>: first coarse level, prolongation and two Jacobi sweeps in "
-              "one LDS-tiled pass",
+    "sub_up": "k_up2d_staged<true>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
+              "pass, element matrices formed from the densities in LDS",
+    "fine_down": "k_down2d_fine<float>: finest level, two Jacobi sweeps, residual and restriction in one "
+                 "LDS-tiled pass",
+    "fine_up": "k_up2d_fine<float,true>: finest level, prolongation, two Jacobi sweeps and the PCG ratio "
+               "r~'y~ in one LDS-tiled pass",
 }
 
 
@@ -66,6 +70,10 @@ def class_bytes(nel, fp32, kind):
         return 2 * w * Nc + w * m + 2 * w * Nc + 2 * w * Nc2
     if kind == "sub_up":                        # read z2, r, coarse correction, fine x; write z
         return 3 * 2 * w * Nc + 2 * w * Nc2 + w * m
+    if kind == "fine_down":                     # read r, x; write z2, coarse residual
+        return 2 * w * N + w * m + 2 * w * N + 2 * w * Nc
+    if kind == "fine_up":                       # read z2, coarse correction, r, x, FP64 r; write z
+        return 3 * 2 * w * N + 2 * w * Nc + w * m + 2 * 8 * N
     if kind == "dir_apply":                     # read y, p_old; write p, q (FP64); read x (FP64)
         return 2 * N * (w + 3 * 8) + 8 * m
     if kind == "pcg_update":                    # read z, r, p, q; write z, r (FP64); write r (V-cycle)

@@ -48,7 +48,8 @@ struct Ops {
   //   up:   z2 (in z), coarse correction zc -> out
   virtual bool fused_applies(const Ctx& c, int lev, int op) const = 0;
   virtual void fused_down(Ctx& c, int lev, const int* gate) = 0;
-  virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) = 0;
+  virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate,
+                        const double* beta64 = nullptr) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
   // Interior point kernels (FP64).
   virtual void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi,
@@ -77,6 +78,10 @@ struct Ctx {
   int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
   int nj32 = 4, nj64 = 2, nj_dir = 4;          // nodes per thread of the tiled passes
   bool fused2d = true;         // 2D K levels with stored operators: two fused launches per level
+  // ... and on the finest level: opt-in, measured slower there than the separate
+  // register-tiled passes (its barrier-separated phases do not hide memory latency)
+  bool fused_fine = false;
+  bool fine_small_tiles = false;  // finest-level fused passes on 256-thread tiles
   bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32; stored levels
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
   int power_steps = 12;        // power iterations of the damping estimate (K)
@@ -143,7 +148,9 @@ enum ProfClass {
   PC_FINE_JACOBI_BETA = 6,  // finest level, last sweep with the fused PCG ratio
   PC_SUB_DOWN = 7,          // first coarse level, fused pre-smoothing + residual + restriction
   PC_SUB_UP = 8,            // first coarse level, fused prolongation + post-smoothing
-  PC_COUNT = 9
+  PC_FINE_DOWN = 9,         // finest level, fused pre-smoothing + residual + restriction
+  PC_FINE_UP = 10,          // finest level, fused prolongation + post-smoothing (+ PCG ratio)
+  PC_COUNT = 11
 };
 
 // Sets the class of the level passes enqueued in its scope.

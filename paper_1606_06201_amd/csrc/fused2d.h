@@ -93,6 +93,51 @@ __device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, i
   }
 }
 
+// Finest level, A_e = x_e K0, with the densities of a block of elements in LDS
+// (xl[le], le as in OpCoarseLDS) and the six K0 constants of the square element.
+template <typename T>
+struct OpFineKLDS {
+  const T* xl;
+  int ex0, ey0, lw, ne;
+  __device__ inline int local(int ei, int ej) const {
+    const int le = (ej - ey0) * lw + (ei - ex0);
+    return le < 0 ? 0 : (le >= ne ? ne - 1 : le);
+  }
+  __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
+    const T xe = xl[local(ei, ej)];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int col = 0; col < 8; ++col) s += k0sq<T>(2 * a + c, col) * ve[col];
+      acc[c] += xe * s;
+    }
+  }
+  __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
+    const T xe = xl[local(ei, ej)];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) dg[c] += xe * k0sq<T>(2 * a + c, 2 * a + c);
+  }
+};
+
+// Densities of the elements [ex0, ex0+LW) x [ey0, ey0+LH) into LDS (zero outside).
+template <typename T, int NT, int LW, int LH>
+__device__ inline void stage_x(const T* __restrict__ x, const Dims& d, int ex0, int ey0, T* xl) {
+  constexpr int NE = LW * LH, PER = (NE + NT - 1) / NT;
+  T v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int le = threadIdx.x + u * NT;
+    const int ei = ex0 + le % LW, ej = ey0 + le / LW;
+    v[u] = (le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny) ? x[(int64_t)ej * d.nx + ei] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int le = threadIdx.x + u * NT;
+    if (le < NE) xl[le] = v[u];
+  }
+}
+
 // Element matrices of the first coarse level formed from the finest densities
 // (A_C = sum_q x_q G_q over the four fine sub-elements, Sec. 5.1 Galerkin product
 // of the x-scaled unit element) for the elements [ex0, ex0+LW) x [ey0, ey0+LH),
@@ -214,9 +259,12 @@ __device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, in
 // Up pass of one tile of TX x TY fine nodes with corner (I0, J0).  LDS: s0 over
 // region 0 ((TX+4) x (TY+4) nodes from (I0-2, J0-2)); sr, sd, s1 over region 1
 // (one node inside).
+// dot64 (optional): accumulate dot64' out over the tile's nodes into red0 (the
+// PCG ratio of the finest level, Algorithm PCG).
 template <typename T, class Op, int TX, int TY, int NT>
 __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0, const T* r, const T* z2,
-                               const T* zc, T* out, T omega, T* s0, T* sr, T* sd, T* s1) {
+                               const T* zc, T* out, T omega, T* s0, T* sr, T* sd, T* s1,
+                               const double* dot64 = nullptr, double* red0 = nullptr) {
   constexpr int W0 = TX + 4, H0 = TY + 4;
   constexpr int W1 = TX + 2, H1 = TY + 2;
   for (int t = threadIdx.x; t < W0 * H0; t += NT) {
@@ -269,7 +317,9 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
     }
-    store_node<2, T>(out, (int64_t)gj * d.nx1 + gi, o);
+    const int64_t qn = (int64_t)gj * d.nx1 + gi;
+    store_node<2, T>(out, qn, o);
+    if (dot64) *red0 += dot64[2 * qn] * (double)o[0] + dot64[2 * qn + 1] * (double)o[1];
   }
 }
 
@@ -347,6 +397,58 @@ __global__ __launch_bounds__(SBS) void k_up2d_staged(const float* __restrict__ E
   __syncthreads();
   const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
   up_tile<float, OpCoarseLDS<float>, STX, STY, SBS>(op, d, dc, I0, J0, r, z2, zc, out, float(*omg), s0, sr, sd, s1);
+}
+
+// Finest level of K (densities x, V-cycle precision T), tiles of CX x CY coarse
+// nodes and NT threads.  Grid: (ceil(dc.nx1 / CX), ceil(dc.ny1 / CY)).  The
+// elements around region 1 are (2CI0-4 .. 2CI0+2CX+1) x (2CJ0-4 .. 2CJ0+2CY+1).
+template <typename T, int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) void k_down2d_fine(const T* __restrict__ x, Dims d, Dims dc,
+                                                    const T* __restrict__ r, T* __restrict__ z2out,
+                                                    T* __restrict__ rc, const double* __restrict__ omg,
+                                                    const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ T xl[LW * LH];
+  __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
+  const Tile tl = xcd_tile();
+  const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
+  const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
+  stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
+  __syncthreads();
+  const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
+  down_tile<T, OpFineKLDS<T>, CX, CY, NT>(op, d, dc, CI0, CJ0, r, z2out, rc, T(*omg), sr, sd, s1, s2, s3);
+}
+
+// Tiles of TX x TY fine nodes, NT threads.  Grid: (ceil(d.nx1 / TX), ceil(d.ny1 /
+// TY)).  Elements (I0-2 .. I0+TX) x (J0-2 .. J0+TY).  BETA: block partials of
+// dot64' out (the PCG ratio r~'y~ with the FP64 residual dot64), summed by
+// k_level_fin<T, M_JACOBI_BETA>.
+template <typename T, bool BETA, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_up2d_fine(const T* __restrict__ x, Dims d, Dims dc,
+                                                   const T* __restrict__ r, const T* __restrict__ z2,
+                                                   const T* __restrict__ zc, T* __restrict__ out,
+                                                   const double* __restrict__ omg, const double* __restrict__ dot64,
+                                                   Red red, const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ T xl[LW * LH];
+  __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
+  const Tile tl = xcd_tile();
+  const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
+  const int ex0 = I0 - 2, ey0 = J0 - 2;
+  stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
+  __syncthreads();
+  const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
+  double red0 = 0.0;
+  up_tile<T, OpFineKLDS<T>, TX, TY, NT>(op, d, dc, I0, J0, r, z2, zc, out, T(*omg), s0, sr, sd, s1,
+                                        BETA ? dot64 : nullptr, &red0);
+  if constexpr (BETA) {
+    const double vals[1] = {red0};
+    block_partials<1, false, NT>(vals, red);
+  }
 }
 
 }  // namespace ipmg

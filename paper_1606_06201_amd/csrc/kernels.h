@@ -89,9 +89,9 @@ __device__ inline Tile xcd_tile() {
 // serialises the blocks; the kernel boundary provides the visibility instead.
 __device__ inline unsigned block_id() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
 
-template <int NV, bool IS_MIN = false>
+template <int NV, bool IS_MIN = false, int NT = BS>
 __device__ void block_partials(const double (&v)[NV], const Red& red) {
-  __shared__ double sh[NV][BS / 64];
+  __shared__ double sh[NV][NT / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int n = 0; n < NV; ++n) {
@@ -104,7 +104,7 @@ __device__ void block_partials(const double (&v)[NV], const Red& red) {
 #pragma unroll
     for (int n = 0; n < NV; ++n) {
       double s = sh[n][0];
-      for (int w = 1; w < BS / 64; ++w) s = IS_MIN ? fmin(s, sh[n][w]) : s + sh[n][w];
+      for (int w = 1; w < NT / 64; ++w) s = IS_MIN ? fmin(s, sh[n][w]) : s + sh[n][w];
       red.partials[(size_t)n * MAX_PARTIALS + bid] = s;
     }
   }

@@ -533,14 +533,30 @@ struct OpsImpl : Ops {
       // The first coarse level formed from the densities is VALU-bound: fused (with
       // its recomputed halos) it pays in FP32 only.
       const bool from_x = lev == c.L - 2 && c.coarse_from_x;
+      const bool fine = lev == c.L - 1;
       return c.fused2d && op == IPMG_OP_K && c.desc.nu_pre == 2 && c.desc.nu_post == 2 && lev >= 1 &&
-             lev < c.L - 1 && lev > c.tail_top && (!from_x || c.fp32);
+             lev > c.tail_top && (!from_x || c.fp32) && (!fine || c.fused_fine);
     }
   }
   template <typename T>
   void fused_down_t(Ctx& c, int lev, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
+    if (lev == c.L - 1) {
+      ProfScope ps(c, PC_FINE_DOWN);
+      if (c.fine_small_tiles) {
+        const dim3 g((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
+        k_down2d_fine<T, SCX, SCY, SBS><<<g, SBS, 0, c.stream>>>((const T*)c.xT, d, dc, (const T*)c.lev[lev].r,
+                                                                 (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r,
+                                                                 c.omega_dev + lev, gate);
+      } else {
+        const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
+        k_down2d_fine<T, FCX, FCY, FBS><<<g, FBS, 0, c.stream>>>((const T*)c.xT, d, dc, (const T*)c.lev[lev].r,
+                                                                 (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r,
+                                                                 c.omega_dev + lev, gate);
+      }
+      return;
+    }
     const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
     if constexpr (std::is_same<T, float>::value) {
@@ -565,9 +581,41 @@ struct OpsImpl : Ops {
                                                              (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
   }
   template <typename T>
-  void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
+  void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate, const double* beta64) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
+    if (lev == c.L - 1) {
+      const int tx = c.fine_small_tiles ? STX : FTX, ty = c.fine_small_tiles ? STY : FTY;
+      const dim3 g((unsigned)((d.nx1 + tx - 1) / tx), (unsigned)((d.ny1 + ty - 1) / ty), 1);
+      IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+      {
+        ProfScope ps(c, PC_FINE_UP);
+        const T* xr = (const T*)c.xT;
+        const T* rr = (const T*)c.lev[lev].r;
+        const T* z2 = (const T*)c.lev[lev].z;
+        const double* w = c.omega_dev + lev;
+        if (c.fine_small_tiles) {
+          if (beta64)
+            k_up2d_fine<T, true, STX, STY, SBS><<<g, SBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out, w,
+                                                                         beta64, c.red, gate);
+          else
+            k_up2d_fine<T, false, STX, STY, SBS><<<g, SBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out,
+                                                                          w, nullptr, c.red, gate);
+        } else {
+          if (beta64)
+            k_up2d_fine<T, true, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out, w,
+                                                                         beta64, c.red, gate);
+          else
+            k_up2d_fine<T, false, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out,
+                                                                          w, nullptr, c.red, gate);
+        }
+      }
+      if (beta64)
+        k_level_fin<T, M_JACOBI_BETA><<<1, BS, 0, c.stream>>>((const T*)out, (const T*)c.lev[lev].r, (T*)out,
+                                                              c.omega_dev + lev, 0, 0.0, d.nslots, beta64, c.red,
+                                                              g.x * g.y, 0, -1, gate);
+      return;
+    }
     const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
     if constexpr (std::is_same<T, float>::value) {
@@ -602,10 +650,10 @@ struct OpsImpl : Ops {
       else fused_down_t<double>(c, lev, gate);
     }
   }
-  void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) override {
+  void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate, const double* beta64) override {
     if constexpr (DIM == 2) {
-      if (c.fp32) fused_up_t<float>(c, lev, zc, out, gate);
-      else fused_up_t<double>(c, lev, zc, out, gate);
+      if (c.fp32) fused_up_t<float>(c, lev, zc, out, gate, beta64);
+      else fused_up_t<double>(c, lev, zc, out, gate, beta64);
     }
   }
 

@@ -114,6 +114,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNSTAGED")) c.fused_staged = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
+  if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);
@@ -318,10 +320,10 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
     else dense_solve<double>(c.stream, c.dAi, n, (const double*)l.r, (double*)l.z, gate);
     return l.z;
   }
-  if (!beta64 && c.ops->fused_applies(c, k, op)) {
+  if (c.ops->fused_applies(c, k, op)) {
     c.ops->fused_down(c, k, gate);                                            // two sweeps, residual, P'
     void* vc = vcycle_level(c, op, k - 1, gate, nullptr);
-    c.ops->fused_up(c, k, vc, l.z2, gate);                                    // P, two sweeps
+    c.ops->fused_up(c, k, vc, l.z2, gate, beta64);                            // P, two sweeps (+ ratio)
     return l.z2;
   }
   void* cur = l.z;
