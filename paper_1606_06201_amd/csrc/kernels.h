@@ -516,14 +516,67 @@ __device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j
   level_node_finish<DIM, T, MODE>(q, acc, dg, vc, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
 }
 
-// Generic form: gathers the neighbourhood with bounds checks first.
+// 3D row sums and diagonal of node (i, j, k): the loop over the 8 elements stays
+// rolled and each element's 24 nodal values are gathered from v (L1/L2) when it is
+// processed, so the 81 neighbourhood values are never live in registers at once
+// (they were: over 256 VGPRs, one wave per SIMD).  Elements outside the grid
+// contribute nothing; clamped nodes (i == 0) read as zero.
+template <typename T, class Op, bool ROWS, bool DIAG>
+__device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
+                                          T* acc, T* dg) {
+#pragma unroll 1
+  for (int q = 0; q < 8; ++q) {
+    const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+    int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && ek >= 0 && ek < d.nz;
+    ei = ok ? ei : 0;
+    ej = ok ? ej : 0;
+    ek = ok ? ek : 0;
+    const int64_t e = ((int64_t)ek * d.ny + ej) * d.nx + ei;
+    const int a = loc_index(1 - ex, 1 - ey, 1 - ez);
+    if constexpr (ROWS) {
+      T ve[24];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int ni = ei + loc_x(b), nj = ej + loc_y(b), nk = ek + loc_z(b);
+        const bool nok = ok && ni >= 1;
+        const int64_t qn = nok ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ve[b * 3 + c] = nok ? v[3 * qn + c] : T(0);
+      }
+      op.rows(e, ei, ej, ek, a, ve, acc);
+    }
+    if constexpr (DIAG) {
+      T dt[3] = {T(0), T(0), T(0)};
+      op.diag(e, ei, ej, ek, a, dt);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dg[c] += ok ? dt[c] : T(0);
+    }
+  }
+}
+
+// Generic form: gathers the neighbourhood with bounds checks first (2D); in 3D,
+// element by element (node_apply_gather3).
 template <int DIM, typename T, class Op, int MODE>
 __device__ inline void level_node(const Op& op, const Dims& d, int i, int j, int k, const T* v, const T* r, T* out,
                                   T omega, const T* augb, T vl, double pin, const double* dot64, double& bdot,
                                   double& red0, double& red1) {
-  T vn[Geo<DIM>::NB][DIM];
-  if constexpr (MODE != M_JACOBI0) load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
-  level_node_core<DIM, T, Op, MODE>(op, d, i, j, k, vn, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
+  if constexpr (DIM == 3) {
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    if (i == 0) {
+      const T z[3] = {T(0), T(0), T(0)};
+      if constexpr (MODE != M_RAYLEIGH) store_node<3, T>(out, q, z);
+      return;
+    }
+    T acc[3] = {T(0), T(0), T(0)}, dg[3] = {T(0), T(0), T(0)}, vc[3] = {T(0), T(0), T(0)};
+    if constexpr (MODE != M_JACOBI0) load_node<3, T>(v, q, vc);
+    node_apply_gather3<T, Op, MODE != M_JACOBI0, true>(op, d, i, j, k, v, acc, dg);
+    level_node_finish<3, T, MODE>(q, acc, dg, vc, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
+  } else {
+    T vn[Geo<DIM>::NB][DIM];
+    if constexpr (MODE != M_JACOBI0) load_neighbourhood<DIM, T>(v, d, i, j, k, vn);
+    level_node_core<DIM, T, Op, MODE>(op, d, i, j, k, vn, r, out, omega, augb, vl, pin, dot64, bdot, red0, red1);
+  }
 }
 
 // Lambda entry of a pass over an augmented level, given the border dot tot0 =
@@ -981,6 +1034,62 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
     }
     store_node<2, double>(p, qn, pc);
     store_node<2, double>(q, qn, o);
+  }
+  const double vals[3] = {pq, bdot, qy};
+  block_partials<3>(vals, red);
+}
+
+// 3D form of the first step of a PCG iteration, in two kernels: k_pdir3 writes
+// p = -y + beta p_old (zero on clamped nodes), k_dir_apply3 gathers q = A p element
+// by element (node_apply_gather3) with the border term b p_lambda and the partials
+// of p'q, b'p and q'y.  Finalized by k_dir_fin like k_dir_apply.
+template <typename TY>
+__global__ __launch_bounds__(BS) void k_pdir3(Dims d, const TY* __restrict__ y, const double* __restrict__ pold,
+                                              double* __restrict__ p, Red red, int first, const int* gate) {
+  if (gate && *gate) return;
+  const double beta = first ? 0.0 : red.scal[S_BETA];
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t >= d.nslots) return;
+  const int64_t q = t / 3;
+  const int i = (int)(q % d.nx1);
+  p[t] = i == 0 ? 0.0 : -(double)y[t] + (first ? 0.0 : beta * pold[t]);
+}
+
+template <typename TY, class Op>
+__global__ __launch_bounds__(BS) void k_dir_apply3(Op op, Dims d, const TY* __restrict__ y,
+                                                   const double* __restrict__ pold, const double* __restrict__ p,
+                                                   double* __restrict__ q, Aug<double> aug, Red red, int first,
+                                                   const int* gate) {
+  if (gate && *gate) return;
+  const double beta = first ? 0.0 : red.scal[S_BETA];
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
+  double pq = 0.0, bdot = 0.0, qy = 0.0;
+  const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
+  if (i < d.nx1 && j < d.ny1) {
+    const int64_t qn = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    double o[3] = {0.0, 0.0, 0.0};
+    if (i > 0) {
+      double dg[3];
+      node_apply_gather3<double, Op, true, false>(op, d, i, j, k, p, o, dg);
+      double pc[3];
+      load_node<3, double>(p, qn, pc);
+      TY yc[3];
+      load_node<3, TY>(y, qn, yc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (aug.b) {
+          const double bc = aug.b[qn * 3 + c];
+          o[c] += bc * pl;
+          bdot += bc * pc[c];
+        }
+        pq += pc[c] * o[c];
+        qy += o[c] * (double)yc[c];
+      }
+    }
+    store_node<3, double>(q, qn, o);
   }
   const double vals[3] = {pq, bdot, qy};
   block_partials<3>(vals, red);

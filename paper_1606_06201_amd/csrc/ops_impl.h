@@ -470,7 +470,11 @@ struct OpsImpl : Ops {
         return launch_dir2d<TY, Op, 2>(c, op, y, pold, p, q, aug, first, gate);
       }
     }
-    {
+    if constexpr (DIM == 3) {
+      k_pdir3<TY><<<lin_grid(d.nslots), BS, 0, c.stream>>>(d, y, pold, p, c.red, first, gate);
+      ProfScope ps(c, PC_DIR_APPLY);
+      k_dir_apply3<TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+    } else {
       ProfScope ps(c, PC_DIR_APPLY);
       k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
     }
