@@ -204,6 +204,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="thr2048x1024")
+    ap.add_argument("--levels", type=int, default=0, help="override the workload's multigrid level count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--flexible", type=int, default=0, choices=(0, 1),
@@ -237,7 +238,7 @@ def main():
     if w["kind"] in ("ip", "adjoint"):
         bench_secondary(args, w, dev)
         return
-    nel, levels = w["nel"], w["levels"]
+    nel, levels = w["nel"], (args.levels or w["levels"])
     x_h = inputs.density_for(args.workload)
     f_h = None
     print(f"[bench] workload {args.workload} nel={nel} levels={levels}", file=sys.stderr, flush=True)

@@ -994,21 +994,29 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
   double pq = 0.0, bdot = 0.0, qy = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
-  TY yw[NJ + 2][3][2];
+  // p = -y + beta p_old on the neighbourhood, combined as each node is loaded;
+  // yc keeps y on the thread's own nodes (for q'y)
+  TY yc[NJ][2];
   double w[NJ + 2][3][2], acc[NJ][2], dg[NJ][2];
-  if (interior) {
-    load_tile<TY, NJ, false>(y, d, i, j0, yw);
-    if (!first) load_tile<double, NJ, false>(pold, d, i, j0, w);
-  } else {
-    load_tile<TY, NJ, true>(y, d, i, j0, yw);
-    if (!first) load_tile<double, NJ, true>(pold, d, i, j0, w);
-  }
 #pragma unroll
   for (int rr = 0; rr < NJ + 2; ++rr)
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc)
+    for (int cc = 0; cc < 3; ++cc) {
+      const int ii = i - 1 + cc, jj = j0 - 1 + rr;
+      TY yy[2] = {TY(0), TY(0)};
+      double po[2] = {0.0, 0.0};
+      if (interior || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1)) {
+        const int64_t qq = (int64_t)jj * d.nx1 + ii;
+        load_node<2, TY>(y, qq, yy);
+        if (!first) load_node<2, double>(pold, qq, po);
+      }
 #pragma unroll
-      for (int c = 0; c < 2; ++c) w[rr][cc][c] = -(double)yw[rr][cc][c] + (first ? 0.0 : beta * w[rr][cc][c]);
+      for (int c = 0; c < 2; ++c) w[rr][cc][c] = -(double)yy[c] + (first ? 0.0 : beta * po[c]);
+      if (cc == 1 && rr >= 1 && rr <= NJ) {
+        yc[rr - 1][0] = yy[0];
+        yc[rr - 1][1] = yy[1];
+      }
+    }
   if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
   else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
 #pragma unroll
@@ -1030,7 +1038,7 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
         }
       }
       pq += pc[0] * o[0] + pc[1] * o[1];
-      qy += o[0] * (double)yw[n + 1][1][0] + o[1] * (double)yw[n + 1][1][1];
+      qy += o[0] * (double)yc[n][0] + o[1] * (double)yc[n][1];
     }
     store_node<2, double>(p, qn, pc);
     store_node<2, double>(q, qn, o);

@@ -467,6 +467,7 @@ struct OpsImpl : Ops {
       if (c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
         if (c.nj_dir == 1) return launch_dir2d<TY, Op, 1>(c, op, y, pold, p, q, aug, first, gate);
         if (c.nj_dir == 4) return launch_dir2d<TY, Op, 4>(c, op, y, pold, p, q, aug, first, gate);
+        if (c.nj_dir == 3) return launch_dir2d<TY, Op, 3>(c, op, y, pold, p, q, aug, first, gate);
         return launch_dir2d<TY, Op, 2>(c, op, y, pold, p, q, aug, first, gate);
       }
     }
