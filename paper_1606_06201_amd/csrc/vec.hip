@@ -329,53 +329,64 @@ __global__ __launch_bounds__(CTT) void k_tri_inv_diag(const double* __restrict__
   }
 }
 
-// Tile row I of X = L^-1 below the diagonal: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ
-// (one block per J < I; tile rows above I are complete).
-__global__ __launch_bounds__(CTT) void k_tri_inv_row(const double* __restrict__ L, double* __restrict__ X, int n,
-                                                     int I) {
-  __shared__ double Ta[CT][CT + 1];
-  __shared__ double Tb[CT][CT + 1];
-  const int J = blockIdx.x;
-  const int i0 = I * CT, j0 = J * CT;
-  const int ib = tile_rows(n, i0);
-  double acc[CT * CT / CTT];
-#pragma unroll
-  for (int u = 0; u < CT * CT / CTT; ++u) acc[u] = 0.0;
-  for (int K = J; K < I; ++K) {
-    const int k0 = K * CT;
-    __syncthreads();
-    for (int t = threadIdx.x; t < CT * CT; t += CTT) {
-      const int r = t / CT, c = t % CT;
-      Ta[r][c] = (r < ib) ? L[(int64_t)(i0 + r) * n + k0 + c] : 0.0;   // L_IK (K < I: full tile)
-      Tb[r][c] = X[(int64_t)(k0 + r) * n + j0 + c];                     // X_KJ (K, J < I: full tile)
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < CT * CT / CTT; ++u) {
-      const int t = threadIdx.x + u * CTT, r = t / CT, c = t % CT;
-      double s = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < CT; ++k) s += Ta[r][k] * Tb[k][c];
-      acc[u] += s;
-    }
+// Right-looking block forward substitution for X = L^-1 (L X = I), in place in X
+// whose strictly lower tiles start at zero and whose diagonal tiles hold L_KK^-1
+// (k_tri_inv_diag).  Step K: row block K, X_KJ = L_KK^-1 B_KJ for J < K
+// (k_trinv_row), then B_IJ -= L_IK X_KJ for I > K, J <= K (k_trinv_update).
+// Every block does one tile product, so the depth is two launches per block row.
+__global__ __launch_bounds__(CTT) void k_trinv_row(double* __restrict__ X, int n, int K) {
+  __shared__ double D[CT][CT + 1];
+  __shared__ double Bt[CT][CT + 1];
+  const int J = blockIdx.x;                          // J < K
+  const int k0 = K * CT, j0 = J * CT;
+  const int kb = tile_rows(n, k0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    D[r][c] = (r < kb && c < kb) ? X[(int64_t)(k0 + r) * n + k0 + c] : 0.0;   // L_KK^-1 (lower)
+    Bt[r][c] = (r < kb) ? X[(int64_t)(k0 + r) * n + j0 + c] : 0.0;            // B_KJ (J tile full)
   }
   __syncthreads();
   for (int t = threadIdx.x; t < CT * CT; t += CTT) {
     const int r = t / CT, c = t % CT;
-    Ta[r][c] = (r < ib && c < ib) ? X[(int64_t)(i0 + r) * n + i0 + c] : 0.0;   // X_II
+    if (r >= kb) continue;
+    double s = 0.0;
+    for (int k = 0; k <= r; ++k) s += D[r][k] * Bt[k][c];
+    X[(int64_t)(k0 + r) * n + j0 + c] = s;
   }
-#pragma unroll
-  for (int u = 0; u < CT * CT / CTT; ++u) {
-    const int t = threadIdx.x + u * CTT;
-    Tb[t / CT][t % CT] = acc[u];
+}
+
+__global__ __launch_bounds__(CTT) void k_trinv_update(const double* __restrict__ L, double* __restrict__ X, int n,
+                                                      int K) {
+  __shared__ double Ta[CT][CT + 1];
+  __shared__ double Tb[CT][CT + 1];
+  const int I = K + 1 + (int)blockIdx.x, J = (int)blockIdx.y;    // I > K >= J
+  const int i0 = I * CT, j0 = J * CT, k0 = K * CT;               // tile K is full (K < I)
+  const int ib = tile_rows(n, i0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    Ta[r][c] = (r < ib) ? L[(int64_t)(i0 + r) * n + k0 + c] : 0.0;   // L_IK
+    Tb[r][c] = X[(int64_t)(k0 + r) * n + j0 + c];                     // X_KJ
   }
   __syncthreads();
   for (int t = threadIdx.x; t < CT * CT; t += CTT) {
     const int r = t / CT, c = t % CT;
     if (r >= ib) continue;
     double s = 0.0;
-    for (int k = 0; k <= r; ++k) s += Ta[r][k] * Tb[k][c];
-    X[(int64_t)(i0 + r) * n + j0 + c] = -s;
+#pragma unroll 8
+    for (int k = 0; k < CT; ++k) s += Ta[r][k] * Tb[k][c];
+    X[(int64_t)(i0 + r) * n + j0 + c] -= s;
+  }
+}
+
+// Strictly lower tiles of X to zero (start of the substitution).
+__global__ __launch_bounds__(CTT) void k_zero_lower_tiles(double* __restrict__ X, int n) {
+  const int nt = (n + CT - 1) / CT;
+  const int I = blockIdx.x % nt, J = blockIdx.x / nt;
+  if (J >= I) return;
+  const int i0 = I * CT, j0 = J * CT, ib = tile_rows(n, i0);
+  for (int t = threadIdx.x; t < CT * CT; t += CTT) {
+    const int r = t / CT, c = t % CT;
+    if (r < ib) X[(int64_t)(i0 + r) * n + j0 + c] = 0.0;
   }
 }
 
@@ -415,7 +426,9 @@ __global__ __launch_bounds__(CTT) void k_inv_product(const double* __restrict__ 
   }
 }
 
-// zc = A^-1 rc, one wavefront per row.
+// zc = A^-1 rc, one wavefront per row; eight independent accumulators keep eight
+// row loads in flight per lane (the matrix is streamed once per V-cycle and needs
+// that many bytes outstanding to approach the HBM rate).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_dense_solve(const double* __restrict__ Ai, int n, const T* __restrict__ rc,
                                                     T* __restrict__ zc, const int* gate) {
@@ -423,10 +436,22 @@ __global__ __launch_bounds__(BS) void k_dense_solve(const double* __restrict__ A
   const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
-  double s = 0.0;
-  for (int c = lane; c < n; c += 64) s += Ai[(int64_t)row * n + c] * (double)rc[c];
-  s = wave_sum(s);
-  if (lane == 0) zc[row] = T(s);
+  const double* a = Ai + (int64_t)row * n;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = lane;
+  for (; c + 7 * 64 < n; c += 8 * 64) {
+    double av[8], rv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = a[c + u * 64];
+      rv[u] = (double)rc[c + u * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += av[u] * rv[u];
+  }
+  for (; c < n; c += 64) s[0] += a[c] * (double)rc[c];
+  const double t = wave_sum(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+  if (lane == 0) zc[row] = T(t);
 }
 
 }  // namespace
@@ -501,7 +526,11 @@ void dense_cholesky(hipStream_t st, double* A, int n, const Red& red) {
 void dense_inverse(hipStream_t st, const double* L, double* Li, double* Ai, int n) {
   const int nt = (n + CT - 1) / CT;
   k_tri_inv_diag<<<nt, CTT, 0, st>>>(L, Li, n);
-  for (int I = 1; I < nt; ++I) k_tri_inv_row<<<I, CTT, 0, st>>>(L, Li, n, I);
+  if (nt > 1) k_zero_lower_tiles<<<nt * nt, CTT, 0, st>>>(Li, n);
+  for (int K = 0; K < nt; ++K) {
+    if (K > 0) k_trinv_row<<<K, CTT, 0, st>>>(Li, n, K);
+    if (K + 1 < nt) k_trinv_update<<<dim3(nt - K - 1, K + 1), CTT, 0, st>>>(L, Li, n, K);
+  }
   k_inv_product<<<nt * nt, CTT, 0, st>>>(Li, Ai, n);
 }
 template <typename T>

@@ -7,7 +7,7 @@ Workloads (cantilevers of Sec. 7, Example 2 shapes, and a 3D analogue):
   ip64x32        64x32 elements, IP run from x = V/m, V = 0.5 m, xbar = 1, 4 levels
   grf1024x512    1024x512, Gaussian random field -> logistic in [1e-3, 1], 7 levels
   thr2048x1024   2048x1024, band-connected random field thresholded to {1e-6, 1},
-                 about 40 % solid, 7 levels (coarsest 32x16, chosen by measurement)
+                 about 40 % solid, 6 levels (coarsest 64x32, chosen by measurement)
   uni512x256     512x256, x ~ U[0.01, 1], objective g ~ N(0, 1), 6 levels
   ip128x64x64    128x64x64 hexahedra, IP run from x = 0.3, V = 0.3 m, 5 levels
 Loads: a unit downward (-y) point load at the right-edge mid node in 2D; in 3D
@@ -110,7 +110,7 @@ def point_load(nel):
 WORKLOADS = {
     "ip64x32": dict(nel=(64, 32), levels=4, kind="ip", vfrac=0.5, xbar=1.0),
     "grf1024x512": dict(nel=(1024, 512), levels=7, kind="solve", density="logistic", seed=1),
-    "thr2048x1024": dict(nel=(2048, 1024), levels=7, kind="solve", density="threshold", seed=2),
+    "thr2048x1024": dict(nel=(2048, 1024), levels=6, kind="solve", density="threshold", seed=2),
     "uni512x256": dict(nel=(512, 256), levels=6, kind="adjoint", density="uniform", seed=3),
     "ip128x64x64": dict(nel=(128, 64, 64), levels=5, kind="ip", vfrac=0.3, xbar=1.0),
 }

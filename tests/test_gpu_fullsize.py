@@ -49,7 +49,7 @@ def test_fp64_solve_1024x512_matches_oracle_mg_pcg():
 
 
 def test_mixed_and_fp64_2048x1024_certified():
-    # The benchmark workload: 2048x1024, thresholded {1e-6, 1} densities, 7 levels.
+    # The benchmark workload: 2048x1024, thresholded {1e-6, 1} densities, 6 levels.
     from paper_1606_06201_amd import Solver
     nel, levels, g, K0, x, f = _setup("thr2048x1024")
     K = fem.stiffness_free(g, x, K0)
