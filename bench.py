@@ -36,7 +36,7 @@ KERNEL_NAMES = {
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
                   "Galerkin element matrices formed from the fine densities on the fly",
-    "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 2>: p = -y + beta p, q = K p (FP64), p'q",
+    "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4>: p = -y + beta p, q = K p (FP64), p'q",
     "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
     "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
                 "restriction in one LDS-tiled pass",

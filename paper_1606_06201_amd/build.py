@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libipmg.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "solver.hip", "vec.hip", "ops2d.hip", "ops3d.hip"]
+SOURCES = ["api.hip", "solver.hip", "vec.hip", "dense.hip", "ops2d.hip", "ops3d.hip"]
 ARCH = os.environ.get("IPMG_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

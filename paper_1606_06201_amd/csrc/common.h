@@ -99,4 +99,34 @@ struct Red {
 // Scalar type of the V-cycle.
 enum Prec { P64 = 0, P32 = 1 };
 
+// Symmetric matrices of the coarsest-level solve are stored as the tiles (I, J),
+// I >= J, of their lower block triangle on DT x DT tiles: every tile row-major and
+// contiguous, tiles in row order (tile (I, J) at I(I+1)/2 + J).  The order is
+// padded to a multiple of DT with identity rows and columns.
+constexpr int DT = 64;
+constexpr int DENSE_MAX_N = 6000;                            // largest coarsest-level order
+constexpr int DENSE_MAX_TILES = (DENSE_MAX_N + DT - 1) / DT;
+__host__ __device__ inline int dense_tiles(int n) { return (n + DT - 1) / DT; }
+__host__ __device__ inline int64_t dense_tile_off(int I, int J) {
+  return ((int64_t)I * (I + 1) / 2 + J) * (DT * DT);
+}
+__host__ __device__ inline int64_t dense_packed_size(int n) {
+  const int nt = dense_tiles(n);
+  return (int64_t)nt * (nt + 1) / 2 * DT * DT;
+}
+// Offset of entry (r, c), r >= c or both in one diagonal tile (stored in full).
+__host__ __device__ inline int64_t dense_lower_at(int r, int c) {
+  return dense_tile_off(r / DT, c / DT) + (int64_t)(r % DT) * DT + c % DT;
+}
+// Offset of entry (r, c), r >= c, when tile (I, J) holds the transpose A_IJ' (the
+// working layout of the factorization: its tile products then read every operand
+// with the summed index first).
+__host__ __device__ inline int64_t dense_lowerT_at(int r, int c) {
+  return dense_tile_off(r / DT, c / DT) + (int64_t)(c % DT) * DT + r % DT;
+}
+// Offset of entry (r, c) of a symmetric matrix whose diagonal tiles are stored in full.
+__host__ __device__ inline int64_t dense_sym_at(int r, int c) {
+  return r / DT >= c / DT ? dense_lower_at(r, c) : dense_lower_at(c, r);
+}
+
 }  // namespace ipmg

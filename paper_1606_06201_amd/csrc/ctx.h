@@ -108,7 +108,8 @@ struct Ctx {
 
   // coarsest dense solve
   int ncoarse = 0;             // dense size incl. lambda (n_slots_coarse + 1)
-  double *dA = nullptr, *dLi = nullptr, *dAi = nullptr;
+  double *dA = nullptr, *dLi = nullptr, *dAi = nullptr;   // packed tiles: A (then L), L^-1, A^-1
+  double* dpart = nullptr;     // partial sums of the dense apply
 
   // per-level damping on the device: omega_dev[k] = weight, omega_dev[L + k] = rho estimate
   double* omega_dev = nullptr;

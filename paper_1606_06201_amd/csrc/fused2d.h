@@ -269,22 +269,28 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
   constexpr int W1 = TX + 2, H1 = TY + 2;
   for (int t = threadIdx.x; t < W0 * H0; t += NT) {
     const int gi = I0 - 2 + t % W0, gj = J0 - 2 + t / W0;
-    T o[2] = {T(0), T(0)};
-    if (node_free(d, gi, gj)) {
-      load_node<2, T>(z2, (int64_t)gj * d.nx1 + gi, o);
-      const int ni = (gi & 1) ? 2 : 1, nj = (gj & 1) ? 2 : 1;
-      for (int b = 0; b < nj; ++b)
-        for (int e = 0; e < ni; ++e) {
-          const int I = (gi >> 1) + e, J = (gj >> 1) + b;
-          const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
-          T vv[2];
-          load_node<2, T>(zc, (int64_t)J * dc.nx1 + I, vv);
-          o[0] += w * vv[0];
-          o[1] += w * vv[1];
-        }
-    }
-    s0[2 * t] = o[0];
-    s0[2 * t + 1] = o[1];
+    // z2 + P zc at free nodes, without branches around the loads: indices are
+    // clamped into the grid, the coarse corners an even coordinate does not use
+    // repeat the first one, and the select drops what is not used.
+    const bool fr = node_free(d, gi, gj);
+    const int ci = min(max(gi, 1), d.nx1 - 1), cj = min(max(gj, 0), d.ny1 - 1);
+    T o[2];
+    load_node<2, T>(z2, (int64_t)cj * d.nx1 + ci, o);
+    const int ni = (ci & 1) ? 2 : 1, nj = (cj & 1) ? 2 : 1;
+    const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool use = e < ni && b < nj;
+        const int I = (ci >> 1) + (e < ni ? e : 0), J = (cj >> 1) + (b < nj ? b : 0);
+        T vv[2];
+        load_node<2, T>(zc, (int64_t)J * dc.nx1 + I, vv);
+        o[0] += use ? w * vv[0] : T(0);
+        o[1] += use ? w * vv[1] : T(0);
+      }
+    s0[2 * t] = fr ? o[0] : T(0);
+    s0[2 * t + 1] = fr ? o[1] : T(0);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < W1 * H1; t += NT) {

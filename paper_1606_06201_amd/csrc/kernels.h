@@ -2,6 +2,8 @@
 // quadrilaterals, 3: trilinear hexahedra) and in the V-cycle precision.
 // Included by one translation unit per dimension (ops2d.hip, ops3d.hip).
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace ipmg {
@@ -300,6 +302,29 @@ struct OpCoarse2K {
   __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
     T xq[4];
     xs(ei, ej, xq);
+    diag_x(xq, a, dg);
+  }
+  // The same with the four densities already loaded (node_apply loads those of
+  // all elements around a node first, so their loads are in flight together).
+  __device__ inline void rows_x(const T* xv, int a, const T* ve, T* acc) const {
+    T s0 = 0, s1 = 0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      const T xq = q == 0 ? xv[0] : q == 1 ? xv[1] : q == 2 ? xv[2] : xv[3];
+      const int r0 = q * 64 + (a * 2) * 8;
+      T t0 = 0, t1 = 0;
+#pragma unroll
+      for (int col = 0; col < 8; ++col) {
+        t0 += g2<T>(r0 + col) * ve[col];
+        t1 += g2<T>(r0 + 8 + col) * ve[col];
+      }
+      s0 += xq * t0;
+      s1 += xq * t1;
+    }
+    acc[0] += s0;
+    acc[1] += s1;
+  }
+  __device__ inline void diag_x(const T* xq, int a, T* dg) const {
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int r = a * DIM + c;
@@ -310,6 +335,12 @@ struct OpCoarse2K {
     }
   }
 };
+
+// Operators whose per-element data node_apply loads for all elements first.
+template <class Op>
+struct preloads_x : std::false_type {};
+template <typename T>
+struct preloads_x<OpCoarse2K<2, T>> : std::true_type {};
 
 // Border of the augmented matrix (lambda row/column): b (n_slots) and corner c.
 template <typename T>
@@ -377,6 +408,21 @@ template <int DIM, typename T, class Op, bool ROWS, bool DIAG, bool INTERIOR = f
 __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int k,
                                   const T (&vn)[Geo<DIM>::NB][DIM], T* acc, T* dg) {
   constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  constexpr bool PRE = preloads_x<Op>::value;
+  T xpre[PRE ? NN : 1][4];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+      const int ex = q & 1, ey = (q >> 1) & 1;
+      int ei = i - 1 + ex, ej = j - 1 + ey;
+      if constexpr (!INTERIOR) {
+        const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+        ei = ok ? ei : 0;
+        ej = ok ? ej : 0;
+      }
+      op.xs(ei, ej, xpre[q]);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < NN; ++q) {
     const int ex = q & 1, ey = (q >> 1) & 1, ez = (q >> 2) & 1;
@@ -402,16 +448,19 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 #pragma unroll
         for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = ok ? vn[nb][c] : T(0);
       }
-      op.rows(e, ei, ej, ek, a, ve, acc);
+      if constexpr (PRE) op.rows_x(xpre[q], a, ve, acc);
+      else op.rows(e, ei, ej, ek, a, ve, acc);
     }
     if constexpr (DIAG) {
       if constexpr (INTERIOR) {
-        op.diag(e, ei, ej, ek, a, dg);
+        if constexpr (PRE) op.diag_x(xpre[q], a, dg);
+        else op.diag(e, ei, ej, ek, a, dg);
       } else {
         T dt[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) dt[c] = T(0);
-        op.diag(e, ei, ej, ek, a, dt);
+        if constexpr (PRE) op.diag_x(xpre[q], a, dt);
+        else op.diag(e, ei, ej, ek, a, dt);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) dg[c] += ok ? dt[c] : T(0);
       }
@@ -1153,22 +1202,24 @@ __global__ __launch_bounds__(BS) void k_restrict(Dims f, Dims c, const TS* __res
   T acc[DIM];
 #pragma unroll
   for (int cc = 0; cc < DIM; ++cc) acc[cc] = T(0);
-  if (I > 0) {
+  // Branch-free: every neighbour is loaded (index clamped into the grid) and the
+  // ones outside the grid, or of a clamped coarse node, are dropped by a select,
+  // so all loads are in flight together.
 #pragma unroll
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+    for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
-          if (i < 1 || i >= f.nx1 || j < 0 || j >= f.ny1 || k < 0 || k >= f.nz1) continue;
-          const T w = T(w1(dx) * w1(dy) * (DIM == 3 ? w1(dz) : 1.0f));
-          TS vv[DIM];
-          load_node<DIM, TS>(rf, ((int64_t)k * f.ny1 + j) * f.nx1 + i, vv);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
+        const bool ok = I > 0 && i >= 1 && i < f.nx1 && j >= 0 && j < f.ny1 && k >= 0 && k < f.nz1;
+        const int ic = min(max(i, 0), f.nx1 - 1), jc = min(max(j, 0), f.ny1 - 1), kc = min(max(k, 0), f.nz1 - 1);
+        const T w = T(w1(dx) * w1(dy) * (DIM == 3 ? w1(dz) : 1.0f));
+        TS vv[DIM];
+        load_node<DIM, TS>(rf, ((int64_t)kc * f.ny1 + jc) * f.nx1 + ic, vv);
 #pragma unroll
-          for (int cc = 0; cc < DIM; ++cc) acc[cc] += w * T(vv[cc]);
-        }
-  }
+        for (int cc = 0; cc < DIM; ++cc) acc[cc] += ok ? w * T(vv[cc]) : T(0);
+      }
   store_node<DIM, T>(rc, qc, acc);
 }
 
@@ -1187,16 +1238,24 @@ __global__ __launch_bounds__(BS) void k_prolong(Dims f, Dims c, T* __restrict__ 
   const int64_t q = ((int64_t)k * f.ny1 + j) * f.nx1 + i;
   T acc[DIM];
   load_node<DIM, T>(z, q, acc);
+  // The 2^dim coarse corners around the node are all loaded (a second corner
+  // along an axis where the node is even repeats the first) and the unused ones
+  // dropped by a select, so all loads are in flight together.
   const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-  for (int a = 0; a < nk; ++a)
-    for (int b = 0; b < nj; ++b)
-      for (int e = 0; e < ni; ++e) {
-        const int I = (i >> 1) + e, J = (j >> 1) + b, K = DIM == 3 ? (k >> 1) + a : 0;
-        const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f) * (nk == 2 ? 0.5f : 1.0f));
+  const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f) * (nk == 2 ? 0.5f : 1.0f));
+#pragma unroll
+  for (int a = 0; a < (DIM == 3 ? 2 : 1); ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool use = e < ni && b < nj && a < nk;
+        const int I = (i >> 1) + (e < ni ? e : 0), J = (j >> 1) + (b < nj ? b : 0);
+        const int K = DIM == 3 ? (k >> 1) + (a < nk ? a : 0) : 0;
         T vv[DIM];
         load_node<DIM, T>(zc, ((int64_t)K * c.ny1 + J) * c.nx1 + I, vv);
 #pragma unroll
-        for (int cc = 0; cc < DIM; ++cc) acc[cc] += w * vv[cc];
+        for (int cc = 0; cc < DIM; ++cc) acc[cc] += use ? w * vv[cc] : T(0);
       }
   store_node<DIM, T>(z, q, acc);
 }
@@ -1272,27 +1331,33 @@ static __global__ void k_galerkin_images2d(const double* __restrict__ K0, double
 }
 
 // ---------------------------------------------------------- coarsest solve --
-// Dense operator of the coarsest level over all slots (+ lambda): rows gathered
-// from the element matrices; clamped rows/columns replaced by identity.
+// Dense operator of the coarsest level over all slots (+ lambda) into the packed
+// tiles (zeroed, padded), each tile transposed (dense_lowerT_at) and the diagonal
+// tiles in full: rows gathered from the element matrices; clamped rows/columns
+// replaced by identity.  Thread `row` writes the entries (row, col <= row), their
+// mirror images inside a diagonal tile, and for the augmented system entry
+// (n-1, row) of the border row; no two threads write one entry.
 template <int DIM, class Op, typename TB>
 __global__ __launch_bounds__(BS) void k_dense_assemble(Op op, Dims d, const TB* border, double corner,
                                                        int aug, double* __restrict__ A, int n) {
-  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  constexpr int NN = Geo<DIM>::NN;
   const int row = blockIdx.x * BS + threadIdx.x;
   if (row >= n) return;
-  double* Ar = A + (int64_t)row * n;
-  for (int col = 0; col < n; ++col) Ar[col] = 0.0;
   if (aug && row == n - 1) {
-    for (int s = 0; s < n - 1; ++s) {
-      const int q = s / DIM;
-      Ar[s] = (q % d.nx1 == 0) ? 0.0 : (double)border[s];
-    }
-    Ar[row] = corner;
+    A[dense_lowerT_at(row, row)] = corner;
     return;
   }
   const int q = row / DIM, comp = row % DIM;
   const int i = q % d.nx1, j = (q / d.nx1) % d.ny1, k = DIM == 3 ? q / (d.nx1 * d.ny1) : 0;
-  if (i == 0) { Ar[row] = 1.0; return; }
+  if (aug) {
+    const double v = i == 0 ? 0.0 : (double)border[row];
+    A[dense_lowerT_at(n - 1, row)] = v;
+    if ((n - 1) / DT == row / DT) A[dense_lower_at(n - 1, row)] = v;
+  }
+  if (i == 0) {
+    A[dense_lowerT_at(row, row)] = 1.0;
+    return;
+  }
   for (int qq = 0; qq < NN; ++qq) {
     const int ex = qq & 1, ey = (qq >> 1) & 1, ez = (qq >> 2) & 1;
     const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
@@ -1303,10 +1368,15 @@ __global__ __launch_bounds__(BS) void k_dense_assemble(Op op, Dims d, const TB* 
       const int bi = ei + loc_x(b), bj = ej + loc_y(b), bk = DIM == 3 ? ek + loc_z(b) : 0;
       if (bi == 0) continue;
       const int qb = (bk * d.ny1 + bj) * d.nx1 + bi;
-      for (int cb = 0; cb < DIM; ++cb) Ar[qb * DIM + cb] += op.entry(e, a * DIM + comp, b * DIM + cb);
+      for (int cb = 0; cb < DIM; ++cb) {
+        const int col = qb * DIM + cb;
+        if (col > row) continue;
+        const double v = op.entry(e, a * DIM + comp, b * DIM + cb);
+        A[dense_lowerT_at(row, col)] += v;
+        if (col != row && col / DT == row / DT) A[dense_lower_at(row, col)] += v;
+      }
     }
   }
-  if (aug) Ar[n - 1] = (double)border[row];
 }
 
 }  // namespace ipmg

@@ -10,6 +10,7 @@
 #include "ctx.h"
 #include "kernels.h"
 #include "vec.h"
+#include "dense.h"
 
 namespace ipmg {
 
@@ -210,7 +211,7 @@ void ctx_free(Ctx& c) {
   c.hT = nullptr;
   dfree(c.x64); dfree(c.h64); dfree(c.bZ64);
   dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu); dfree(c.pp2);
-  dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.omega_dev);
+  dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.dpart); dfree(c.omega_dev);
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
@@ -265,10 +266,12 @@ static void jacobi_damping(Ctx& c, int k, int op) {
 static void ensure_dense(Ctx& c) {
   if (c.dA) return;
   const int64_t n = c.lev[0].d.nslots + 1;
-  IPMG_REQUIRE(n <= 6000, IPMG_E_INVALID, "coarsest level too large for the dense solve; use more levels");
-  dalloc(c.dA, sizeof(double) * n * n);
-  dalloc(c.dLi, sizeof(double) * n * n);
-  dalloc(c.dAi, sizeof(double) * n * n);
+  IPMG_REQUIRE(n <= DENSE_MAX_N, IPMG_E_INVALID, "coarsest level too large for the dense solve; use more levels");
+  const int64_t np = dense_packed_size((int)n), nt = dense_tiles((int)n);
+  dalloc(c.dA, sizeof(double) * np);
+  dalloc(c.dLi, sizeof(double) * np);
+  dalloc(c.dAi, sizeof(double) * np);
+  dalloc(c.dpart, sizeof(double) * nt * nt * DT);
 }
 
 void mg_setup(Ctx& c, int op, double* ms) {
@@ -293,9 +296,9 @@ void mg_setup(Ctx& c, int op, double* ms) {
   for (int k = 1; k < L; ++k) jacobi_damping(c, k, op);
   const int n = c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);
   IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  dense_init(c.stream, c.dA, n, 1);
   c.ops->dense_assemble(c, op, c.dA, n);
-  dense_cholesky(c.stream, c.dA, n, c.red);
-  dense_inverse(c.stream, c.dA, c.dLi, c.dAi, n);
+  dense_factor_inverse(c.stream, c.dA, c.dLi, c.dAi, n, c.red);
   IPMG_HIP(hipGetLastError());
   read_scalars(c);
   IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_BREAKDOWN, "coarsest operator is not positive definite");
@@ -316,8 +319,8 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   }
   if (k == 0) {
     const int n = l.d.nslots + aug;
-    if (c.fp32) dense_solve<float>(c.stream, c.dAi, n, (const float*)l.r, (float*)l.z, gate);
-    else dense_solve<double>(c.stream, c.dAi, n, (const double*)l.r, (double*)l.z, gate);
+    if (c.fp32) dense_apply<float>(c.stream, c.dAi, c.dpart, n, (const float*)l.r, (float*)l.z, gate);
+    else dense_apply<double>(c.stream, c.dAi, c.dpart, n, (const double*)l.r, (double*)l.z, gate);
     return l.z;
   }
   if (c.ops->fused_applies(c, k, op)) {

@@ -27,7 +27,7 @@ struct TailArgs {
   int nt;              // number of tail levels; lv[0] is the coarsest, lv[nt-1] the top
   const T* rin;        // right-hand side of the top level (global)
   T* zout;             // result of the top level (global)
-  const double* Ainv;  // dense inverse of the coarsest operator (FP64)
+  const double* Ainv;  // dense inverse of the coarsest operator (FP64, packed tiles)
   int n0;              // its size
   double c;            // corner of the augmented system
   int aug, nu1, nu2;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TopOp top, int top_is_fin
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int row = wid; row < a.n0; row += TAIL_THREADS / 64) {
       double s = 0.0;
-      for (int col = lane; col < a.n0; col += 64) s += a.Ainv[(int64_t)row * a.n0 + col] * (double)r[col];
+      for (int col = lane; col < a.n0; col += 64) s += a.Ainv[dense_sym_at(row, col)] * (double)r[col];
       s = wave_sum(s);
       if (lane == 0) z[row] = T(s);
     }

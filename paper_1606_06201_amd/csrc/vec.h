@@ -30,9 +30,5 @@ void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, c
 void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
                 double product);
 void vfill_small(hipStream_t st, double* w, int n, double value);   // n <= 64
-void dense_cholesky(hipStream_t st, double* A, int n, const Red& red);
-void dense_inverse(hipStream_t st, const double* L, double* Li, double* Ai, int n);
-template <typename T>
-void dense_solve(hipStream_t st, const double* Ai, int n, const T* rc, T* zc, const int* gate);
 
 }  // namespace ipmg

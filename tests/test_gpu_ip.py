@@ -56,7 +56,7 @@ def test_newton_system_and_z_operator(nel, levels, fp32):
 
 
 def test_z_dense_coarse_solve_many_tiles():
-    # One-level hierarchy of the augmented system: 529 unknowns (17 tiles, ragged),
+    # One-level hierarchy of the augmented system: 529 unknowns (9 tiles of 64, padded),
     # the V-cycle is the exact solve with Z.
     from paper_1606_06201_amd import Solver
     nel = (24, 10)

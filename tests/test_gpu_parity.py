@@ -86,8 +86,9 @@ def test_vcycle_matches_oracle(nel, levels, fp32, tol):
 
 @pytest.mark.parametrize("nel,levels", [((40, 18), 1), ((80, 36), 2), ((8, 4, 4), 1)])
 def test_dense_coarse_solve_many_tiles(nel, levels):
-    # The coarsest-level factorization and explicit inverse run on 32 x 32 tiles:
-    # sizes of 1520 (2D) and 600 (3D) unknowns span many tiles and end in a ragged one.
+    # The coarsest-level factorization, explicit inverse and apply run on 64 x 64
+    # tiles: sizes of 1520 (2D) and 600 (3D) unknowns span many tiles and end in a
+    # padded one.
     g, K0, x = _kproblem(nel)
     s = _solver(nel, levels)
     s.set_density(T(x))
