@@ -84,6 +84,8 @@ struct Ctx {
   bool fine_small_tiles = false;  // finest-level fused passes on 256-thread tiles
   bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32; stored levels
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
+  bool staged_down_from_x = false;   // the first coarse level's down pass staged as well
+  bool staged_big = false;           // first coarse level: staged passes on the large tiles
   int power_steps = 12;        // power iterations of the damping estimate (K)
   int power_steps_z = 30;      // ... (augmented system Z)
 

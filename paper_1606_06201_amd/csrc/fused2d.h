@@ -73,7 +73,9 @@ struct OpCoarseLDS {
 
 // Copies the stored matrices of elements [ex0, ex0+LW) x [ey0, ey0+LH) of a level
 // into LDS (zero outside the grid).  Every thread issues all of its loads before
-// its first LDS store, so the copy costs one memory latency.
+// its first LDS store, so the copy costs one memory latency: indices are clamped
+// into the grid and the (finite) value is multiplied by 0 or 1, since a select on
+// the loaded value would be compiled back into a branch around each load.
 template <typename T, int NT, int LW, int LH>
 __device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, int ex0, int ey0, T* El) {
   constexpr int NE = LW * LH, TOTAL = 36 * NE, PER = (TOTAL + NT - 1) / NT;
@@ -81,10 +83,11 @@ __device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, i
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * NT;
-    const int s = t / NE, le = t % NE;
+    const int s = min(t / NE, 35), le = t % NE;
     const int ei = ex0 + le % LW, ej = ey0 + le / LW;
     const bool in = t < TOTAL && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-    v[u] = in ? Eg[(int64_t)s * d.m + (int64_t)ej * d.nx + ei] : T(0);
+    const int eic = min(max(ei, 0), d.nx - 1), ejc = min(max(ej, 0), d.ny - 1);
+    v[u] = Eg[(int64_t)s * d.m + (int64_t)ejc * d.nx + eic] * T(in ? 1 : 0);
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -120,7 +123,8 @@ struct OpFineKLDS {
   }
 };
 
-// Densities of the elements [ex0, ex0+LW) x [ey0, ey0+LH) into LDS (zero outside).
+// Densities of the elements [ex0, ex0+LW) x [ey0, ey0+LH) into LDS (zero outside:
+// those read the zero pad after the densities, index d.m, so no load is branched).
 template <typename T, int NT, int LW, int LH>
 __device__ inline void stage_x(const T* __restrict__ x, const Dims& d, int ex0, int ey0, T* xl) {
   constexpr int NE = LW * LH, PER = (NE + NT - 1) / NT;
@@ -129,7 +133,8 @@ __device__ inline void stage_x(const T* __restrict__ x, const Dims& d, int ex0, 
   for (int u = 0; u < PER; ++u) {
     const int le = threadIdx.x + u * NT;
     const int ei = ex0 + le % LW, ej = ey0 + le / LW;
-    v[u] = (le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny) ? x[(int64_t)ej * d.nx + ei] : T(0);
+    const bool in = le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+    v[u] = x[in ? (int64_t)ej * d.nx + ei : d.m];
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -154,9 +159,10 @@ __device__ inline void stage_from_x(const float* __restrict__ x, int fnx, const 
     const int le = threadIdx.x + u * NT;
     const int ei = ex0 + le % LW, ej = ey0 + le / LW;
     const bool in = le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-    const int64_t b = in ? (int64_t)(2 * ej) * fnx + 2 * ei : 0;
+    // outside the grid: the zero pad after the fine densities (fine m = fnx * 2 ny)
+    const int64_t b = in ? (int64_t)(2 * ej) * fnx + 2 * ei : (int64_t)fnx * 2 * d.ny;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xs[u][q] = in ? x[b + (q >> 1) * fnx + (q & 1)] : 0.0f;
+    for (int q = 0; q < 4; ++q) xs[u][q] = x[b + (q >> 1) * fnx + (q & 1)];
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -174,21 +180,81 @@ __device__ inline void stage_from_x(const float* __restrict__ x, int fnx, const 
   }
 }
 
+// Global operands of the first phase of a down tile (r on region 1) and of the
+// first two phases of an up tile (z2 and the coarse corners on region 0, r on
+// region 1).  Kernels load them before they stage element data, so all of a
+// thread's global loads are in flight together.  A node that is not free reads the
+// clamped node (0, j) of its row, where every level vector is zero, so no load sits
+// under a branch.
+template <typename T, int CX, int CY, int NT>
+struct DownLoads {
+  static constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, P1 = (W1 * H1 + NT - 1) / NT;
+  T r[P1][2];
+  __device__ inline void load(const Dims& d, int CI0, int CJ0, const T* __restrict__ rg) {
+    const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
+#pragma unroll
+    for (int u = 0; u < P1; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int gi = ox + t % W1, gj = oy + t / W1;
+      const bool fr = t < W1 * H1 && node_free(d, gi, gj);
+      load_node<2, T>(rg, (int64_t)min(max(gj, 0), d.ny1 - 1) * d.nx1 + (fr ? gi : 0), r[u]);
+    }
+  }
+};
+
+template <typename T, int TX, int TY, int NT>
+struct UpLoads {
+  static constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  static constexpr int P0 = (W0 * H0 + NT - 1) / NT, P1 = (W1 * H1 + NT - 1) / NT;
+  T z[P0][2], c[P0][4][2], r[P1][2];
+  // Region 0: z2 at the node and the four coarse corners around it (indices
+  // clamped into the grid; a second corner along an axis where the node is even
+  // repeats the first).  Region 1: r.
+  __device__ inline void load(const Dims& d, const Dims& dc, int I0, int J0, const T* __restrict__ rg,
+                              const T* __restrict__ z2, const T* __restrict__ zc) {
+#pragma unroll
+    for (int u = 0; u < P0; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int gi = I0 - 2 + t % W0, gj = J0 - 2 + t / W0;
+      const int ci = min(max(gi, 1), d.nx1 - 1), cj = min(max(gj, 0), d.ny1 - 1);
+      load_node<2, T>(z2, (int64_t)cj * d.nx1 + ci, z[u]);
+      const int i1 = (ci & 1) ? 1 : 0, j1 = (cj & 1) ? 1 : 0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          load_node<2, T>(zc, (int64_t)((cj >> 1) + b * j1) * dc.nx1 + (ci >> 1) + e * i1, c[u][2 * b + e]);
+    }
+#pragma unroll
+    for (int u = 0; u < P1; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int gi = I0 - 1 + t % W1, gj = J0 - 1 + t / W1;
+      const bool fr = t < W1 * H1 && node_free(d, gi, gj);
+      load_node<2, T>(rg, (int64_t)min(max(gj, 0), d.ny1 - 1) * d.nx1 + (fr ? gi : 0), r[u]);
+    }
+  }
+};
+
 // Down pass of one tile of CX x CY coarse nodes with corner (CI0, CJ0).  LDS:
 // sr, sd, s1 over region 1 ((2CX+5) x (2CY+5) fine nodes from (2CI0-3, 2CJ0-3)),
 // s2 over region 2 (one node inside), s3 over region 3 (two nodes inside).
 template <typename T, class Op, int CX, int CY, int NT>
-__device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, int CI0, int CJ0, const T* r,
-                                 T* z2out, T* rc, T omega, T* sr, T* sd, T* s1, T* s2, T* s3) {
+__device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, int CI0, int CJ0,
+                                 const DownLoads<T, CX, CY, NT>& pre, T* z2out, T* rc, T omega, T* sr, T* sd,
+                                 T* s1, T* s2, T* s3) {
   constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5;
   constexpr int W2 = W1 - 2, H2 = H1 - 2;
   constexpr int W3 = W1 - 4, H3 = H1 - 4;
   const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
-  for (int t = threadIdx.x; t < W1 * H1; t += NT) {
+#pragma unroll
+  for (int u = 0; u < DownLoads<T, CX, CY, NT>::P1; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t >= W1 * H1) break;
     const int gi = ox + t % W1, gj = oy + t / W1;
     T rr[2] = {T(0), T(0)}, dg[2] = {T(0), T(0)}, o[2] = {T(0), T(0)};
     if (node_free(d, gi, gj)) {
-      load_node<2, T>(r, (int64_t)gj * d.nx1 + gi, rr);
+      rr[0] = pre.r[u][0];
+      rr[1] = pre.r[u][1];
       T vn[9][2], acc[2] = {T(0), T(0)};
       node_apply<2, T, Op, false, true, false>(op, d, gi, gj, 0, vn, acc, dg);
 #pragma unroll
@@ -262,20 +328,21 @@ __device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, in
 // dot64 (optional): accumulate dot64' out over the tile's nodes into red0 (the
 // PCG ratio of the finest level, Algorithm PCG).
 template <typename T, class Op, int TX, int TY, int NT>
-__device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0, const T* r, const T* z2,
-                               const T* zc, T* out, T omega, T* s0, T* sr, T* sd, T* s1,
+__device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0,
+                               const UpLoads<T, TX, TY, NT>& pre, T* out, T omega, T* s0, T* sr, T* sd, T* s1,
                                const double* dot64 = nullptr, double* red0 = nullptr) {
   constexpr int W0 = TX + 4, H0 = TY + 4;
   constexpr int W1 = TX + 2, H1 = TY + 2;
-  for (int t = threadIdx.x; t < W0 * H0; t += NT) {
+#pragma unroll
+  for (int u = 0; u < UpLoads<T, TX, TY, NT>::P0; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t >= W0 * H0) break;
     const int gi = I0 - 2 + t % W0, gj = J0 - 2 + t / W0;
-    // z2 + P zc at free nodes, without branches around the loads: indices are
-    // clamped into the grid, the coarse corners an even coordinate does not use
-    // repeat the first one, and the select drops what is not used.
+    // z2 + P zc at free nodes (operands from UpLoads; the select drops the corners
+    // an even coordinate does not use)
     const bool fr = node_free(d, gi, gj);
     const int ci = min(max(gi, 1), d.nx1 - 1), cj = min(max(gj, 0), d.ny1 - 1);
-    T o[2];
-    load_node<2, T>(z2, (int64_t)cj * d.nx1 + ci, o);
+    T o[2] = {pre.z[u][0], pre.z[u][1]};
     const int ni = (ci & 1) ? 2 : 1, nj = (cj & 1) ? 2 : 1;
     const T w = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
 #pragma unroll
@@ -283,22 +350,23 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const bool use = e < ni && b < nj;
-        const int I = (ci >> 1) + (e < ni ? e : 0), J = (cj >> 1) + (b < nj ? b : 0);
-        T vv[2];
-        load_node<2, T>(zc, (int64_t)J * dc.nx1 + I, vv);
-        o[0] += use ? w * vv[0] : T(0);
-        o[1] += use ? w * vv[1] : T(0);
+        o[0] += use ? w * pre.c[u][2 * b + e][0] : T(0);
+        o[1] += use ? w * pre.c[u][2 * b + e][1] : T(0);
       }
     s0[2 * t] = fr ? o[0] : T(0);
     s0[2 * t + 1] = fr ? o[1] : T(0);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < W1 * H1; t += NT) {
+#pragma unroll
+  for (int u = 0; u < UpLoads<T, TX, TY, NT>::P1; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t >= W1 * H1) break;
     const int li = t % W1, lj = t / W1;                 // position in region 1
     const int gi = I0 - 1 + li, gj = J0 - 1 + lj;
     T rr[2] = {T(0), T(0)}, dg[2] = {T(0), T(0)}, o[2] = {T(0), T(0)};
     if (node_free(d, gi, gj)) {
-      load_node<2, T>(r, (int64_t)gj * d.nx1 + gi, rr);
+      rr[0] = pre.r[u][0];
+      rr[1] = pre.r[u][1];
       T vn[9][2], acc[2] = {T(0), T(0)};
       lds_neighbourhood<T>(s0, W0, li + 1, lj + 1, vn);
       node_apply<2, T, Op, true, true, false>(op, d, gi, gj, 0, vn, acc, dg);
@@ -338,7 +406,9 @@ __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T*
   constexpr int W1 = 2 * FCX + 5, H1 = 2 * FCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
   const Tile tl = xcd_tile();
-  down_tile<T, Op, FCX, FCY, FBS>(op, d, dc, (int)tl.x * FCX, (int)tl.y * FCY, r, z2out, rc, T(*omg), sr, sd, s1,
+  DownLoads<T, FCX, FCY, FBS> pre;
+  pre.load(d, (int)tl.x * FCX, (int)tl.y * FCY, r);
+  down_tile<T, Op, FCX, FCY, FBS>(op, d, dc, (int)tl.x * FCX, (int)tl.y * FCY, pre, z2out, rc, T(*omg), sr, sd, s1,
                                   s2, s3);
 }
 
@@ -352,57 +422,65 @@ __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* _
   constexpr int W0 = FTX + 4, H0 = FTY + 4, W1 = FTX + 2, H1 = FTY + 2;
   __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
   const Tile tl = xcd_tile();
-  up_tile<T, Op, FTX, FTY, FBS>(op, d, dc, (int)tl.x * FTX, (int)tl.y * FTY, r, z2, zc, out, T(*omg), s0, sr, sd,
-                                s1);
+  UpLoads<T, FTX, FTY, FBS> pre;
+  pre.load(d, dc, (int)tl.x * FTX, (int)tl.y * FTY, r, z2, zc);
+  up_tile<T, Op, FTX, FTY, FBS>(op, d, dc, (int)tl.x * FTX, (int)tl.y * FTY, pre, out, T(*omg), s0, sr, sd, s1);
 }
 
-// Stored FP32 element matrices staged in LDS.  Grid: (ceil(dc.nx1 / SCX), ceil(dc.ny1 / SCY)).
-// Region 1 of a tile has nodes (2CI0-3 .. 2CI0+2SCX+1); the elements around them
-// are (2CI0-4 .. 2CI0+2SCX+1) x (2CJ0-4 .. 2CJ0+2SCY+1).
+// Stored FP32 element matrices staged in LDS, tiles of CX x CY coarse nodes and NT
+// threads.  Grid: (ceil(dc.nx1 / CX), ceil(dc.ny1 / CY)).  Region 1 of a tile has
+// nodes (2CI0-3 .. 2CI0+2CX+1); the elements around them are
+// (2CI0-4 .. 2CI0+2CX+1) x (2CJ0-4 .. 2CJ0+2CY+1).
 // FROM_X: the level is the first coarse level formed from the densities x (fnx
-// finest elements along x) instead of stored matrices Eg.
-template <bool FROM_X>
-__global__ __launch_bounds__(SBS) void k_down2d_staged(const float* __restrict__ Eg, const float* __restrict__ x,
-                                                       int fnx, Dims d, Dims dc, const float* __restrict__ r,
-                                                       float* __restrict__ z2out, float* __restrict__ rc,
-                                                       const double* __restrict__ omg, const int* gate) {
+// finest elements along x) instead of stored matrices Eg.  Large tiles (more than
+// 64 KB of LDS, one workgroup per CU) form fewer halo elements twice.
+template <bool FROM_X, int CX = SCX, int CY = SCY, int NT = SBS>
+__global__ __launch_bounds__(NT) void k_down2d_staged(const float* __restrict__ Eg, const float* __restrict__ x,
+                                                      int fnx, Dims d, Dims dc, const float* __restrict__ r,
+                                                      float* __restrict__ z2out, float* __restrict__ rc,
+                                                      const double* __restrict__ omg, const int* gate) {
   if (gate && *gate) return;
-  constexpr int W1 = 2 * SCX + 5, H1 = 2 * SCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   constexpr int LW = W1 + 1, LH = H1 + 1;
   __shared__ float El[36 * LW * LH];
   __shared__ float sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
   const Tile tl = xcd_tile();
-  const int CI0 = (int)tl.x * SCX, CJ0 = (int)tl.y * SCY;
+  const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
   const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
-  if constexpr (FROM_X) stage_from_x<SBS, LW, LH>(x, fnx, d, ex0, ey0, El);
-  else stage_elements<float, SBS, LW, LH>(Eg, d, ex0, ey0, El);
+  DownLoads<float, CX, CY, NT> pre;
+  pre.load(d, CI0, CJ0, r);
+  if constexpr (FROM_X) stage_from_x<NT, LW, LH>(x, fnx, d, ex0, ey0, El);
+  else stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
   __syncthreads();
   const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
-  down_tile<float, OpCoarseLDS<float>, SCX, SCY, SBS>(op, d, dc, CI0, CJ0, r, z2out, rc, float(*omg), sr, sd, s1,
-                                                      s2, s3);
+  down_tile<float, OpCoarseLDS<float>, CX, CY, NT>(op, d, dc, CI0, CJ0, pre, z2out, rc, float(*omg), sr, sd, s1, s2,
+                                                   s3);
 }
 
-// Grid: (ceil(d.nx1 / STX), ceil(d.ny1 / STY)).  Region 1 has nodes
-// (I0-1 .. I0+STX); the elements around them are (I0-2 .. I0+STX) x (J0-2 .. J0+STY).
-template <bool FROM_X>
-__global__ __launch_bounds__(SBS) void k_up2d_staged(const float* __restrict__ Eg, const float* __restrict__ x, int fnx,
-                                                     Dims d, Dims dc, const float* __restrict__ r,
-                                                     const float* __restrict__ z2, const float* __restrict__ zc,
-                                                     float* __restrict__ out, const double* __restrict__ omg,
-                                                     const int* gate) {
+// Tiles of TX x TY fine nodes and NT threads.  Grid: (ceil(d.nx1 / TX),
+// ceil(d.ny1 / TY)).  Region 1 has nodes (I0-1 .. I0+TX); the elements around them
+// are (I0-2 .. I0+TX) x (J0-2 .. J0+TY).
+template <bool FROM_X, int TX = STX, int TY = STY, int NT = SBS>
+__global__ __launch_bounds__(NT) void k_up2d_staged(const float* __restrict__ Eg, const float* __restrict__ x, int fnx,
+                                                    Dims d, Dims dc, const float* __restrict__ r,
+                                                    const float* __restrict__ z2, const float* __restrict__ zc,
+                                                    float* __restrict__ out, const double* __restrict__ omg,
+                                                    const int* gate) {
   if (gate && *gate) return;
-  constexpr int W0 = STX + 4, H0 = STY + 4, W1 = STX + 2, H1 = STY + 2;
+  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int LW = W1 + 1, LH = H1 + 1;
   __shared__ float El[36 * LW * LH];
   __shared__ float s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
   const Tile tl = xcd_tile();
-  const int I0 = (int)tl.x * STX, J0 = (int)tl.y * STY;
+  const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
   const int ex0 = I0 - 2, ey0 = J0 - 2;
-  if constexpr (FROM_X) stage_from_x<SBS, LW, LH>(x, fnx, d, ex0, ey0, El);
-  else stage_elements<float, SBS, LW, LH>(Eg, d, ex0, ey0, El);
+  UpLoads<float, TX, TY, NT> pre;
+  pre.load(d, dc, I0, J0, r, z2, zc);
+  if constexpr (FROM_X) stage_from_x<NT, LW, LH>(x, fnx, d, ex0, ey0, El);
+  else stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
   __syncthreads();
   const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
-  up_tile<float, OpCoarseLDS<float>, STX, STY, SBS>(op, d, dc, I0, J0, r, z2, zc, out, float(*omg), s0, sr, sd, s1);
+  up_tile<float, OpCoarseLDS<float>, TX, TY, NT>(op, d, dc, I0, J0, pre, out, float(*omg), s0, sr, sd, s1);
 }
 
 // Finest level of K (densities x, V-cycle precision T), tiles of CX x CY coarse
@@ -421,10 +499,12 @@ __global__ __launch_bounds__(NT) void k_down2d_fine(const T* __restrict__ x, Dim
   const Tile tl = xcd_tile();
   const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
   const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
+  DownLoads<T, CX, CY, NT> pre;
+  pre.load(d, CI0, CJ0, r);
   stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
   __syncthreads();
   const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
-  down_tile<T, OpFineKLDS<T>, CX, CY, NT>(op, d, dc, CI0, CJ0, r, z2out, rc, T(*omg), sr, sd, s1, s2, s3);
+  down_tile<T, OpFineKLDS<T>, CX, CY, NT>(op, d, dc, CI0, CJ0, pre, z2out, rc, T(*omg), sr, sd, s1, s2, s3);
 }
 
 // Tiles of TX x TY fine nodes, NT threads.  Grid: (ceil(d.nx1 / TX), ceil(d.ny1 /
@@ -445,11 +525,13 @@ __global__ __launch_bounds__(NT) void k_up2d_fine(const T* __restrict__ x, Dims 
   const Tile tl = xcd_tile();
   const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
   const int ex0 = I0 - 2, ey0 = J0 - 2;
+  UpLoads<T, TX, TY, NT> pre;
+  pre.load(d, dc, I0, J0, r, z2, zc);
   stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
   __syncthreads();
   const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
   double red0 = 0.0;
-  up_tile<T, OpFineKLDS<T>, TX, TY, NT>(op, d, dc, I0, J0, r, z2, zc, out, T(*omg), s0, sr, sd, s1,
+  up_tile<T, OpFineKLDS<T>, TX, TY, NT>(op, d, dc, I0, J0, pre, out, T(*omg), s0, sr, sd, s1,
                                         BETA ? dot64 : nullptr, &red0);
   if constexpr (BETA) {
     const double vals[1] = {red0};

@@ -267,10 +267,15 @@ struct OpCoarse {
 // density per fine element instead of 36 matrix entries per coarse element.
 template <int DIM, typename T>
 struct OpCoarse2K {
-  const T* x;      // finest-level densities
+  const T* x;      // finest-level densities, followed by a zero pad of fnx + 2 entries
   int fnx;         // finest-level elements along x
-  __device__ inline void xs(int ei, int ej, T* xq) const {
-    const int64_t b = (int64_t)(2 * ej) * fnx + 2 * ei;
+  int64_t fm;      // finest-level element count (start of the zero pad)
+  __device__ inline void xs(int ei, int ej, T* xq) const { xs_at((int64_t)(2 * ej) * fnx + 2 * ei, xq); }
+  // ok false: the four values come from the zero pad (an element outside the grid)
+  __device__ inline void xs_or_zero(bool ok, int ei, int ej, T* xq) const {
+    xs_at(ok ? (int64_t)(2 * ej) * fnx + 2 * ei : fm, xq);
+  }
+  __device__ inline void xs_at(int64_t b, T* xq) const {
     xq[0] = x[b];
     xq[1] = x[b + 1];
     xq[2] = x[b + fnx];
@@ -414,13 +419,8 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
       const int ex = q & 1, ey = (q >> 1) & 1;
-      int ei = i - 1 + ex, ej = j - 1 + ey;
-      if constexpr (!INTERIOR) {
-        const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-        ei = ok ? ei : 0;
-        ej = ok ? ej : 0;
-      }
-      op.xs(ei, ej, xpre[q]);
+      const int ei = i - 1 + ex, ej = j - 1 + ey;
+      op.xs_or_zero(INTERIOR || (ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny), ei, ej, xpre[q]);
     }
   }
 #pragma unroll
@@ -500,6 +500,47 @@ __device__ inline double recip(double v) { return 1.0 / v; }
 // value vc (unused for M_JACOBI0).  Adds the border term b*v_lambda and
 // accumulates the border dot b.v (augmented system) in bdot and the mode's
 // reduction terms in red0/red1.
+template <int MODE>
+constexpr bool mode_reads_r() {
+  return MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA;
+}
+
+// As level_node_finish with the node's entries of r (rr), of dot64 (d64, M_JACOBI_BETA)
+// and of the border (bb, when augb) already loaded.
+template <int DIM, typename T, int MODE>
+__device__ inline void level_node_finish_vals(int64_t q, T* acc, const T* dg, const T* vc, const T* rr, T* out,
+                                              T omega, bool augb, const T* bb, T vl, double pin, const double* d64,
+                                              double& bdot, double& red0, double& red1) {
+  constexpr bool NEED_ROWS = MODE != M_JACOBI0;
+  T o[DIM];
+  if constexpr (NEED_ROWS) {
+    if (augb) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        acc[c] += bb[c] * vl;
+        bdot += (double)bb[c] * (double)vc[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if constexpr (MODE == M_APPLY) o[c] = acc[c];
+    if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
+    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
+    if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
+    if constexpr (MODE == M_POWER) {
+      o[c] = T(pin * (double)(acc[c] / dg[c]));
+      red0 += (double)o[c] * (double)o[c];
+    }
+    if constexpr (MODE == M_RAYLEIGH) {
+      red0 += (double)vc[c] * (double)acc[c];
+      red1 += (double)vc[c] * (double)dg[c] * (double)vc[c];
+    }
+    if constexpr (MODE == M_JACOBI_BETA) red0 += d64[c] * (double)o[c];
+  }
+  if constexpr (MODE != M_RAYLEIGH) store_node<DIM, T>(out, q, o);
+}
+
 template <int DIM, typename T, int MODE>
 __device__ inline void level_node_finish(int64_t q, T* acc, const T* dg, const T* vc, const T* r, T* out,
                                          T omega, const T* augb, T vl, double pin, const double* dot64,
@@ -517,7 +558,7 @@ __device__ inline void level_node_finish(int64_t q, T* acc, const T* dg, const T
     }
   }
   T rr[DIM];
-  if constexpr (MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA)
+  if constexpr (mode_reads_r<MODE>())
     load_node<DIM, T>(r, q, rr);
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
@@ -771,14 +812,24 @@ struct TileApply<T, OpFineK<2, T>, ROWS, NJ> {
   __device__ static inline void run(const OpFineK<2, T>& op, const Dims& d, int i, int j0,
                                     const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
     T xe[NJ + 1][2];
+    load_x<EDGE>(op, d, i, j0, xe);
+    run_x(xe, w, acc, dg);
+  }
+  // Elements outside the grid read the zero pad after the densities (index m), so
+  // the loads need no branch and no select.
+  template <bool EDGE>
+  __device__ static inline void load_x(const OpFineK<2, T>& op, const Dims& d, int i, int j0, T (&xe)[NJ + 1][2]) {
 #pragma unroll
     for (int er = 0; er <= NJ; ++er)
 #pragma unroll
       for (int ec = 0; ec < 2; ++ec) {
         const int ei = i - 1 + ec, ej = j0 - 1 + er;
-        if (!EDGE || elem_in(d, ei, ej)) xe[er][ec] = op.x[(int64_t)ej * d.nx + ei];
-        else xe[er][ec] = T(0);
+        const int64_t e = (int64_t)ej * d.nx + ei;
+        xe[er][ec] = op.x[(!EDGE || elem_in(d, ei, ej)) ? e : op.m];
       }
+  }
+  __device__ static inline void run_x(const T (&xe)[NJ + 1][2], const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2],
+                                      T (&dg)[NJ][2]) {
 #pragma unroll
     for (int n = 0; n < NJ; ++n) {
       acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
@@ -823,12 +874,7 @@ struct TileApply<T, OpCoarse2K<2, T>, ROWS, NJ> {
 #pragma unroll
       for (int ec = 0; ec < 2; ++ec) {
         const int ei = i - 1 + ec, ej = j0 - 1 + er;
-        if (!EDGE || elem_in(d, ei, ej)) {
-          op.xs(ei, ej, xs[er][ec]);
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) xs[er][ec][t] = T(0);
-        }
+        op.xs_or_zero(!EDGE || elem_in(d, ei, ej), ei, ej, xs[er][ec]);   // zero pad outside: no branch
       }
 #pragma unroll
     for (int n = 0; n < NJ; ++n) acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
@@ -878,12 +924,17 @@ __device__ inline void load_tile(const T* __restrict__ v, const Dims& d, int i, 
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       const int ii = i - 1 + cc, jj = j0 - 1 + rr;
-      if (!EDGE || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1)) {
+      if (!EDGE) {
         const unsigned o = 2u * ((unsigned)jj * (unsigned)d.nx1 + (unsigned)ii);
         w[rr][cc][0] = v[o];
         w[rr][cc][1] = v[o + 1];
-      } else {
-        w[rr][cc][0] = w[rr][cc][1] = T(0);
+      } else {                                     // clamped index, selected value: no branch
+        const bool ok = ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1;
+        const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 +
+                                 (unsigned)min(max(ii, 0), d.nx1 - 1));
+        const T a = v[o], b = v[o + 1];
+        w[rr][cc][0] = ok ? a : T(0);
+        w[rr][cc][1] = ok ? b : T(0);
       }
     }
 }
@@ -910,6 +961,23 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   double bdot = 0.0, red0 = 0.0, red1 = 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
   constexpr bool ROWS = MODE != M_JACOBI0;
+  // The thread's entries of r, of the FP64 dot vector and of the border are loaded
+  // first, without branches (index clamped into the grid), so they are in flight
+  // with the tile's loads instead of waiting one by one after the arithmetic.
+  T rpre[NJ][2], bpre[NJ][2];
+  double dpre[NJ][2];
+#pragma unroll
+  for (int n = 0; n < NJ; ++n) {
+    const int j = min(j0 + n, d.ny1 - 1), ic = min(i, d.nx1 - 1);
+    const int64_t q = (int64_t)j * d.nx1 + ic;
+    if constexpr (mode_reads_r<MODE>()) load_node<2, T>(r, q, rpre[n]);
+    if constexpr (MODE == M_JACOBI_BETA) {
+      const double2 t = *reinterpret_cast<const double2*>(dot64 + 2 * q);
+      dpre[n][0] = t.x;
+      dpre[n][1] = t.y;
+    }
+    if (ROWS && aug.b) load_node<2, T>(aug.b, q, bpre[n]);
+  }
   T w[NJ + 2][3][2];
   T acc[NJ][2], dg[NJ][2];
   if (interior) {
@@ -930,7 +998,8 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
       continue;
     }
     const T vc[2] = {ROWS ? w[n + 1][1][0] : T(0), ROWS ? w[n + 1][1][1] : T(0)};
-    level_node_finish<2, T, MODE>(q, acc[n], dg[n], vc, r, out, omega, aug.b, vl, 1.0, dot64, bdot, red0, red1);
+    level_node_finish_vals<2, T, MODE>(q, acc[n], dg[n], vc, rpre[n], out, omega, aug.b != nullptr, bpre[n], vl,
+                                       1.0, dpre[n], bdot, red0, red1);
   }
   if (aug.b) {
     if constexpr (MODE == M_JACOBI0) {
@@ -1043,8 +1112,15 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
   double pq = 0.0, bdot = 0.0, qy = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
-  // p = -y + beta p_old on the neighbourhood, combined as each node is loaded;
-  // yc keeps y on the thread's own nodes (for q'y)
+  // p = -y + beta p_old on the neighbourhood; yc keeps y on the thread's own nodes
+  // (for q'y).  A neighbour outside the grid or clamped is read at the clamped node
+  // (0, j) of its row, where y and p_old are zero, so no load sits under a branch
+  // or feeds a select and all of them are in flight together.  (p_old is finite
+  // on the first iteration too: both direction buffers start zeroed.)
+  const double bf = first ? 0.0 : beta;
+  constexpr bool FINE_K = std::is_same<Op, OpFineK<2, double>>::value;
+  double xe[NJ + 1][2];                    // densities, loaded first (finest-level K)
+  if constexpr (FINE_K) TileApply<double, Op, true, NJ>::template load_x<true>(op, d, i, j0, xe);
   TY yc[NJ][2];
   double w[NJ + 2][3][2], acc[NJ][2], dg[NJ][2];
 #pragma unroll
@@ -1052,22 +1128,25 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       const int ii = i - 1 + cc, jj = j0 - 1 + rr;
-      TY yy[2] = {TY(0), TY(0)};
-      double po[2] = {0.0, 0.0};
-      if (interior || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1)) {
-        const int64_t qq = (int64_t)jj * d.nx1 + ii;
-        load_node<2, TY>(y, qq, yy);
-        if (!first) load_node<2, double>(pold, qq, po);
-      }
+      const bool ok = interior || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1);
+      const int64_t qq = (int64_t)min(max(jj, 0), d.ny1 - 1) * d.nx1 + (ok ? ii : 0);
+      TY yy[2];
+      double po[2];
+      load_node<2, TY>(y, qq, yy);
+      load_node<2, double>(pold, qq, po);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) w[rr][cc][c] = -(double)yy[c] + (first ? 0.0 : beta * po[c]);
+      for (int c = 0; c < 2; ++c) w[rr][cc][c] = -(double)yy[c] + bf * po[c];
       if (cc == 1 && rr >= 1 && rr <= NJ) {
         yc[rr - 1][0] = yy[0];
         yc[rr - 1][1] = yy[1];
       }
     }
-  if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
-  else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
+  if constexpr (FINE_K) {
+    TileApply<double, Op, true, NJ>::run_x(xe, w, acc, dg);
+  } else {
+    if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
+    else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
+  }
 #pragma unroll
   for (int n = 0; n < NJ; ++n) {
     const int j = j0 + n;

@@ -431,7 +431,7 @@ struct OpsImpl : Ops {
         launch_level<T>(c, d, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, mode, (const T*)v, (const T*)r,
                         (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else if (DIM == 2 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x) {
-      launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx}, mode, (const T*)v, (const T*)r,
+      launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, mode, (const T*)v, (const T*)r,
                       (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else {
       launch_level<T>(c, d, OpCoarse<DIM, T>{(const T*)c.lev[lev].E, d.m}, mode, (const T*)v, (const T*)r, (T*)out,
@@ -568,16 +568,27 @@ struct OpsImpl : Ops {
       // measured: the down pass of the first coarse level is faster unstaged (its
       // small staged tiles form each halo element matrix again)
       const bool from_x = lev == c.L - 2 && c.coarse_from_x;
-      if (c.fused_staged && !from_x && d.nnodes < c.staged_max_nodes) {
+      if (c.fused_staged && from_x && c.staged_big) {
+        k_down2d_staged<true, FCX, FCY, FBS><<<g, FBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
+                                                                     (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
+                                                                     (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+        return;
+      }
+      if (c.fused_staged && ((!from_x && d.nnodes < c.staged_max_nodes) || (from_x && c.staged_down_from_x))) {
         const dim3 gs((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
-        k_down2d_staged<false><<<gs, SBS, 0, c.stream>>>((const float*)c.lev[lev].E, nullptr, 0, d, dc,
-                                                         (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
-                                                         (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+        if (from_x)
+          k_down2d_staged<true><<<gs, SBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
+                                                          (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
+                                                          (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+        else
+          k_down2d_staged<false><<<gs, SBS, 0, c.stream>>>((const float*)c.lev[lev].E, nullptr, 0, d, dc,
+                                                           (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
+                                                           (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
         return;
       }
     }
     if (lev == c.L - 2 && c.coarse_from_x)
-      k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
+      k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, d, dc,
                                                                (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
                                                                (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
     else
@@ -625,6 +636,13 @@ struct OpsImpl : Ops {
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
     if constexpr (std::is_same<T, float>::value) {
       const bool from_x = lev == c.L - 2 && c.coarse_from_x;
+      if (c.fused_staged && from_x && c.staged_big) {
+        k_up2d_staged<true, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
+                                                                   (const float*)c.lev[lev].r,
+                                                                   (const float*)c.lev[lev].z, (const float*)zc,
+                                                                   (float*)out, c.omega_dev + lev, gate);
+        return;
+      }
       if (c.fused_staged && (from_x || d.nnodes < c.staged_max_nodes)) {
         const dim3 gs((unsigned)((d.nx1 + STX - 1) / STX), (unsigned)((d.ny1 + STY - 1) / STY), 1);
         const float* E = (const float*)c.lev[lev].E;
@@ -641,7 +659,7 @@ struct OpsImpl : Ops {
       }
     }
     if (lev == c.L - 2 && c.coarse_from_x)
-      k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx}, d, dc,
+      k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, d, dc,
                                                              (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
                                                              (const T*)zc, (T*)out, c.omega_dev + lev, gate);
     else

@@ -115,6 +115,9 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNSTAGED")) c.fused_staged = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_STAGED_MAX_NODES")) c.staged_max_nodes = std::max<int64_t>(0, std::atoll(e));
+  if (const char* e = std::getenv("IPMG_STAGED_DOWN_FROM_X")) c.staged_down_from_x = e[0] == '1';
+  if (const char* e = std::getenv("IPMG_STAGED_BIG")) c.staged_big = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -168,9 +171,17 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
       else l.E = l.E64;
     }
   }
-  dalloc(c.x64, sizeof(double) * fd.m);
-  if (c.fp32) dalloc(c.xT, sizeof(float) * fd.m);
-  else c.xT = c.x64;
+  // Densities, followed by a zero pad of nx + 2 entries: kernels read an element
+  // outside the grid (or a 2 x 2 block of them) there instead of branching.
+  const int64_t xn = fd.m + fd.nx + 2;
+  dalloc(c.x64, sizeof(double) * xn);
+  IPMG_HIP(hipMemsetAsync(c.x64, 0, sizeof(double) * xn, st));
+  if (c.fp32) {
+    dalloc(c.xT, sizeof(float) * xn);
+    IPMG_HIP(hipMemsetAsync(c.xT, 0, sizeof(float) * xn, st));
+  } else {
+    c.xT = c.x64;
+  }
   const size_t n1 = (size_t)fd.nslots + 1;
   dalloc(c.pr, sizeof(double) * n1);
   dalloc(c.pp, sizeof(double) * n1);
@@ -179,6 +190,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   dalloc(c.pb, sizeof(double) * n1);
   dalloc(c.pu, sizeof(double) * n1);
   dalloc(c.pp2, sizeof(double) * n1);
+  vfill(st, c.pp, 0.0, (int64_t)n1);    // the direction kernel reads p_old (times 0) on the first iteration
+  vfill(st, c.pp2, 0.0, (int64_t)n1);
   dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
   vfill_small(st, c.omega_dev, c.L, d.omega);
 

@@ -69,21 +69,62 @@ __global__ __launch_bounds__(BS) void k_dot(const TA* __restrict__ a, const TB* 
 }
 
 // z += alpha p; r += alpha q; rT = (T) r; ||r||^2 -> convergence flag.
+// Each thread takes pairs of entries (16-byte accesses), two pairs per step with
+// all eight loads issued first, so enough bytes are in flight to stream at the
+// HBM rate; an odd last entry is taken by the first thread.
+template <typename T>
+__device__ inline void store_pair(T* p, double a, double b) {
+  if constexpr (sizeof(T) == 8) *reinterpret_cast<double2*>(p) = make_double2(a, b);
+  else *reinterpret_cast<float2*>(p) = make_float2((float)a, (float)b);
+}
+
 template <typename T>
 __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, double* __restrict__ r,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    T* __restrict__ rT, int64_t n, Red red, const int* gate) {
   if (gate && *gate) return;
   const double alpha = red.scal[S_ALPHA];
-  double s = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
-    z[t] += alpha * p[t];
-    const double rn = r[t] + alpha * q[t];
-    r[t] = rn;
-    if (rT) rT[t] = T(rn);
-    s += rn * rn;
+  double s0 = 0.0, s1 = 0.0;
+  const int64_t np = n / 2, stride = (int64_t)gridDim.x * BS;
+  double2* z2 = reinterpret_cast<double2*>(z);
+  double2* r2 = reinterpret_cast<double2*>(r);
+  const double2* p2 = reinterpret_cast<const double2*>(p);
+  const double2* q2 = reinterpret_cast<const double2*>(q);
+  int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  for (; t + stride < np; t += 2 * stride) {
+    const int64_t u = t + stride;
+    const double2 za = z2[t], pa = p2[t], ra = r2[t], qa = q2[t];
+    const double2 zb = z2[u], pb = p2[u], rb = r2[u], qb = q2[u];
+    z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
+    z2[u] = make_double2(zb.x + alpha * pb.x, zb.y + alpha * pb.y);
+    const double2 na = make_double2(ra.x + alpha * qa.x, ra.y + alpha * qa.y);
+    const double2 nb = make_double2(rb.x + alpha * qb.x, rb.y + alpha * qb.y);
+    r2[t] = na;
+    r2[u] = nb;
+    if (rT) {
+      store_pair<T>(rT + 2 * t, na.x, na.y);
+      store_pair<T>(rT + 2 * u, nb.x, nb.y);
+    }
+    s0 += na.x * na.x + na.y * na.y;
+    s1 += nb.x * nb.x + nb.y * nb.y;
   }
-  const double v[1] = {s};
+  if (t < np) {
+    const double2 za = z2[t], pa = p2[t], ra = r2[t], qa = q2[t];
+    z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
+    const double2 na = make_double2(ra.x + alpha * qa.x, ra.y + alpha * qa.y);
+    r2[t] = na;
+    if (rT) store_pair<T>(rT + 2 * t, na.x, na.y);
+    s0 += na.x * na.x + na.y * na.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t e = n - 1;
+    z[e] += alpha * p[e];
+    const double rn = r[e] + alpha * q[e];
+    r[e] = rn;
+    if (rT) rT[e] = T(rn);
+    s0 += rn * rn;
+  }
+  const double v[1] = {s0 + s1};
   block_partials<1>(v, red);
 }
 
