@@ -1118,9 +1118,6 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
   // or feeds a select and all of them are in flight together.  (p_old is finite
   // on the first iteration too: both direction buffers start zeroed.)
   const double bf = first ? 0.0 : beta;
-  constexpr bool FINE_K = std::is_same<Op, OpFineK<2, double>>::value;
-  double xe[NJ + 1][2];                    // densities, loaded first (finest-level K)
-  if constexpr (FINE_K) TileApply<double, Op, true, NJ>::template load_x<true>(op, d, i, j0, xe);
   TY yc[NJ][2];
   double w[NJ + 2][3][2], acc[NJ][2], dg[NJ][2];
 #pragma unroll
@@ -1141,12 +1138,8 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
         yc[rr - 1][1] = yy[1];
       }
     }
-  if constexpr (FINE_K) {
-    TileApply<double, Op, true, NJ>::run_x(xe, w, acc, dg);
-  } else {
-    if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
-    else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
-  }
+  if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
+  else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
 #pragma unroll
   for (int n = 0; n < NJ; ++n) {
     const int j = j0 + n;
