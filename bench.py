@@ -40,7 +40,7 @@ KERNEL_NAMES = {
     "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
     "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
                 "restriction in one LDS-tiled pass",
-    "sub_up": "k_up2d_staged<true>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
+    "sub_up": "k_up2d_staged<true, 16, 8, 256>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
               "pass, element matrices formed from the densities in LDS",
     "fine_down": "k_down2d_fine<float>: finest level, two Jacobi sweeps, residual and restriction in one "
                  "LDS-tiled pass",
