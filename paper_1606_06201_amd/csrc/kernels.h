@@ -14,8 +14,30 @@ static __constant__ double cK0d[576];
 static __constant__ float cK0f[576];
 // Galerkin images G_q = W_q' K0 W_q of the unit element on the next coarser grid,
 // one 8x8 matrix per sub-element q of a coarse 2D element (row-major, q-major).
-static __constant__ double cG2d[256];
-static __constant__ float cG2f[256];
+// With the square-element symmetry of K0 every entry is a signed copy of one of 18
+// values: G[t] = sign * g[k] with kSqG2d[t] = sign * (k + 1).  The kernels keep the
+// 18 values in scalar registers instead of loading 256 constants; the table follows
+// from the structure of W_q and kSq2d and is checked against the computed images at
+// set-up.
+static __constant__ double cG18d[18];
+static __constant__ float cG18f[18];
+constexpr signed char kSqG2d[256] = {
+      1,   2,   3,   4,   5,   6,   7,   8,   2,   1,   8,   7,   6,   5,   4,   3,
+      3,   8,   9,   6,  10,  11,   5,  12,   4,   7,   6,  13,  14,  15,  16,   5,
+      5,   6,  10,  14,  17,  18,  15,  11,   6,   5,  11,  15,  18,  17,  14,  10,
+      7,   4,   5,  16,  15,  14,  13,   6,   8,   3,  12,   5,  11,  10,   6,   9,
+      9,  -6,   3,  -8,   5, -12,  10, -11,  -6,  13,  -4,   7, -16,   5, -14,  15,
+      3,  -4,   1,  -2,   7,  -8,   5,  -6,  -8,   7,  -2,   1,  -4,   3,  -6,   5,
+      5, -16,   7,  -4,  13,  -6,  15, -14, -12,   5,  -8,   3,  -6,   9, -11,  10,
+     10, -14,   5,  -6,  15, -11,  17, -18, -11,  15,  -6,   5, -14,  10, -18,  17,
+     13,  -6,  15, -14,   5, -16,   7,  -4,  -6,   9, -11,  10, -12,   5,  -8,   3,
+     15, -11,  17, -18,  10, -14,   5,  -6, -14,  10, -18,  17, -11,  15,  -6,   5,
+      5, -12,  10, -11,   9,  -6,   3,  -8, -16,   5, -14,  15,  -6,  13,  -4,   7,
+      7,  -8,   5,  -6,   3,  -4,   1,  -2,  -4,   3,  -6,   5,  -8,   7,  -2,   1,
+     17,  18,  15,  11,   5,   6,  10,  14,  18,  17,  14,  10,   6,   5,  11,  15,
+     15,  14,  13,   6,   7,   4,   5,  16,  11,  10,   6,   9,   8,   3,  12,   5,
+      5,   6,   7,   8,   1,   2,   3,   4,   6,   5,   4,   3,   2,   1,   8,   7,
+     10,  11,   5,  12,   3,   8,   9,   6,  14,  15,  16,   5,   4,   7,   6,  13};
 
 template <typename T> __device__ inline T k0(int idx);
 template <> __device__ inline double k0<double>(int idx) { return cK0d[idx]; }
@@ -46,8 +68,14 @@ __device__ inline T k0rc(int r, int c) {
   else return k0<T>(r * Geo<DIM>::ND + c);
 }
 
-template <> __device__ inline double g2<double>(int idx) { return cG2d[idx]; }
-template <> __device__ inline float g2<float>(int idx) { return cG2f[idx]; }
+template <> __device__ inline double g2<double>(int idx) {
+  const int t = kSqG2d[idx];
+  return t > 0 ? cG18d[t - 1] : -cG18d[-t - 1];
+}
+template <> __device__ inline float g2<float>(int idx) {
+  const int t = kSqG2d[idx];
+  return t > 0 ? cG18f[t - 1] : -cG18f[-t - 1];
+}
 
 // ------------------------------------------------------------------ reductions --
 __device__ inline double wave_sum(double v) {
@@ -281,14 +309,13 @@ struct OpCoarse2K {
     xq[2] = x[b + fnx];
     xq[3] = x[b + fnx + 1];
   }
-  // The four densities are loaded before the sub-element loop, which stays rolled
-  // so that only the 16 constants of one G_q row block are live in scalar
-  // registers at a time.
+  // The four densities are loaded before the sub-element loop; the G_q entries are
+  // signed copies of the 18 values held in scalar registers (kSqG2d).
   __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
     T xv[4];
     xs(ei, ej, xv);
     T s0 = 0, s1 = 0;
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T xq = q == 0 ? xv[0] : q == 1 ? xv[1] : q == 2 ? xv[2] : xv[3];
       const int r0 = q * 64 + (a * 2) * 8;
@@ -313,7 +340,7 @@ struct OpCoarse2K {
   // all elements around a node first, so their loads are in flight together).
   __device__ inline void rows_x(const T* xv, int a, const T* ve, T* acc) const {
     T s0 = 0, s1 = 0;
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T xq = q == 0 ? xv[0] : q == 1 ? xv[1] : q == 2 ? xv[2] : xv[3];
       const int r0 = q * 64 + (a * 2) * 8;
@@ -861,8 +888,8 @@ struct TileApply<T, OpFineK<2, T>, ROWS, NJ> {
 
 // First coarse level formed on the fly: the element matrix of a coarse element is
 // sum_q x_q G_q over its four fine sub-elements q.  The densities of every element
-// the thread touches are loaded up front; the loop over q is the outer one, so one
-// G_q block (64 constants) is live at a time and no load waits inside it.
+// the thread touches are loaded up front; the G_q entries are signed copies of 18
+// values held in scalar registers (kSqG2d), so no load waits inside the loops.
 template <typename T, bool ROWS, int NJ>
 struct TileApply<T, OpCoarse2K<2, T>, ROWS, NJ> {
   template <bool EDGE>
@@ -878,7 +905,7 @@ struct TileApply<T, OpCoarse2K<2, T>, ROWS, NJ> {
       }
 #pragma unroll
     for (int n = 0; n < NJ; ++n) acc[n][0] = acc[n][1] = dg[n][0] = dg[n][1] = T(0);
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
       T xq[NJ + 1][2];
 #pragma unroll

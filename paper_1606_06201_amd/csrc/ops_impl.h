@@ -338,13 +338,25 @@ struct OpsImpl : Ops {
       IPMG_HIP(hipMemcpy(dK, K0, sizeof(double) * 64, hipMemcpyHostToDevice));
       k_galerkin_images2d<<<4, 64>>>(dK, dG);
       double G[256];
-      float Gf[256];
       IPMG_HIP(hipMemcpy(G, dG, sizeof(double) * 256, hipMemcpyDeviceToHost));
       (void)hipFree(dK);
       (void)hipFree(dG);
-      for (int t = 0; t < 256; ++t) Gf[t] = (float)G[t];
-      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG2d), G, sizeof(double) * 256));
-      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG2f), Gf, sizeof(float) * 256));
+      // the 18 distinct values, and every entry checked against its signed copy
+      double g18[18] = {0.0};
+      bool have[18] = {false};
+      double gmax = 0.0;
+      for (int t = 0; t < 256; ++t) gmax = std::max(gmax, std::fabs(G[t]));
+      for (int t = 0; t < 256; ++t) {
+        const int e = kSqG2d[t], k = (e > 0 ? e : -e) - 1;
+        if (!have[k]) { g18[k] = e > 0 ? G[t] : -G[t]; have[k] = true; }
+        const double want = e > 0 ? g18[k] : -g18[k];
+        IPMG_REQUIRE(std::fabs(G[t] - want) <= 1e-12 * gmax, IPMG_E_INVALID,
+                     "Galerkin images lack the square-element symmetry");
+      }
+      float g18f[18];
+      for (int k = 0; k < 18; ++k) g18f[k] = (float)g18[k];
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG18d), g18, sizeof(double) * 18));
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG18f), g18f, sizeof(float) * 18));
     }
   }
 
