@@ -120,6 +120,16 @@ struct Ctx {
   Red red{};
   double* hscal = nullptr;     // pinned host mirror of scal
   int* hflags = nullptr;       // pinned host mirror of flags
+  // Within a PCG iteration: the pinned host slot that the iteration's last kernel
+  // (the finalize of the fused PCG ratio) fills with the flags, and whether one did.
+  int* flag_dst = nullptr;
+  bool flag_written = false;
+  int* take_flag_dst() {
+    int* p = flag_dst;
+    if (p) flag_written = true;
+    flag_dst = nullptr;
+    return p;
+  }
 
   // interior-point scratch (FP64, m or n_slots + 1)
   double *ipG3 = nullptr, *ipW = nullptr, *ipSW = nullptr, *ipDx = nullptr, *ipDphi = nullptr, *ipDpsi = nullptr;

@@ -635,9 +635,11 @@ __device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j
 
 // 3D row sums and diagonal of node (i, j, k): the loop over the 8 elements stays
 // rolled and each element's 24 nodal values are gathered from v (L1/L2) when it is
-// processed, so the 81 neighbourhood values are never live in registers at once
-// (they were: over 256 VGPRs, one wave per SIMD).  Elements outside the grid
-// contribute nothing; clamped nodes (i == 0) read as zero.
+// processed, so the 81 neighbourhood values are never live in registers
+// at once (they were: over 256 VGPRs, one wave per SIMD).  Elements outside the
+// grid contribute nothing; clamped nodes (i == 0), and every node of an element
+// outside the grid, are read at node 0, which is clamped and holds zero in every
+// level vector, so the loads carry no branch.
 template <typename T, class Op, bool ROWS, bool DIAG>
 __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
                                           T* acc, T* dg) {
@@ -659,7 +661,7 @@ __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, in
         const bool nok = ok && ni >= 1;
         const int64_t qn = nok ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ve[b * 3 + c] = nok ? v[3 * qn + c] : T(0);
+        for (int c = 0; c < 3; ++c) ve[b * 3 + c] = v[3 * qn + c];
       }
       op.rows(e, ei, ej, ek, a, ve, acc);
     }
@@ -772,12 +774,25 @@ __global__ __launch_bounds__(BS) void k_level(Op op, Dims d, const T* __restrict
 
 // Finalize of a level pass that reduces (augmented border, M_POWER, M_RAYLEIGH,
 // M_JACOBI_BETA): one block of BS threads, launched right after k_level.
+// The device flags into pinned host memory (thread 0): the last kernel of a PCG
+// iteration hands the host its stop test this way instead of a separate copy.
+__device__ inline void flags_to_host(const Red& red, int* __restrict__ h) {
+#pragma unroll
+  for (int f = 0; f < F_COUNT; ++f) h[f] = red.flags[f];
+  __threadfence_system();
+}
+
+// hflags (M_JACOBI_BETA, may be null): pinned host slot that receives the flags.
 template <typename T, int MODE>
 __global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const T* __restrict__ r,
                                                   T* __restrict__ out, const double* __restrict__ omg, int aug,
                                                   double c, int64_t n, const double* __restrict__ dot64, Red red,
-                                                  unsigned nblocks, int sidx, int sidx_in, const int* gate) {
-  if (gate && *gate) return;
+                                                  unsigned nblocks, int sidx, int sidx_in, const int* gate,
+                                                  int* hflags) {
+  if (gate && *gate) {
+    if (hflags && threadIdx.x == 0) flags_to_host(red, hflags);
+    return;
+  }
   double tot[3];
   sum_partials<3>(red, nblocks, tot);
   if (threadIdx.x != 0) return;
@@ -798,6 +813,7 @@ __global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const
       if constexpr (MODE == M_RAYLEIGH) red.scal[sidx + 1] = tot[1];
     }
   }
+  if (hflags) flags_to_host(red, hflags);
 }
 
 // Row sums (A v) and diagonals of the NJ nodes (i, j0..j0+NJ-1) of one thread of

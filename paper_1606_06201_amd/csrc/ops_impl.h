@@ -375,7 +375,8 @@ struct OpsImpl : Ops {
     }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
-                                                 sidx, sidx_in, gate);                                      \
+                                                 sidx, sidx_in, gate,                                       \
+                                                 M == M_JACOBI_BETA ? c.take_flag_dst() : nullptr);         \
     return;
     switch (mode) {
       IPMG_L2D_CASE(M_APPLY)
@@ -415,7 +416,8 @@ struct OpsImpl : Ops {
     }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb, \
-                                                 sidx, sidx_in, gate);                                      \
+                                                 sidx, sidx_in, gate,                                       \
+                                                 M == M_JACOBI_BETA ? c.take_flag_dst() : nullptr);         \
     break;
     switch (mode) {
       IPMG_LEVEL_CASE(M_APPLY)
@@ -641,7 +643,7 @@ struct OpsImpl : Ops {
       if (beta64)
         k_level_fin<T, M_JACOBI_BETA><<<1, BS, 0, c.stream>>>((const T*)out, (const T*)c.lev[lev].r, (T*)out,
                                                               c.omega_dev + lev, 0, 0.0, d.nslots, beta64, c.red,
-                                                              g.x * g.y, 0, -1, gate);
+                                                              g.x * g.y, 0, -1, gate, c.take_flag_dst());
       return;
     }
     const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);

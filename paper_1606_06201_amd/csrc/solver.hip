@@ -149,7 +149,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   IPMG_HIP(hipMemsetAsync(c.red.flags, 0, sizeof(int) * F_COUNT, st));
   if (hipHostMalloc((void**)&c.hscal, sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess)
     throw Error(IPMG_E_NOMEM, "pinned allocation failed");
-  if (hipHostMalloc((void**)&c.hflags, sizeof(int) * F_COUNT * 4, hipHostMallocDefault) != hipSuccess)
+  // coherent: kernels write PCG flags into it directly
+  if (hipHostMalloc((void**)&c.hflags, sizeof(int) * F_COUNT * 4, hipHostMallocCoherent) != hipSuccess)
     throw Error(IPMG_E_NOMEM, "pinned allocation failed");
   IPMG_HIP(hipEventCreate(&c.ev0));
   IPMG_HIP(hipEventCreate(&c.ev1));
@@ -472,9 +473,13 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
     int slot = 0;
     enq = 0;
     while (iters_before + enq < maxit) {
+      c.flag_dst = c.hflags + F_COUNT * (1 + slot);   // the last kernel writes the flags there ...
+      c.flag_written = false;
       pcg_iteration(c, op, n, gate, enq == 0 ? 1 : 0);
-      IPMG_HIP(hipMemcpyAsync(c.hflags + F_COUNT * (1 + slot), c.red.flags, sizeof(int) * F_COUNT,
-                              hipMemcpyDeviceToHost, c.stream));
+      if (!c.flag_written)                               // ... or they are copied
+        IPMG_HIP(hipMemcpyAsync(c.hflags + F_COUNT * (1 + slot), c.red.flags, sizeof(int) * F_COUNT,
+                                hipMemcpyDeviceToHost, c.stream));
+      c.flag_dst = nullptr;
       IPMG_HIP(hipEventRecord(slot ? c.ev1 : c.ev0, c.stream));
       ++enq;
       if (enq >= 2) {
