@@ -4,11 +4,12 @@
 // beside dense_tiles), and the product z = A^-1 r applied once per V-cycle.
 //
 // One sweep over the block columns k does the factorization and the triangular
-// inverse together, three launches per k:
-//   diag:   L_kk = chol(A_kk) and X_kk = L_kk^-1;
+// inverse together, two launches per k:
 //   panel:  L_ik = A_ik X_kk' (i > k), and X_kJ = X_kk B_kJ (J < k);
 //   update: A_IJ -= L_Ik L_Jk' (I >= J > k), and B_IJ -= L_Ik X_kJ (I > k, J <= k),
-// where B accumulates the right-looking block forward substitution L X = I.  The
+// where B accumulates the right-looking block forward substitution L X = I; the
+// block of the update that finishes A_{k+1,k+1} then forms L_{k+1,k+1} =
+// chol(A_{k+1,k+1}) and X_{k+1,k+1} = L^-1 ("diag", a launch of its own for k = 0).  The
 // working matrix W keeps every tile transposed (tile (I, J) holds A_IJ', then
 // L_Ik' in the panel column, and X_kk' on the diagonal once factored), so every
 // 64 x 64 x 64 tile product reads both operands from LDS with the summed index
@@ -156,14 +157,14 @@ __device__ inline void diag_steps(double (&row)[DW], double (&y)[DW], double (*L
   }
 }
 
-__global__ __launch_bounds__(DTT) void k_dense_diag(double* __restrict__ W, double* __restrict__ X, int k,
-                                                    Red red) {
-  __shared__ double Lc[DT][DT + 2];   // the tile, then row j = column j of L
-  __shared__ double Xc[DT][DT + 2];   // row j: x_j of every column of X
+typedef double DiagRows[DT + 2];
+constexpr int DIAG_LDS = 2 * DT * (DT + 2);   // doubles: the tile / L by columns, and x_j rows
+
+// Factor the symmetric tile A_kk held in Lc (row-major), writing X_kk to X and
+// its transpose to W's diagonal tile.
+__device__ inline void diag_factor(DiagRows* Lc, DiagRows* Xc, double* __restrict__ W, double* __restrict__ X,
+                                   int k, const Red& red) {
   const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double* a = W + dense_tile_off(k, k);
-  for (int t = threadIdx.x; t < DT * DT; t += DTT) Lc[t / DT][t % DT] = a[t];
-  __syncthreads();
   double row[DW], y[DW];
 #pragma unroll
   for (int c = 0; c < DW; ++c) {
@@ -186,6 +187,17 @@ __global__ __launch_bounds__(DTT) void k_dense_diag(double* __restrict__ W, doub
   }
 }
 
+__global__ __launch_bounds__(DTT) void k_dense_diag(double* __restrict__ W, double* __restrict__ X, int k,
+                                                    Red red) {
+  __shared__ double smem[DIAG_LDS];
+  DiagRows* Lc = reinterpret_cast<DiagRows*>(smem);
+  DiagRows* Xc = reinterpret_cast<DiagRows*>(smem + DT * (DT + 2));
+  const double* a = W + dense_tile_off(k, k);
+  for (int t = threadIdx.x; t < DT * DT; t += DTT) Lc[t / DT][t % DT] = a[t];
+  __syncthreads();
+  diag_factor(Lc, Xc, W, X, k, red);
+}
+
 // Panel of block column k: blocks b < nt-k-1 form L_ik' = X_kk A_ik' for
 // i = k+1+b (in place in W); the next k blocks form X_kJ = X_kk B_kJ (in place in X).
 __global__ __launch_bounds__(DTT) void k_dense_panel(double* __restrict__ W, double* __restrict__ X, int k, int nt) {
@@ -204,8 +216,10 @@ __global__ __launch_bounds__(DTT) void k_dense_panel(double* __restrict__ W, dou
 // Trailing update after block column k: A_IJ' -= L_Jk L_Ik' for I >= J > k (first
 // (nt-k-1)(nt-k)/2 blocks), then B_IJ -= L_Ik X_kJ for I > k, J <= k.
 __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, double* __restrict__ X, int k,
-                                                      int nt) {
-  __shared__ Tile SA, SB;
+                                                      int nt, Red red) {
+  __shared__ double smem[DIAG_LDS];
+  Tile& SA = *reinterpret_cast<Tile*>(smem);
+  Tile& SB = *reinterpret_cast<Tile*>(smem + DT * DT);
   const int m = nt - k - 1, nchol = m * (m + 1) / 2;
   const int b = blockIdx.x;
   const double *ga, *gb;
@@ -233,6 +247,19 @@ __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, do
   acc_zero(acc);
   tile_mac(SA, SB, acc);
   acc_store<true>(g, acc, old);
+  if (b != 0 || nchol == 0) return;
+  // Block 0 updated tile (k+1, k+1) for the last time: factor it here, from the
+  // values in registers, instead of in a launch of its own.
+  __syncthreads();                                  // SA, SB no longer read
+  DiagRows* Lc = reinterpret_cast<DiagRows*>(smem);
+  DiagRows* Xc = reinterpret_cast<DiagRows*>(smem + DT * (DT + 2));
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Lc[4 * ty + i][4 * tx + j] = old[i][j] - acc[i][j];
+  __syncthreads();
+  diag_factor(Lc, Xc, W, X, k + 1, red);
 }
 
 // A^-1 = X' X: tile (I, J), I >= J, is sum_{K >= I} X_KI' X_KJ.  Blocks run in
@@ -356,12 +383,12 @@ void dense_init(hipStream_t st, double* A, int n, int pad) {
 void dense_factor_inverse(hipStream_t st, double* W, double* X, double* Ai, int n, const Red& red) {
   const int nt = dense_tiles(n);
   k_dense_init<<<nt * (nt + 1) / 2, DTT, 0, st>>>(X, n, 0);
-  for (int k = 0; k < nt; ++k) {
+  k_dense_diag<<<1, DTT, 0, st>>>(W, X, 0, red);
+  for (int k = 0; k < nt; ++k) {                  // the update of step k factors diagonal tile k+1
     const int m = nt - k - 1;
-    k_dense_diag<<<1, DTT, 0, st>>>(W, X, k, red);
     if (nt > 1) k_dense_panel<<<nt - 1, DTT, 0, st>>>(W, X, k, nt);
     const int nu = m * (m + 1) / 2 + m * (k + 1);
-    if (nu > 0) k_dense_update<<<nu, DTT, 0, st>>>(W, X, k, nt);
+    if (nu > 0) k_dense_update<<<nu, DTT, 0, st>>>(W, X, k, nt, red);
   }
   k_dense_product<<<nt * (nt + 1) / 2, DTT, 0, st>>>(X, Ai, nt);
 }
