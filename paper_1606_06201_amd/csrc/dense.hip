@@ -158,11 +158,11 @@ __device__ inline void diag_steps(double (&row)[DW], double (&y)[DW], double (*L
 }
 
 typedef double DiagRows[DT + 2];
-constexpr int DIAG_LDS = 2 * DT * (DT + 2);   // doubles: the tile / L by columns, and x_j rows
+constexpr int DIAG_ROWS = DT * (DT + 2);   // doubles of each of the two LDS arrays of the factor
 
 // Factor the symmetric tile A_kk held in Lc (row-major), writing X_kk to X and
 // its transpose to W's diagonal tile.
-__device__ inline void diag_factor(DiagRows* Lc, DiagRows* Xc, double* __restrict__ W, double* __restrict__ X,
+__device__ __attribute__((always_inline)) inline void diag_factor(DiagRows* Lc, DiagRows* Xc, double* __restrict__ W, double* __restrict__ X,
                                    int k, const Red& red) {
   const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
   double row[DW], y[DW];
@@ -189,9 +189,9 @@ __device__ inline void diag_factor(DiagRows* Lc, DiagRows* Xc, double* __restric
 
 __global__ __launch_bounds__(DTT) void k_dense_diag(double* __restrict__ W, double* __restrict__ X, int k,
                                                     Red red) {
-  __shared__ double smem[DIAG_LDS];
-  DiagRows* Lc = reinterpret_cast<DiagRows*>(smem);
-  DiagRows* Xc = reinterpret_cast<DiagRows*>(smem + DT * (DT + 2));
+  __shared__ double smemA[DIAG_ROWS], smemB[DIAG_ROWS];   // separate arrays: the compiler sees no alias
+  DiagRows* Lc = reinterpret_cast<DiagRows*>(smemA);
+  DiagRows* Xc = reinterpret_cast<DiagRows*>(smemB);
   const double* a = W + dense_tile_off(k, k);
   for (int t = threadIdx.x; t < DT * DT; t += DTT) Lc[t / DT][t % DT] = a[t];
   __syncthreads();
@@ -217,9 +217,9 @@ __global__ __launch_bounds__(DTT) void k_dense_panel(double* __restrict__ W, dou
 // (nt-k-1)(nt-k)/2 blocks), then B_IJ -= L_Ik X_kJ for I > k, J <= k.
 __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, double* __restrict__ X, int k,
                                                       int nt, Red red) {
-  __shared__ double smem[DIAG_LDS];
-  Tile& SA = *reinterpret_cast<Tile*>(smem);
-  Tile& SB = *reinterpret_cast<Tile*>(smem + DT * DT);
+  __shared__ double smemA[DIAG_ROWS], smemB[DIAG_ROWS];
+  Tile& SA = *reinterpret_cast<Tile*>(smemA);
+  Tile& SB = *reinterpret_cast<Tile*>(smemB);
   const int m = nt - k - 1, nchol = m * (m + 1) / 2;
   const int b = blockIdx.x;
   const double *ga, *gb;
@@ -251,8 +251,8 @@ __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, do
   // Block 0 updated tile (k+1, k+1) for the last time: factor it here, from the
   // values in registers, instead of in a launch of its own.
   __syncthreads();                                  // SA, SB no longer read
-  DiagRows* Lc = reinterpret_cast<DiagRows*>(smem);
-  DiagRows* Xc = reinterpret_cast<DiagRows*>(smem + DT * (DT + 2));
+  DiagRows* Lc = reinterpret_cast<DiagRows*>(smemA);
+  DiagRows* Xc = reinterpret_cast<DiagRows*>(smemB);
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
