@@ -32,6 +32,8 @@ KERNEL_SOURCES = ["paper_1606_06201_amd/csrc/kernels.h", "paper_1606_06201_amd/c
 KERNEL_NAMES = {
     "fine_jacobi": "k_level2d<float, OpFineK<2,float>, M_JACOBI, 4>: finest-level damped-Jacobi sweep",
     "fine_jacobi0": "k_level2d<float, OpFineK<2,float>, M_JACOBI0, 4>: first sweep from a zero iterate",
+    "fine_pjacobi": "k_level2d<float, OpFineK<2,float>, M_PJACOBI, 4>: first post-sweep from z2 + P zc "
+                    "(prolongation folded in)",
     "fine_jacobi_beta": "k_level2d<float, OpFineK<2,float>, M_JACOBI_BETA, 4>: last sweep + fused PCG ratio",
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
@@ -61,6 +63,8 @@ def class_bytes(nel, fp32, kind):
         return 3 * 2 * w * N + w * m
     if kind == "fine_jacobi0":                  # read r; write z; read x
         return 2 * 2 * w * N + w * m
+    if kind == "fine_pjacobi":                  # read z2, r, coarse correction; write z; read x
+        return 3 * 2 * w * N + w * m + 2 * w * Nc
     if kind == "fine_jacobi_beta":              # fine_jacobi + read FP64 r for the ratio
         return 3 * 2 * w * N + w * m + 2 * 8 * N
     if kind == "sub_jacobi":                    # read z, r; write z'; read the fine x (4 per coarse element)

@@ -218,6 +218,7 @@ int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg
  *   8: fused prolongation and post-smoothing on the first coarse level
  *   9: fused pre-smoothing, residual and restriction on the finest level
  *  10: fused prolongation and post-smoothing on the finest level (with the PCG ratio)
+ *  11: prolongation folded into the first post-smoothing sweep on the finest level
  * Launches skipped on device after convergence are recorded too (with near-zero
  * duration).  max_launches: event pairs to keep (further launches are not timed).
  * durations_ms: [host] capacity entries, each launch's duration; classes: [host,

@@ -497,7 +497,8 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 
 // ------------------------------------------------------------ level kernels --
 enum LevelMode {
-  M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5, M_JACOBI_BETA = 6
+  M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5, M_JACOBI_BETA = 6,
+  M_PJACOBI = 7   // 2D tiled passes only: Jacobi sweep from z2 + P zc (prolongation folded in)
 };
 
 // Post-processing of the PCG ratio by the thread that owns the final sum
@@ -529,7 +530,7 @@ __device__ inline double recip(double v) { return 1.0 / v; }
 // reduction terms in red0/red1.
 template <int MODE>
 constexpr bool mode_reads_r() {
-  return MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA;
+  return MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA || MODE == M_PJACOBI;
 }
 
 // As level_node_finish with the node's entries of r (rr), of dot64 (d64, M_JACOBI_BETA)
@@ -553,7 +554,8 @@ __device__ inline void level_node_finish_vals(int64_t q, T* acc, const T* dg, co
   for (int c = 0; c < DIM; ++c) {
     if constexpr (MODE == M_APPLY) o[c] = acc[c];
     if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
-    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA) o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
+    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA || MODE == M_PJACOBI)
+      o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
     if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
     if constexpr (MODE == M_POWER) {
       o[c] = T(pin * (double)(acc[c] / dg[c]));
@@ -982,17 +984,77 @@ __device__ inline void load_tile(const T* __restrict__ v, const Dims& d, int i, 
     }
 }
 
+// As load_tile, of z2 + P zc: the fine values z2 plus the bilinear prolongation of
+// the coarse correction zc (Sec. 5.1 solution update, summed in the order of
+// k_prolong), zero outside the grid and on clamped nodes.  NJ is even, so j0 is
+// even and the coarse rows of every fine row are fixed; the thread loads the
+// (NJ/2+2) x 3 coarse nodes from row j0/2-1 and column (i-1)>>1 once, and the
+// parity of i picks, per fine column, which of them a node interpolates from.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void load_tile_prolong(const T* __restrict__ z2, const T* __restrict__ zc, const Dims& d,
+                                         const Dims& dc, int i, int j0, T (&w)[NJ + 2][3][2]) {
+  static_assert(NJ % 2 == 0, "the folded prolongation needs an even node count per thread");
+  constexpr int CR = NJ / 2 + 2;
+  const int c0 = (i - 1) >> 1, jb = (j0 >> 1) - 1;
+  T cv[CR][3][2];
+#pragma unroll
+  for (int cr = 0; cr < CR; ++cr)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int J = min(max(jb + cr, 0), dc.ny1 - 1), I = min(max(c0 + t, 0), dc.nx1 - 1);
+      load_node<2, T>(zc, (int64_t)J * dc.nx1 + I, cv[cr][t]);
+    }
+  const bool ieven = ((i - 1) & 1) != 0;
+  // per fine column cc: first and second coarse column (relative to c0) and count,
+  // for odd i and for even i
+  constexpr int I0o[3] = {0, 0, 1}, I1o[3] = {0, 1, 1}, Nio[3] = {1, 2, 1};
+  constexpr int I0e[3] = {0, 1, 1}, I1e[3] = {1, 1, 2}, Nie[3] = {2, 1, 2};
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr) {
+    const int jj = j0 - 1 + rr;
+    const int nj = (rr & 1) == 0 ? 2 : 1;             // fine row j0-1+rr is odd when rr is even
+    const int J0 = (rr + 1) >> 1;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int ii = i - 1 + cc;
+      const bool ok = !EDGE || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1);
+      const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 + (unsigned)(ok ? ii : 0));
+      T acc[2] = {z2[o], z2[o + 1]};
+      const int ni = ieven ? Nie[cc] : Nio[cc];
+      const T wgt = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const bool use = e < ni && b < nj;
+          const int Jr = J0 + (b < nj ? b : 0);
+          const int Io = e == 0 ? I0o[cc] : I1o[cc], Ie = e == 0 ? I0e[cc] : I1e[cc];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const T vv = ieven ? cv[Jr][Ie][c] : cv[Jr][Io][c];
+            acc[c] += use ? wgt * vv : T(0);
+          }
+        }
+      w[rr][cc][0] = ok ? acc[0] : T(0);
+      w[rr][cc][1] = ok ? acc[1] : T(0);
+    }
+  }
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
 // along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
 // whose nodes are all at least one node away from every boundary (and off the
 // clamped column) skip every bounds check; the others run the same code with
 // masked loads, so that no block waits on a chain of per-node loads.
 // Modes as in k_level except M_POWER and M_RAYLEIGH.
+// M_PJACOBI: v is z2 on this level and zc the coarse correction on level dc; the
+// sweep starts from z2 + P zc (the prolongation of the V-cycle's up path folded in).
 template <typename T, class Op, int MODE, int NJ>
 __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restrict__ v,
                                                 const T* __restrict__ r, T* __restrict__ out,
                                                 const double* __restrict__ omg, Aug<T> aug, Red red,
-                                                const double* __restrict__ dot64, const int* gate) {
+                                                const double* __restrict__ dot64, const int* gate,
+                                                const T* __restrict__ zc, Dims dc) {
   if (gate && *gate) return;
   const T omega = omg ? T(*omg) : T(0);
   const Tile tl = xcd_tile();
@@ -1024,10 +1086,12 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   T w[NJ + 2][3][2];
   T acc[NJ][2], dg[NJ][2];
   if (interior) {
-    if constexpr (ROWS) load_tile<T, NJ, false>(v, d, i, j0, w);
+    if constexpr (MODE == M_PJACOBI) load_tile_prolong<T, NJ, false>(v, zc, d, dc, i, j0, w);
+    else if constexpr (ROWS) load_tile<T, NJ, false>(v, d, i, j0, w);
     TileApply<T, Op, ROWS, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
   } else {
-    if constexpr (ROWS) load_tile<T, NJ, true>(v, d, i, j0, w);
+    if constexpr (MODE == M_PJACOBI) load_tile_prolong<T, NJ, true>(v, zc, d, dc, i, j0, w);
+    else if constexpr (ROWS) load_tile<T, NJ, true>(v, d, i, j0, w);
     TileApply<T, Op, ROWS, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
   }
 #pragma unroll

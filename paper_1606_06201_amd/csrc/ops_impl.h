@@ -363,7 +363,9 @@ struct OpsImpl : Ops {
   // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes.
   template <typename T, class Op, int NJ>
   void launch_l2d(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out, const double* omg,
-                  Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64, bool fin) {
+                  Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64, bool fin,
+                  const T* zc = nullptr, const Dims* dcp = nullptr) {
+    const Dims dc = dcp ? *dcp : d;
     const dim3 g2((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
     const unsigned nb2 = g2.x * g2.y;
     IPMG_REQUIRE((int64_t)nb2 <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
@@ -371,7 +373,7 @@ struct OpsImpl : Ops {
   case M:                                                                                                    \
     {                                                                                                        \
       ProfScope ps_(c, c.prof_tag);                                                                          \
-      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate);      \
+      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc, dc); \
     }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
@@ -387,6 +389,59 @@ struct OpsImpl : Ops {
       default: break;
     }
 #undef IPMG_L2D_CASE
+    if constexpr (NJ % 2 == 0) {
+      if (mode == M_PJACOBI) {
+        ProfScope ps_(c, c.prof_tag);
+        k_level2d<T, Op, M_PJACOBI, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
+                                                                 dc);
+      }
+    }
+  }
+
+  // z2 + P zc, then one Jacobi sweep, in one tiled pass (2D, operator K, even
+  // register-block width); false when it does not apply (the caller prolongs and
+  // sweeps separately).
+  template <typename T, class Op>
+  bool pjacobi_t(Ctx& c, const Dims& d, const Dims& dc, const Op& op, const T* z2, const T* zc, const T* r, T* out,
+                 const double* omg, const int* gate) {
+    const int nj = sizeof(T) == 4 ? c.nj32 : c.nj64;
+    if (!c.tiled2d || d.nnodes < c.tiled_min_nodes || nj % 2 != 0) return false;
+    const Aug<T> aug{nullptr, 0.0, d.nslots};
+    if (nj == 2) launch_l2d<T, Op, 2>(c, d, op, M_PJACOBI, z2, r, out, omg, aug, 0, -1, gate, nullptr, false, zc, &dc);
+    else if (nj == 8) launch_l2d<T, Op, 8>(c, d, op, M_PJACOBI, z2, r, out, omg, aug, 0, -1, gate, nullptr, false, zc, &dc);
+    else launch_l2d<T, Op, 4>(c, d, op, M_PJACOBI, z2, r, out, omg, aug, 0, -1, gate, nullptr, false, zc, &dc);
+    return true;
+  }
+  bool prolong_jacobi(Ctx& c, int lev, int op, const void* z2, const void* zc, const void* r, void* out,
+                      const double* omg, const int* gate) override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      if (op != IPMG_OP_K || !c.fold_prolong) return false;
+      const Dims& d = c.lev[lev].d;
+      const Dims& dc = c.lev[lev - 1].d;
+      if (c.fp32) {
+        using T = float;
+        if (lev == c.L - 1)
+          return pjacobi_t<T>(c, d, dc, OpFineK<2, T>{(const T*)c.xT, d.m}, (const T*)z2, (const T*)zc, (const T*)r,
+                              (T*)out, omg, gate);
+        if (lev == c.L - 2 && c.coarse_from_x)
+          return pjacobi_t<T>(c, d, dc, OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, (const T*)z2,
+                              (const T*)zc, (const T*)r, (T*)out, omg, gate);
+        return pjacobi_t<T>(c, d, dc, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, (const T*)z2, (const T*)zc,
+                            (const T*)r, (T*)out, omg, gate);
+      } else {
+        using T = double;
+        if (lev == c.L - 1)
+          return pjacobi_t<T>(c, d, dc, OpFineK<2, T>{(const T*)c.xT, d.m}, (const T*)z2, (const T*)zc, (const T*)r,
+                              (T*)out, omg, gate);
+        if (lev == c.L - 2 && c.coarse_from_x)
+          return pjacobi_t<T>(c, d, dc, OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, (const T*)z2,
+                              (const T*)zc, (const T*)r, (T*)out, omg, gate);
+        return pjacobi_t<T>(c, d, dc, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, (const T*)z2, (const T*)zc,
+                            (const T*)r, (T*)out, omg, gate);
+      }
+    }
   }
 
   template <typename T, class Op>

@@ -118,6 +118,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_STAGED_MAX_NODES")) c.staged_max_nodes = std::max<int64_t>(0, std::atoll(e));
   if (const char* e = std::getenv("IPMG_STAGED_DOWN_FROM_X")) c.staged_down_from_x = e[0] == '1';
   if (const char* e = std::getenv("IPMG_STAGED_BIG")) c.staged_big = e[0] == '1';
+  if (const char* e = std::getenv("IPMG_NO_FOLD_PROLONG")) c.fold_prolong = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -363,8 +364,16 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   }
   c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
   void* vc = vcycle_level(c, op, k - 1, gate, nullptr);                       // coarse correction
-  c.ops->prolong_from(c, k, cur, vc, aug, gate);                              // solution update
-  for (int s = 0; s < c.desc.nu_post; ++s) {                                  // post-smoothing
+  int s0 = 0;
+  if (c.desc.nu_post >= 2) {                  // solution update folded into the first post-sweep
+    ProfTag pt(c, fine ? PC_FINE_PJACOBI : jac);
+    if (c.ops->prolong_jacobi(c, k, op, cur, vc, l.r, nxt, w, gate)) {
+      std::swap(cur, nxt);
+      s0 = 1;
+    }
+  }
+  if (s0 == 0) c.ops->prolong_from(c, k, cur, vc, aug, gate);                 // solution update
+  for (int s = s0; s < c.desc.nu_post; ++s) {                                 // post-smoothing
     const bool last = beta64 && s == c.desc.nu_post - 1;
     ProfTag pt(c, last ? (fine ? PC_FINE_JACOBI_BETA : -1) : jac);
     c.ops->level(c, k, op, last ? M_JACOBI_BETA : M_JACOBI, cur, l.r, nxt, w, 0, -1, gate, last ? beta64 : nullptr);
