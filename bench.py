@@ -34,6 +34,8 @@ KERNEL_NAMES = {
     "fine_jacobi0": "k_level2d<float, OpFineK<2,float>, M_JACOBI0, 4>: first sweep from a zero iterate",
     "fine_pjacobi": "k_level2d<float, OpFineK<2,float>, M_PJACOBI, 4>: first post-sweep from z2 + P zc "
                     "(prolongation folded in)",
+    "fine_jacobi2": "k_level2d<float, OpFineK<2,float>, M_JACOBI2, 4>: the first two pre-sweeps from zero in one "
+                    "pass",
     "fine_jacobi_beta": "k_level2d<float, OpFineK<2,float>, M_JACOBI_BETA, 4>: last sweep + fused PCG ratio",
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
@@ -65,6 +67,8 @@ def class_bytes(nel, fp32, kind):
         return 2 * 2 * w * N + w * m
     if kind == "fine_pjacobi":                  # read z2, r, coarse correction; write z; read x
         return 3 * 2 * w * N + w * m + 2 * w * Nc
+    if kind == "fine_jacobi2":                  # read r, x; write z2 (z1 never stored)
+        return 2 * 2 * w * N + w * m
     if kind == "fine_jacobi_beta":              # fine_jacobi + read FP64 r for the ratio
         return 3 * 2 * w * N + w * m + 2 * 8 * N
     if kind == "sub_jacobi":                    # read z, r; write z'; read the fine x (4 per coarse element)

@@ -219,6 +219,7 @@ int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg
  *   9: fused pre-smoothing, residual and restriction on the finest level
  *  10: fused prolongation and post-smoothing on the finest level (with the PCG ratio)
  *  11: prolongation folded into the first post-smoothing sweep on the finest level
+ *  12: the first two pre-smoothing sweeps on the finest level in one pass
  * Launches skipped on device after convergence are recorded too (with near-zero
  * duration).  max_launches: event pairs to keep (further launches are not timed).
  * durations_ms: [host] capacity entries, each launch's duration; classes: [host,

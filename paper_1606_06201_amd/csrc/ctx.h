@@ -40,6 +40,9 @@ struct Ops {
   // sweep); false when that pass does not apply.
   virtual bool prolong_jacobi(Ctx& c, int lev, int op, const void* z2, const void* zc, const void* r, void* out,
                               const double* omg, const int* gate) = 0;
+  // out = the first two damped-Jacobi sweeps from a zero iterate on level lev, in
+  // one pass; false when that pass does not apply.
+  virtual bool jacobi2(Ctx& c, int lev, int op, const void* r, void* out, const double* omg, const int* gate) = 0;
   virtual void restrict64(Ctx& c, int lev_f, const double* rf, double* rc) = 0;    // border vectors
   virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E64 of level lev_f-1
   virtual void dense_assemble(Ctx& c, int op, double* A, int n) = 0;
@@ -90,7 +93,8 @@ struct Ctx {
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
   bool staged_down_from_x = false;   // the first coarse level's down pass staged as well
   bool staged_big = false;           // first coarse level: staged passes on the large tiles
-  bool fold_prolong = true;          // 2D tiled levels: prolongation folded into the first post-sweep
+  bool fold_prolong = true;          // 2D tiled levels: prolongation folded into the first post-sweep, and
+                                     // the finest level's first two pre-sweeps fused
   int power_steps = 12;        // power iterations of the damping estimate (K)
   int power_steps_z = 30;      // ... (augmented system Z)
 
@@ -169,7 +173,8 @@ enum ProfClass {
   PC_FINE_DOWN = 9,         // finest level, fused pre-smoothing + residual + restriction
   PC_FINE_UP = 10,          // finest level, fused prolongation + post-smoothing (+ PCG ratio)
   PC_FINE_PJACOBI = 11,     // finest level, prolongation folded into the first post-smoothing sweep
-  PC_COUNT = 12
+  PC_FINE_JACOBI2 = 12,     // finest level, the first two pre-smoothing sweeps in one pass
+  PC_COUNT = 13
 };
 
 // Sets the class of the level passes enqueued in its scope.

@@ -498,7 +498,8 @@ __device__ inline void node_apply(const Op& op, const Dims& d, int i, int j, int
 // ------------------------------------------------------------ level kernels --
 enum LevelMode {
   M_APPLY = 0, M_RESID = 1, M_JACOBI = 2, M_JACOBI0 = 3, M_POWER = 4, M_RAYLEIGH = 5, M_JACOBI_BETA = 6,
-  M_PJACOBI = 7   // 2D tiled passes only: Jacobi sweep from z2 + P zc (prolongation folded in)
+  M_PJACOBI = 7,  // 2D tiled passes only: Jacobi sweep from z2 + P zc (prolongation folded in)
+  M_JACOBI2 = 8   // 2D tiled finest-level K only: the first two sweeps from a zero iterate in one pass
 };
 
 // Post-processing of the PCG ratio by the thread that owns the final sum
@@ -530,7 +531,8 @@ __device__ inline double recip(double v) { return 1.0 / v; }
 // reduction terms in red0/red1.
 template <int MODE>
 constexpr bool mode_reads_r() {
-  return MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA || MODE == M_PJACOBI;
+  return MODE == M_RESID || MODE == M_JACOBI || MODE == M_JACOBI0 || MODE == M_JACOBI_BETA || MODE == M_PJACOBI ||
+         MODE == M_JACOBI2;
 }
 
 // As level_node_finish with the node's entries of r (rr), of dot64 (d64, M_JACOBI_BETA)
@@ -554,7 +556,7 @@ __device__ inline void level_node_finish_vals(int64_t q, T* acc, const T* dg, co
   for (int c = 0; c < DIM; ++c) {
     if constexpr (MODE == M_APPLY) o[c] = acc[c];
     if constexpr (MODE == M_RESID) o[c] = rr[c] - acc[c];
-    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA || MODE == M_PJACOBI)
+    if constexpr (MODE == M_JACOBI || MODE == M_JACOBI_BETA || MODE == M_PJACOBI || MODE == M_JACOBI2)
       o[c] = vc[c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
     if constexpr (MODE == M_JACOBI0) o[c] = omega * rr[c] * recip(dg[c]);
     if constexpr (MODE == M_POWER) {
@@ -1041,6 +1043,52 @@ __device__ inline void load_tile_prolong(const T* __restrict__ z2, const T* __re
   }
 }
 
+// First two damped-Jacobi sweeps from a zero iterate on the finest level: w gets
+// z1 = omega D^-1 r on the thread's (NJ+2) x 3 neighbourhood (zero outside the grid
+// and on clamped nodes), then acc = A z1 and dg = D on its NJ nodes.  D at each
+// neighbourhood node is summed over its four elements in the order of TileApply.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void jacobi2_tile(const OpFineK<2, T>& op, const Dims& d, int i, int j0, const T* __restrict__ r,
+                                    T omega, T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+  // Element (i-2+ec, j0-2+er), the zero pad outside the grid.  The outer ring can
+  // lie outside the grid even on interior tiles (a node on the last row or column
+  // has no element beyond it), so every index is checked.
+  T xb[NJ + 3][4];
+#pragma unroll
+  for (int er = 0; er < NJ + 3; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 4; ++ec) {
+      const int ei = i - 2 + ec, ej = j0 - 2 + er;
+      xb[er][ec] = op.x[elem_in(d, ei, ej) ? (int64_t)ej * d.nx + ei : op.m];
+    }
+  load_tile<T, NJ, EDGE>(r, d, i, j0, w);   // r on the neighbourhood, then z1 in place
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int ii = i - 1 + cc, jj = j0 - 1 + rr;
+      const bool ok = !EDGE || (ii >= 1 && ii < d.nx1 && jj >= 0 && jj < d.ny1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        T dd = T(0);
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+          for (int ex = 0; ex < 2; ++ex) {
+            const int a = loc_index(1 - ex, 1 - ey, 0);
+            dd += xb[rr + ey][cc + ex] * k0sq<T>(2 * a + c, 2 * a + c);
+          }
+        w[rr][cc][c] = ok ? omega * w[rr][cc][c] * recip(dd) : T(0);
+      }
+    }
+  T xe[NJ + 1][2];
+#pragma unroll
+  for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) xe[er][ec] = xb[er + 1][ec + 1];
+  TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe, w, acc, dg);
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
 // along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
 // whose nodes are all at least one node away from every boundary (and off the
@@ -1049,6 +1097,10 @@ __device__ inline void load_tile_prolong(const T* __restrict__ z2, const T* __re
 // Modes as in k_level except M_POWER and M_RAYLEIGH.
 // M_PJACOBI: v is z2 on this level and zc the coarse correction on level dc; the
 // sweep starts from z2 + P zc (the prolongation of the V-cycle's up path folded in).
+// M_JACOBI2 (finest level, A_e = x_e K0): the first two pre-smoothing sweeps from a
+// zero iterate in one pass; the first sweep's z1 = omega D^-1 r is formed on the
+// thread's neighbourhood from r and the densities of the (NJ+3) x 4 elements around
+// it (same arithmetic and order as the M_JACOBI0 pass), so z1 is never stored.
 template <typename T, class Op, int MODE, int NJ>
 __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restrict__ v,
                                                 const T* __restrict__ r, T* __restrict__ out,
@@ -1085,7 +1137,11 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   }
   T w[NJ + 2][3][2];
   T acc[NJ][2], dg[NJ][2];
-  if (interior) {
+  if constexpr (MODE == M_JACOBI2) {
+    static_assert(std::is_same<Op, OpFineK<2, T>>::value, "two fused sweeps from zero: finest level only");
+    if (interior) jacobi2_tile<T, NJ, false>(op, d, i, j0, r, omega, w, acc, dg);
+    else jacobi2_tile<T, NJ, true>(op, d, i, j0, r, omega, w, acc, dg);
+  } else if (interior) {
     if constexpr (MODE == M_PJACOBI) load_tile_prolong<T, NJ, false>(v, zc, d, dc, i, j0, w);
     else if constexpr (ROWS) load_tile<T, NJ, false>(v, d, i, j0, w);
     TileApply<T, Op, ROWS, NJ>::template run<false>(op, d, i, j0, w, acc, dg);

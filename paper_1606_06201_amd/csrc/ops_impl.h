@@ -389,6 +389,13 @@ struct OpsImpl : Ops {
       default: break;
     }
 #undef IPMG_L2D_CASE
+    if constexpr (std::is_same<Op, OpFineK<2, T>>::value) {
+      if (mode == M_JACOBI2) {
+        ProfScope ps_(c, c.prof_tag);
+        k_level2d<T, Op, M_JACOBI2, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
+                                                                 dc);
+      }
+    }
     if constexpr (NJ % 2 == 0) {
       if (mode == M_PJACOBI) {
         ProfScope ps_(c, c.prof_tag);
@@ -411,6 +418,30 @@ struct OpsImpl : Ops {
     else if (nj == 8) launch_l2d<T, Op, 8>(c, d, op, M_PJACOBI, z2, r, out, omg, aug, 0, -1, gate, nullptr, false, zc, &dc);
     else launch_l2d<T, Op, 4>(c, d, op, M_PJACOBI, z2, r, out, omg, aug, 0, -1, gate, nullptr, false, zc, &dc);
     return true;
+  }
+  // The first two pre-smoothing sweeps (zero start) in one tiled pass on the finest
+  // level of K; false when that pass does not apply.
+  template <typename T>
+  bool jacobi2_t(Ctx& c, const Dims& d, const T* r, T* out, const double* omg, const int* gate) {
+    const int nj = sizeof(T) == 4 ? c.nj32 : c.nj64;
+    if (!c.tiled2d || d.nnodes < c.tiled_min_nodes) return false;
+    const OpFineK<2, T> op{(const T*)c.xT, d.m};
+    const Aug<T> aug{nullptr, 0.0, d.nslots};
+    if (nj == 1) launch_l2d<T, OpFineK<2, T>, 1>(c, d, op, M_JACOBI2, nullptr, r, out, omg, aug, 0, -1, gate, nullptr, false);
+    else if (nj == 2) launch_l2d<T, OpFineK<2, T>, 2>(c, d, op, M_JACOBI2, nullptr, r, out, omg, aug, 0, -1, gate, nullptr, false);
+    else if (nj == 8) launch_l2d<T, OpFineK<2, T>, 8>(c, d, op, M_JACOBI2, nullptr, r, out, omg, aug, 0, -1, gate, nullptr, false);
+    else launch_l2d<T, OpFineK<2, T>, 4>(c, d, op, M_JACOBI2, nullptr, r, out, omg, aug, 0, -1, gate, nullptr, false);
+    return true;
+  }
+  bool jacobi2(Ctx& c, int lev, int op, const void* r, void* out, const double* omg, const int* gate) override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      if (op != IPMG_OP_K || !c.fold_prolong || lev != c.L - 1) return false;
+      const Dims& d = c.lev[lev].d;
+      if (c.fp32) return jacobi2_t<float>(c, d, (const float*)r, (float*)out, omg, gate);
+      return jacobi2_t<double>(c, d, (const double*)r, (double*)out, omg, gate);
+    }
   }
   bool prolong_jacobi(Ctx& c, int lev, int op, const void* z2, const void* zc, const void* r, void* out,
                       const double* omg, const int* gate) override {

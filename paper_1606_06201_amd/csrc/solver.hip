@@ -349,11 +349,20 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   const double* w = c.omega_dev + k;
   const bool fine = k == c.L - 1;
   const int jac = fine ? PC_FINE_JACOBI : (k == c.L - 2 ? PC_SUB_JACOBI : -1);
-  {
+  int pre = 0;
+  if (c.desc.nu_pre >= 2) {                   // the first two sweeps in one pass (z1 not stored)
+    ProfTag pt(c, fine ? PC_FINE_JACOBI2 : -1);
+    if (c.ops->jacobi2(c, k, op, l.r, nxt, w, gate)) {
+      std::swap(cur, nxt);
+      pre = 2;
+    }
+  }
+  if (pre == 0) {
     ProfTag pt(c, fine ? PC_FINE_JACOBI0 : -1);
     c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);     // pre-smoothing
+    pre = 1;
   }
-  for (int s = 1; s < c.desc.nu_pre; ++s) {
+  for (int s = pre; s < c.desc.nu_pre; ++s) {
     ProfTag pt(c, jac);
     c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
     std::swap(cur, nxt);
