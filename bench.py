@@ -40,8 +40,9 @@ KERNEL_NAMES = {
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
                   "Galerkin element matrices formed from the fine densities on the fly",
-    "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4>: p = -y + beta p, q = K p (FP64), p'q",
-    "pcg_update": "k_pcg_update<float>: z += alpha p, r += alpha q (FP64), FP32 copy of r, ||r||^2",
+    "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4, true>: p = -y + beta p, q = K p (FP64), p'q, "
+                 "and the previous step's z += alpha p_old",
+    "pcg_update": "k_pcg_update<float, false>: r += alpha q (FP64), FP32 copy of r, ||r||^2",
     "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
                 "restriction in one LDS-tiled pass",
     "sub_up": "k_up2d_staged<true, 16, 8, 256>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
@@ -82,10 +83,11 @@ def class_bytes(nel, fp32, kind):
         return 2 * w * N + w * m + 2 * w * N + 2 * w * Nc
     if kind == "fine_up":                       # read z2, coarse correction, r, x, FP64 r; write z
         return 3 * 2 * w * N + 2 * w * Nc + w * m + 2 * 8 * N
+    fold = os.environ.get("IPMG_NO_FOLD_SOLUTION", "0") != "1"   # z += alpha p in the direction kernel
     if kind == "dir_apply":                     # read y, p_old; write p, q (FP64); read x (FP64)
-        return 2 * N * (w + 3 * 8) + 8 * m
-    if kind == "pcg_update":                    # read z, r, p, q; write z, r (FP64); write r (V-cycle)
-        return 2 * N * (6 * 8 + w)
+        return 2 * N * (w + 3 * 8 + (2 * 8 if fold else 0)) + 8 * m     # (+ read, write z)
+    if kind == "pcg_update":                    # read r, q; write r (FP64); write r (V-cycle)
+        return 2 * N * ((3 if fold else 6) * 8 + w)                     # (+ read z, p; write z)
     raise ValueError(kind)
 
 

@@ -82,7 +82,9 @@ enum Scal {
   S_COUNT = 32
 };
 // Indices into the int device flag array.
-enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_COUNT = 8 };
+// F_ZPEND: the solution update z += alpha p of the last PCG step is pending (it
+// is folded into the next step's direction kernel).
+enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_ZPEND, F_COUNT = 8 };
 // Reduction counters (one per concurrently pending reduction kind).
 enum { C_MAIN = 0, C_AUX, C_COUNT = 8 };
 

@@ -30,8 +30,12 @@ struct Ops {
   virtual void level(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out,
                      const double* omg, int sidx, int sidx_in, const int* gate, const double* dot64 = nullptr) = 0;
   // p = -y + beta p_old; q = A p (FP64, finest level); alpha = rho / p'q on the device.
+  // zs (only where dir_folds_solution): the previous step's solution update
+  // zs += alpha p_old is done in the same pass when flags[F_ZPEND] is set, also
+  // after the solve has stopped (gate set).
   virtual void dir_apply(Ctx& c, int op, const void* y, const double* pold, double* p, double* q, int first,
-                         const int* gate) = 0;
+                         const int* gate, double* zs = nullptr) = 0;
+  virtual bool dir_folds_solution(const Ctx& c) const = 0;
   // FP64 operator on the finest grid (PCG operator), y = A v.
   virtual void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) = 0;
   virtual void restrict_to(Ctx& c, int lev_f, const void* rf, void* rc, int aug, const int* gate) = 0;
@@ -93,6 +97,7 @@ struct Ctx {
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
   bool staged_down_from_x = false;   // the first coarse level's down pass staged as well
   bool staged_big = false;           // first coarse level: staged passes on the large tiles
+  bool fold_solution = true;         // PCG solution update folded into the next direction kernel
   bool fold_prolong = true;          // 2D tiled levels: prolongation folded into the first post-sweep, and
                                      // the finest level's first two pre-sweeps fused
   int power_steps = 12;        // power iterations of the damping estimate (K)
@@ -120,6 +125,7 @@ struct Ctx {
   // coarsest dense solve
   int ncoarse = 0;             // dense size incl. lambda (n_slots_coarse + 1)
   double *dA = nullptr, *dLi = nullptr, *dAi = nullptr;   // packed tiles: A (then L), L^-1, A^-1
+  float* dAif = nullptr;       // A^-1 rounded to FP32 (FP32 V-cycle)
   double* dpart = nullptr;     // partial sums of the dense apply
 
   // per-level damping on the device: omega_dev[k] = weight, omega_dev[L + k] = rho estimate

@@ -263,9 +263,10 @@ __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, do
 }
 
 // A^-1 = X' X: tile (I, J), I >= J, is sum_{K >= I} X_KI' X_KJ.  Blocks run in
-// row order, so the tiles with the longest sums start first.
+// row order, so the tiles with the longest sums start first.  With Af set, the
+// tile is also stored rounded to FP32 (the inverse an FP32 V-cycle applies).
 __global__ __launch_bounds__(DTT) void k_dense_product(const double* __restrict__ X, double* __restrict__ Ai,
-                                                       int nt) {
+                                                       float* __restrict__ Af, int nt) {
   __shared__ Tile SA, SB;
   int I, J;
   tri_index((int)blockIdx.x, I, J);
@@ -279,9 +280,17 @@ __global__ __launch_bounds__(DTT) void k_dense_product(const double* __restrict_
     tile_mac(SA, SB, acc);
   }
   acc_store<false>(Ai + dense_tile_off(I, J), acc, acc);
+  if (Af) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<float4*>(Af + dense_tile_off(I, J) + (4 * ty + i) * DT + 4 * tx) =
+          make_float4((float)acc[i][0], (float)acc[i][1], (float)acc[i][2], (float)acc[i][3]);
+  }
 }
 
-// z = A^-1 r, part 1: tile (I, J) of the packed inverse gives its row sums
+// z = A^-1 r, part 1 (inverse stored as M = double or float, sums in FP64):
+// tile (I, J) of the packed inverse gives its row sums
 // A_IJ r_J to part[I][J] and, off the diagonal, its column sums A_IJ' r_I to
 // part[J][I] (64 values each), so every packed tile is read once.  Half-wave h of
 // wave w reads rows w*16 + 2i + h (i < 8) as 16-byte column pairs; each row sum
@@ -295,8 +304,14 @@ __device__ inline double masked_entry(const T* __restrict__ v, int i, int n) {
   return i < n ? x : 0.0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(DTT) void k_dense_apply(const double* __restrict__ Ai, int n, int nt,
+__device__ inline double2 pair_at(const double* __restrict__ a) { return *reinterpret_cast<const double2*>(a); }
+__device__ inline double2 pair_at(const float* __restrict__ a) {
+  const float2 v = *reinterpret_cast<const float2*>(a);
+  return make_double2((double)v.x, (double)v.y);
+}
+
+template <typename T, typename M>
+__global__ __launch_bounds__(DTT) void k_dense_apply(const M* __restrict__ Ai, int n, int nt,
                                                      const T* __restrict__ rc, double* __restrict__ part,
                                                      const int* gate) {
   if (gate && *gate) return;
@@ -310,10 +325,10 @@ __global__ __launch_bounds__(DTT) void k_dense_apply(const double* __restrict__ 
   double ri[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) ri[i] = masked_entry(rc, I * DT + w * 16 + 2 * i + h, n);
-  const double* a = Ai + (int64_t)blockIdx.x * DT * DT;
+  const M* a = Ai + (int64_t)blockIdx.x * DT * DT;
   double2 v[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const double2*>(a + (w * 16 + 2 * i + h) * DT + c2);
+  for (int i = 0; i < 8; ++i) v[i] = pair_at(a + (w * 16 + 2 * i + h) * DT + c2);
   double p[8], cs0 = 0.0, cs1 = 0.0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -380,7 +395,7 @@ void dense_init(hipStream_t st, double* A, int n, int pad) {
   k_dense_init<<<nt * (nt + 1) / 2, DTT, 0, st>>>(A, n, pad);
 }
 
-void dense_factor_inverse(hipStream_t st, double* W, double* X, double* Ai, int n, const Red& red) {
+void dense_factor_inverse(hipStream_t st, double* W, double* X, double* Ai, int n, const Red& red, float* Af) {
   const int nt = dense_tiles(n);
   k_dense_init<<<nt * (nt + 1) / 2, DTT, 0, st>>>(X, n, 0);
   k_dense_diag<<<1, DTT, 0, st>>>(W, X, 0, red);
@@ -390,17 +405,19 @@ void dense_factor_inverse(hipStream_t st, double* W, double* X, double* Ai, int 
     const int nu = m * (m + 1) / 2 + m * (k + 1);
     if (nu > 0) k_dense_update<<<nu, DTT, 0, st>>>(W, X, k, nt, red);
   }
-  k_dense_product<<<nt * (nt + 1) / 2, DTT, 0, st>>>(X, Ai, nt);
+  k_dense_product<<<nt * (nt + 1) / 2, DTT, 0, st>>>(X, Ai, Af, nt);
 }
 
-template <typename T>
-void dense_apply(hipStream_t st, const double* Ai, double* part, int n, const T* rc, T* zc, const int* gate) {
+template <typename T, typename M>
+void dense_apply(hipStream_t st, const M* Ai, double* part, int n, const T* rc, T* zc, const int* gate) {
   const int nt = dense_tiles(n);
-  k_dense_apply<T><<<nt * (nt + 1) / 2, DTT, 0, st>>>(Ai, n, nt, rc, part, gate);
+  k_dense_apply<T, M><<<nt * (nt + 1) / 2, DTT, 0, st>>>(Ai, n, nt, rc, part, gate);
   k_dense_apply_fin<T><<<nt, DTT, 0, st>>>(part, n, nt, zc, gate);
 }
 
-template void dense_apply<float>(hipStream_t, const double*, double*, int, const float*, float*, const int*);
-template void dense_apply<double>(hipStream_t, const double*, double*, int, const double*, double*, const int*);
+template void dense_apply<float, double>(hipStream_t, const double*, double*, int, const float*, float*, const int*);
+template void dense_apply<float, float>(hipStream_t, const float*, double*, int, const float*, float*, const int*);
+template void dense_apply<double, double>(hipStream_t, const double*, double*, int, const double*, double*,
+                                          const int*);
 
 }  // namespace ipmg

@@ -1260,18 +1260,41 @@ __global__ __launch_bounds__(BS) void k_dir_apply(Op op, Dims d, const TY* __res
 // 2D form of k_dir_apply with register-blocked tiles (as k_level2d): each thread
 // owns NJ nodes of one column, forms p = -y + beta p_old on the (NJ+2) x 3
 // neighbourhood once and reuses it for the NJ rows of q = A p.
-template <typename TY, class Op, int NJ>
+// ZF: the previous step's solution update zs += alpha p_old (alpha still in
+// scal[S_ALPHA]) is done here on the thread's own nodes, where p_old is loaded
+// anyway, when flags[F_ZPEND] is set; with the gate set only that update runs,
+// so the last step's update is not lost when the stop test passed.  The zs
+// loads follow the neighbourhood loads, so the operator's work hides them.
+template <typename TY, class Op, int NJ, bool ZF>
 __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __restrict__ y,
                                                     const double* __restrict__ pold, double* __restrict__ p,
                                                     double* __restrict__ q, Aug<double> aug, Red red, int first,
-                                                    const int* gate) {
-  if (gate && *gate) return;
-  const double beta = first ? 0.0 : red.scal[S_BETA];
+                                                    const int* gate, double* __restrict__ zs) {
+  const bool zup = ZF && red.flags[F_ZPEND] != 0;
+  const double alpha_prev = ZF ? red.scal[S_ALPHA] : 0.0;
   const Tile tl = xcd_tile();
   constexpr int RJ = (BS / 64) * NJ;
   const int ti0 = tl.x * 64, tj0 = tl.y * RJ;
   const int i = ti0 + (threadIdx.x & 63);
   const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
+  if (gate && *gate) {
+    if (zup && i < d.nx1) {
+#pragma unroll
+      for (int n = 0; n < NJ; ++n) {
+        const int j = j0 + n;
+        if (j >= d.ny1) break;
+        const int64_t qn = (int64_t)j * d.nx1 + i;
+        double po[2], zz[2];
+        load_node<2, double>(pold, qn, po);
+        load_node<2, double>(zs, qn, zz);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) zz[c] += alpha_prev * po[c];
+        store_node<2, double>(zs, qn, zz);
+      }
+    }
+    return;
+  }
+  const double beta = first ? 0.0 : red.scal[S_BETA];
   double pq = 0.0, bdot = 0.0, qy = 0.0;
   const double pl = aug.b ? (-(double)y[aug.n] + beta * (first ? 0.0 : pold[aug.n])) : 0.0;
   const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
@@ -1283,6 +1306,7 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
   const double bf = first ? 0.0 : beta;
   TY yc[NJ][2];
   double w[NJ + 2][3][2], acc[NJ][2], dg[NJ][2];
+  double zc[ZF ? NJ : 1][2];   // own nodes: p_old, then zs + alpha_prev p_old
 #pragma unroll
   for (int rr = 0; rr < NJ + 2; ++rr)
 #pragma unroll
@@ -1299,8 +1323,25 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
       if (cc == 1 && rr >= 1 && rr <= NJ) {
         yc[rr - 1][0] = yy[0];
         yc[rr - 1][1] = yy[1];
+        if constexpr (ZF) {
+          zc[rr - 1][0] = po[0];
+          zc[rr - 1][1] = po[1];
+        }
       }
     }
+  if constexpr (ZF) {
+    if (zup) {
+#pragma unroll
+      for (int n = 0; n < NJ; ++n) {   // clamped into the grid like the neighbourhood
+        const int jj = min(j0 + n, d.ny1 - 1);
+        const int64_t qq = (int64_t)jj * d.nx1 + (interior || i < d.nx1 ? i : 0);
+        double zz[2];
+        load_node<2, double>(zs, qq, zz);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) zc[n][c] = zz[c] + alpha_prev * zc[n][c];
+      }
+    }
+  }
   if (interior) TileApply<double, Op, true, NJ>::template run<false>(op, d, i, j0, w, acc, dg);
   else TileApply<double, Op, true, NJ>::template run<true>(op, d, i, j0, w, acc, dg);
 #pragma unroll
@@ -1326,6 +1367,9 @@ __global__ __launch_bounds__(BS) void k_dir_apply2d(Op op, Dims d, const TY* __r
     }
     store_node<2, double>(p, qn, pc);
     store_node<2, double>(q, qn, o);
+    if constexpr (ZF) {
+      if (zup) store_node<2, double>(zs, qn, zc[n]);
+    }
   }
   const double vals[3] = {pq, bdot, qy};
   block_partials<3>(vals, red);
@@ -1388,11 +1432,18 @@ __global__ __launch_bounds__(BS) void k_dir_apply3(Op op, Dims d, const TY* __re
 }
 
 // Finalize of k_dir_apply: lambda entries of p and q (augmented system) and
-// alpha = rho / p'q, with the breakdown test p'q > 0.
+// alpha = rho / p'q, with the breakdown test p'q > 0.  With zs (solution update
+// folded into the direction kernel) it also updates the lambda entry of zs and
+// clears the pending flag, gate or not.
 template <typename TY>
 __global__ __launch_bounds__(BS) void k_dir_fin(const TY* __restrict__ y, const double* __restrict__ pold,
                                                 double* __restrict__ p, double* __restrict__ q, int aug, double c,
-                                                int64_t n, int first, Red red, unsigned nblocks, const int* gate) {
+                                                int64_t n, int first, Red red, unsigned nblocks, const int* gate,
+                                                double* __restrict__ zs) {
+  if (zs && threadIdx.x == 0 && red.flags[F_ZPEND]) {
+    if (aug) zs[n] += red.scal[S_ALPHA] * pold[n];
+    red.flags[F_ZPEND] = 0;
+  }
   if (gate && *gate) return;
   double tot[3];
   sum_partials<3>(red, nblocks, tot);

@@ -547,30 +547,32 @@ struct OpsImpl : Ops {
 
   template <typename TY, class Op, int NJ>
   void launch_dir2d(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q, Aug<double> aug,
-                    int first, const int* gate) {
+                    int first, const int* gate, double* zs) {
     const Dims& d = c.fine();
     const dim3 g((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
     IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
     {
       ProfScope ps(c, PC_DIR_APPLY);
-      k_dir_apply2d<TY, Op, NJ><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+      if (zs) k_dir_apply2d<TY, Op, NJ, true><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate, zs);
+      else k_dir_apply2d<TY, Op, NJ, false><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate, zs);
     }
     k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
-                                          g.x * g.y, gate);
+                                          g.x * g.y, gate, zs);
   }
   template <typename TY, class Op>
   void launch_dir_apply(Ctx& c, const Op& op, const TY* y, const double* pold, double* p, double* q,
-                        Aug<double> aug, int first, const int* gate) {
+                        Aug<double> aug, int first, const int* gate, double* zs) {
     const Dims& d = c.fine();
     dim3 g = node_grid(d);
     if constexpr (DIM == 2) {
-      if (c.tiled2d && d.nnodes >= c.tiled_min_nodes) {
-        if (c.nj_dir == 1) return launch_dir2d<TY, Op, 1>(c, op, y, pold, p, q, aug, first, gate);
-        if (c.nj_dir == 4) return launch_dir2d<TY, Op, 4>(c, op, y, pold, p, q, aug, first, gate);
-        if (c.nj_dir == 3) return launch_dir2d<TY, Op, 3>(c, op, y, pold, p, q, aug, first, gate);
-        return launch_dir2d<TY, Op, 2>(c, op, y, pold, p, q, aug, first, gate);
+      if (dir_tiled(c)) {
+        if (c.nj_dir == 1) return launch_dir2d<TY, Op, 1>(c, op, y, pold, p, q, aug, first, gate, zs);
+        if (c.nj_dir == 4) return launch_dir2d<TY, Op, 4>(c, op, y, pold, p, q, aug, first, gate, zs);
+        if (c.nj_dir == 3) return launch_dir2d<TY, Op, 3>(c, op, y, pold, p, q, aug, first, gate, zs);
+        return launch_dir2d<TY, Op, 2>(c, op, y, pold, p, q, aug, first, gate, zs);
       }
     }
+    IPMG_REQUIRE(!zs, IPMG_E_STATE, "solution update folded into an untiled direction kernel");
     if constexpr (DIM == 3) {
       k_pdir3<TY><<<lin_grid(d.nslots), BS, 0, c.stream>>>(d, y, pold, p, c.red, first, gate);
       ProfScope ps(c, PC_DIR_APPLY);
@@ -580,21 +582,23 @@ struct OpsImpl : Ops {
       k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
     }
     k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
-                                          g.x * g.y * g.z, gate);
+                                          g.x * g.y * g.z, gate, nullptr);
   }
+  bool dir_tiled(const Ctx& c) const { return DIM == 2 && c.tiled2d && c.fine().nnodes >= c.tiled_min_nodes; }
+  bool dir_folds_solution(const Ctx& c) const override { return c.fold_solution && dir_tiled(c); }
   void dir_apply(Ctx& c, int op, const void* y, const double* pold, double* p, double* q, int first,
-                 const int* gate) override {
+                 const int* gate, double* zs) override {
     const Dims& d = c.fine();
     if (op == IPMG_OP_K) {
       OpFineK<DIM, double> o{c.x64, d.m};
       Aug<double> a{nullptr, 0.0, d.nslots};
-      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate);
-      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate);
+      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate, zs);
+      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate, zs);
     } else {
       OpFineZ<DIM, double> o{c.x64, c.h64, d.m};
       Aug<double> a{c.bZ64, c.cZ, d.nslots};
-      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate);
-      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate);
+      if (c.fp32) launch_dir_apply<float>(c, o, (const float*)y, pold, p, q, a, first, gate, zs);
+      else launch_dir_apply<double>(c, o, (const double*)y, pold, p, q, a, first, gate, zs);
     }
   }
 

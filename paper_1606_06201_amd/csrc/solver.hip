@@ -119,6 +119,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_STAGED_DOWN_FROM_X")) c.staged_down_from_x = e[0] == '1';
   if (const char* e = std::getenv("IPMG_STAGED_BIG")) c.staged_big = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_PROLONG")) c.fold_prolong = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_FOLD_SOLUTION")) c.fold_solution = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -226,7 +227,7 @@ void ctx_free(Ctx& c) {
   c.hT = nullptr;
   dfree(c.x64); dfree(c.h64); dfree(c.bZ64);
   dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu); dfree(c.pp2);
-  dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.dpart); dfree(c.omega_dev);
+  dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.dAif); dfree(c.dpart); dfree(c.omega_dev);
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
@@ -286,6 +287,7 @@ static void ensure_dense(Ctx& c) {
   dalloc(c.dA, sizeof(double) * np);
   dalloc(c.dLi, sizeof(double) * np);
   dalloc(c.dAi, sizeof(double) * np);
+  if (c.fp32) dalloc(c.dAif, sizeof(float) * np);
   dalloc(c.dpart, sizeof(double) * nt * nt * DT);
 }
 
@@ -313,7 +315,7 @@ void mg_setup(Ctx& c, int op, double* ms) {
   IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
   dense_init(c.stream, c.dA, n, 1);
   c.ops->dense_assemble(c, op, c.dA, n);
-  dense_factor_inverse(c.stream, c.dA, c.dLi, c.dAi, n, c.red);
+  dense_factor_inverse(c.stream, c.dA, c.dLi, c.dAi, n, c.red, c.dAif);
   IPMG_HIP(hipGetLastError());
   read_scalars(c);
   IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_BREAKDOWN, "coarsest operator is not positive definite");
@@ -334,8 +336,8 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   }
   if (k == 0) {
     const int n = l.d.nslots + aug;
-    if (c.fp32) dense_apply<float>(c.stream, c.dAi, c.dpart, n, (const float*)l.r, (float*)l.z, gate);
-    else dense_apply<double>(c.stream, c.dAi, c.dpart, n, (const double*)l.r, (double*)l.z, gate);
+    if (c.fp32) dense_apply<float, float>(c.stream, c.dAif, c.dpart, n, (const float*)l.r, (float*)l.z, gate);
+    else dense_apply<double, double>(c.stream, c.dAi, c.dpart, n, (const double*)l.r, (double*)l.z, gate);
     return l.z;
   }
   if (c.ops->fused_applies(c, k, op)) {
@@ -412,18 +414,22 @@ void vcycle64(Ctx& c, int op, const double* r, double* z) {
 //   z += alpha p, r += alpha q, ||r||^2  (one fused kernel, sets the done flag)
 //   y = M r with beta = r'y / rho fused into the last smoothing sweep.
 // `first` selects beta = 0 (first step after a (re)start).
+// With the fold, z += alpha p of a step is done by the next step's direction
+// kernel (which reads that p anyway) and, for the last step, by vzflush.
 static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first) {
-  c.ops->dir_apply(c, op, c.yT, c.pp, c.pp2, c.pq, first, gate);
+  const bool fold = c.ops->dir_folds_solution(c);
+  c.ops->dir_apply(c, op, c.yT, c.pp, c.pp2, c.pq, first, gate, fold ? c.pu : nullptr);
   std::swap(c.pp, c.pp2);                                               // c.pp holds the new p
   void* rT = c.lev[c.L - 1].r;
+  double* z = fold ? nullptr : c.pu;
   {
     ProfScope ps(c, PC_PCG_UPDATE);
     if (c.fp32)
-      vpcg_update<float>(c.stream, c.pu, c.pr, c.pp, c.pq, (float*)rT, n, c.red, gate);
+      vpcg_update<float>(c.stream, z, c.pr, c.pp, c.pq, (float*)rT, n, c.red, gate);
     else
-      vpcg_update<double>(c.stream, c.pu, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
+      vpcg_update<double>(c.stream, z, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
   }
-  vpcg_update_fin(c.stream, n, c.red, gate);
+  vpcg_update_fin(c.stream, n, c.red, gate, fold);
   const bool fused_beta = c.desc.nu_post >= 1 && c.tail_top < c.L - 1;
   void* y = vcycle_level(c, op, c.L - 1, gate, fused_beta ? c.pr : nullptr);
   if (!fused_beta) {
@@ -506,6 +512,9 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
       }
       slot ^= 1;
     }
+    // A pending update belongs to the last enqueued step (any later direction
+    // kernel, gated or not, applies and clears it), whose p is c.pp.
+    if (c.ops->dir_folds_solution(c)) vzflush(c.stream, c.pu, c.pp, n, c.red);
     IPMG_HIP(hipGetLastError());
     read_scalars(c);
     (void)done;

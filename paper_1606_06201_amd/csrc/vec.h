@@ -12,8 +12,11 @@ template <typename T>
 void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Red& red, int sidx, const int* gate);
 template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
-                 const Red& red, const int* gate);   // block partials of ||r||^2 ...
-void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate);   // ... summed, done flag
+                 const Red& red, const int* gate);   // z may be null; block partials of ||r||^2 ...
+// ... summed, done flag; zpend: z was left out (flags[F_ZPEND] set for the next step)
+void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate, bool zpend = false);
+// z += alpha p if flags[F_ZPEND], then the flag cleared (after the PCG step loop).
+void vzflush(hipStream_t st, double* z, const double* p, int64_t n, const Red& red);
 template <typename T>
 void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate);
 void vsub_norm(hipStream_t st, const double* a, const double* b, double* out, int64_t n, const Red& red, int sidx);

@@ -14,7 +14,7 @@ inline int vgrid(int64_t n) {
 }
 
 // Post-processing done by the last block of a reduction.
-enum Fin { FIN_STORE = 0, FIN_ALPHA = 1, FIN_RN2 = 2, FIN_BETA = 3 };
+enum Fin { FIN_STORE = 0, FIN_ALPHA = 1, FIN_RN2 = 2, FIN_BETA = 3, FIN_RN2_ZPEND = 4 };
 
 __device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
   if (fin == FIN_STORE) {
@@ -27,7 +27,8 @@ __device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
     } else {
       red.scal[S_ALPHA] = red.scal[S_RHO] / tot;
     }
-  } else if (fin == FIN_RN2) {                   // convergence test on ||r||^2
+  } else if (fin == FIN_RN2 || fin == FIN_RN2_ZPEND) {   // convergence test on ||r||^2
+    if (fin == FIN_RN2_ZPEND) red.flags[F_ZPEND] = 1;     // z += alpha p left to the next step
     red.scal[S_RN2] = tot;
     red.flags[F_ITERS] += 1;
     if (!isfinite(tot)) {
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(BS) void k_dot(const TA* __restrict__ a, const TB* 
   block_partials<1>(v, red);
 }
 
-// z += alpha p; r += alpha q; rT = (T) r; ||r||^2 -> convergence flag.
+// z += alpha p (unless ZUPD is off: then the next direction kernel does it);
+// r += alpha q; rT = (T) r; ||r||^2 -> convergence flag.
 // Each thread takes pairs of entries (16-byte accesses), two pairs per step with
 // all eight loads issued first, so enough bytes are in flight to stream at the
 // HBM rate; an odd last entry is taken by the first thread.
@@ -78,7 +80,7 @@ __device__ inline void store_pair(T* p, double a, double b) {
   else *reinterpret_cast<float2*>(p) = make_float2((float)a, (float)b);
 }
 
-template <typename T>
+template <typename T, bool ZUPD>
 __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, double* __restrict__ r,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    T* __restrict__ rT, int64_t n, Red red, const int* gate) {
@@ -93,10 +95,14 @@ __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, doubl
   int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
   for (; t + stride < np; t += 2 * stride) {
     const int64_t u = t + stride;
-    const double2 za = z2[t], pa = p2[t], ra = r2[t], qa = q2[t];
-    const double2 zb = z2[u], pb = p2[u], rb = r2[u], qb = q2[u];
-    z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
-    z2[u] = make_double2(zb.x + alpha * pb.x, zb.y + alpha * pb.y);
+    const double2 ra = r2[t], qa = q2[t];
+    const double2 rb = r2[u], qb = q2[u];
+    if constexpr (ZUPD) {
+      const double2 za = z2[t], pa = p2[t];
+      const double2 zb = z2[u], pb = p2[u];
+      z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
+      z2[u] = make_double2(zb.x + alpha * pb.x, zb.y + alpha * pb.y);
+    }
     const double2 na = make_double2(ra.x + alpha * qa.x, ra.y + alpha * qa.y);
     const double2 nb = make_double2(rb.x + alpha * qb.x, rb.y + alpha * qb.y);
     r2[t] = na;
@@ -109,8 +115,11 @@ __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, doubl
     s1 += nb.x * nb.x + nb.y * nb.y;
   }
   if (t < np) {
-    const double2 za = z2[t], pa = p2[t], ra = r2[t], qa = q2[t];
-    z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
+    const double2 ra = r2[t], qa = q2[t];
+    if constexpr (ZUPD) {
+      const double2 za = z2[t], pa = p2[t];
+      z2[t] = make_double2(za.x + alpha * pa.x, za.y + alpha * pa.y);
+    }
     const double2 na = make_double2(ra.x + alpha * qa.x, ra.y + alpha * qa.y);
     r2[t] = na;
     if (rT) store_pair<T>(rT + 2 * t, na.x, na.y);
@@ -118,7 +127,7 @@ __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, doubl
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
     const int64_t e = n - 1;
-    z[e] += alpha * p[e];
+    if constexpr (ZUPD) z[e] += alpha * p[e];
     const double rn = r[e] + alpha * q[e];
     r[e] = rn;
     if (rT) rT[e] = T(rn);
@@ -126,6 +135,20 @@ __global__ __launch_bounds__(BS) void k_pcg_update(double* __restrict__ z, doubl
   }
   const double v[1] = {s0 + s1};
   block_partials<1>(v, red);
+}
+
+// The pending solution update of the last PCG step (flags[F_ZPEND], see
+// k_dir_apply2d), applied after the step loop whatever stopped it; the flag is
+// cleared by the next kernel.
+__global__ __launch_bounds__(BS) void k_zflush(double* __restrict__ z, const double* __restrict__ p, int64_t n,
+                                               Red red) {
+  if (!red.flags[F_ZPEND]) return;
+  const double alpha = red.scal[S_ALPHA];
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    z[t] += alpha * p[t];
+}
+__global__ void k_zclear(Red red) {
+  if (threadIdx.x == 0) red.flags[F_ZPEND] = 0;
 }
 
 // p = -y + beta p  (the reading p := -y~ + beta p of Algorithm PCG).
@@ -261,10 +284,15 @@ void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Re
 template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
                  const Red& red, const int* gate) {
-  k_pcg_update<T><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+  if (z) k_pcg_update<T, true><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+  else k_pcg_update<T, false><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
 }
-void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate) {
-  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), FIN_RN2, 0, gate);
+void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate, bool zpend) {
+  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
+}
+void vzflush(hipStream_t st, double* z, const double* p, int64_t n, const Red& red) {
+  k_zflush<<<vgrid(n), BS, 0, st>>>(z, p, n, red);
+  k_zclear<<<1, 64, 0, st>>>(red);
 }
 template <typename T>
 void vpcg_dir(hipStream_t st, double* p, const T* y, int64_t n, const Red& red, int first, const int* gate) {
