@@ -98,6 +98,9 @@ struct Ctx {
   bool staged_down_from_x = false;   // the first coarse level's down pass staged as well
   bool staged_big = false;           // first coarse level: staged passes on the large tiles
   bool fold_solution = true;         // PCG solution update folded into the next direction kernel
+  bool fold_rn2_fin = true;          // PCG ||r||^2 finalize done by the V-cycle's first pass
+  unsigned rn2_fin_blocks = 0;       // pending ||r||^2 finalize (partials of the update kernel) ...
+  bool rn2_fin_zpend = false;        // ... and whether it marks z += alpha p pending
   bool fold_prolong = true;          // 2D tiled levels: prolongation folded into the first post-sweep, and
                                      // the finest level's first two pre-sweeps fused
   int power_steps = 12;        // power iterations of the damping estimate (K)

@@ -188,6 +188,22 @@ __device__ void sum_partials(const Red& red, unsigned nblocks, double (&tot)[NV]
   }
 }
 
+// Convergence test of a PCG step on ||r||^2 (Algorithm PCG, stopping rule):
+// counts the step, sets the done flag when ||r||^2 <= tol^2 and the breakdown
+// flag when it is not finite; zpend marks the step's z += alpha p as pending
+// (done by the next direction kernel).  One thread.
+__device__ inline void rn2_finish(double tot, const Red& red, bool zpend) {
+  if (zpend) red.flags[F_ZPEND] = 1;
+  red.scal[S_RN2] = tot;
+  red.flags[F_ITERS] += 1;
+  if (!isfinite(tot)) {
+    red.flags[F_DONE] = 2;
+    red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
+  } else if (tot <= red.scal[S_TOL2]) {
+    red.flags[F_DONE] = 1;
+  }
+}
+
 // --------------------------------------------------------------- operators ----
 // Each operator gives, for element e and local node a, the contribution of the
 // element matrix rows (a,c) times the local vector ve, and the diagonal entries.
@@ -1106,7 +1122,8 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
                                                 const T* __restrict__ r, T* __restrict__ out,
                                                 const double* __restrict__ omg, Aug<T> aug, Red red,
                                                 const double* __restrict__ dot64, const int* gate,
-                                                const T* __restrict__ zc, Dims dc) {
+                                                const T* __restrict__ zc, Dims dc, unsigned fin_blocks,
+                                                int fin_zpend) {
   if (gate && *gate) return;
   const T omega = omg ? T(*omg) : T(0);
   const Tile tl = xcd_tile();
@@ -1175,6 +1192,16 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   } else if constexpr (MODE == M_JACOBI_BETA) {
     const double vals[3] = {red0, red1, 0.0};
     block_partials<3>(vals, red);
+  }
+  if constexpr (MODE == M_JACOBI2) {
+    // fin_blocks != 0: this pass follows the PCG residual update (same gate) and
+    // its first block also finalizes that update's ||r||^2, in place of a
+    // one-block kernel between the two; the later passes are gated on the result.
+    if (fin_blocks && block_id() == 0) {
+      double tot[1];
+      sum_partials<1>(red, fin_blocks, tot);
+      if (threadIdx.x == 0) rn2_finish(tot[0], red, fin_zpend != 0);
+    }
   }
 }
 

@@ -373,7 +373,8 @@ struct OpsImpl : Ops {
   case M:                                                                                                    \
     {                                                                                                        \
       ProfScope ps_(c, c.prof_tag);                                                                          \
-      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc, dc); \
+      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc, dc, \
+                                                       0u, 0);                                               \
     }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
@@ -393,14 +394,15 @@ struct OpsImpl : Ops {
       if (mode == M_JACOBI2) {
         ProfScope ps_(c, c.prof_tag);
         k_level2d<T, Op, M_JACOBI2, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
-                                                                 dc);
+                                                                 dc, c.rn2_fin_blocks, c.rn2_fin_zpend ? 1 : 0);
+        c.rn2_fin_blocks = 0;
       }
     }
     if constexpr (NJ % 2 == 0) {
       if (mode == M_PJACOBI) {
         ProfScope ps_(c, c.prof_tag);
         k_level2d<T, Op, M_PJACOBI, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
-                                                                 dc);
+                                                                 dc, 0u, 0);
       }
     }
   }

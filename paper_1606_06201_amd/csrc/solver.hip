@@ -120,6 +120,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_STAGED_BIG")) c.staged_big = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_PROLONG")) c.fold_prolong = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_SOLUTION")) c.fold_solution = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_FOLD_RN2")) c.fold_rn2_fin = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -327,9 +328,20 @@ void mg_setup(Ctx& c, int op, double* ms) {
 // V-cycle on level k: lev[k].r -> returned buffer (Algorithm MG, zero start).
 // beta64 (finest level only): if not null, the last post-smoothing sweep also
 // forms beta = beta64'y / rho of Algorithm PCG on the device.
+// A ||r||^2 finalize left pending by pcg_iteration (c.rn2_fin_blocks) is done by
+// the finest level's fused first two sweeps, else here before the first kernel.
+static void rn2_fin_flush(Ctx& c, const int* gate) {
+  if (!c.rn2_fin_blocks) return;
+  vpcg_update_fin_nb(c.stream, c.rn2_fin_blocks, c.red, gate, c.rn2_fin_zpend);
+  c.rn2_fin_blocks = 0;
+}
+
 static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* beta64) {
   Level& l = c.lev[k];
   const int aug = op == IPMG_OP_Z;
+  if (c.rn2_fin_blocks &&
+      (k == c.tail_top || k == 0 || c.ops->fused_applies(c, k, op) || c.desc.nu_pre < 2))
+    rn2_fin_flush(c, gate);
   if (k == c.tail_top) {
     c.ops->tail(c, op, gate);
     return l.z;
@@ -359,6 +371,7 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
       pre = 2;
     }
   }
+  rn2_fin_flush(c, gate);
   if (pre == 0) {
     ProfTag pt(c, fine ? PC_FINE_JACOBI0 : -1);
     c.ops->level(c, k, op, M_JACOBI0, nullptr, l.r, cur, w, 0, -1, gate);     // pre-smoothing
@@ -429,7 +442,12 @@ static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first)
     else
       vpcg_update<double>(c.stream, z, c.pr, c.pp, c.pq, (double*)rT, n, c.red, gate);
   }
-  vpcg_update_fin(c.stream, n, c.red, gate, fold);
+  if (c.fold_rn2_fin) {                   // finalized by the V-cycle's first pass
+    c.rn2_fin_blocks = vpcg_update_blocks(n);
+    c.rn2_fin_zpend = fold;
+  } else {
+    vpcg_update_fin(c.stream, n, c.red, gate, fold);
+  }
   const bool fused_beta = c.desc.nu_post >= 1 && c.tail_top < c.L - 1;
   void* y = vcycle_level(c, op, c.L - 1, gate, fused_beta ? c.pr : nullptr);
   if (!fused_beta) {

@@ -15,6 +15,8 @@ void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const do
                  const Red& red, const int* gate);   // z may be null; block partials of ||r||^2 ...
 // ... summed, done flag; zpend: z was left out (flags[F_ZPEND] set for the next step)
 void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate, bool zpend = false);
+unsigned vpcg_update_blocks(int64_t n);   // partials vpcg_update writes
+void vpcg_update_fin_nb(hipStream_t st, unsigned nblocks, const Red& red, const int* gate, bool zpend);
 // z += alpha p if flags[F_ZPEND], then the flag cleared (after the PCG step loop).
 void vzflush(hipStream_t st, double* z, const double* p, int64_t n, const Red& red);
 template <typename T>

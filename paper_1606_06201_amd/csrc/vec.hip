@@ -28,15 +28,7 @@ __device__ inline void finish(int fin, double tot, const Red& red, int sidx) {
       red.scal[S_ALPHA] = red.scal[S_RHO] / tot;
     }
   } else if (fin == FIN_RN2 || fin == FIN_RN2_ZPEND) {   // convergence test on ||r||^2
-    if (fin == FIN_RN2_ZPEND) red.flags[F_ZPEND] = 1;     // z += alpha p left to the next step
-    red.scal[S_RN2] = tot;
-    red.flags[F_ITERS] += 1;
-    if (!isfinite(tot)) {
-      red.flags[F_DONE] = 2;
-      red.flags[F_STATUS] = IPMG_E_BREAKDOWN;
-    } else if (tot <= red.scal[S_TOL2]) {
-      red.flags[F_DONE] = 1;
-    }
+    rn2_finish(tot, red, fin == FIN_RN2_ZPEND);
   } else if (fin == FIN_BETA) {                  // beta = r~'y~ / r'y (or Polak-Ribiere)
     if (!(tot > 0.0) || !isfinite(tot)) {
       red.flags[F_DONE] = 2;
@@ -289,6 +281,10 @@ void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const do
 }
 void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate, bool zpend) {
   k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
+}
+unsigned vpcg_update_blocks(int64_t n) { return (unsigned)vgrid(n); }
+void vpcg_update_fin_nb(hipStream_t st, unsigned nblocks, const Red& red, const int* gate, bool zpend) {
+  k_fin1<<<1, BS, 0, st>>>(red, nblocks, zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
 }
 void vzflush(hipStream_t st, double* z, const double* p, int64_t n, const Red& red) {
   k_zflush<<<vgrid(n), BS, 0, st>>>(z, p, n, red);

@@ -172,27 +172,29 @@ def test_pcg_edge_cases():
     assert info4["iters"] == 1
 
 
+@pytest.mark.parametrize("env", ["IPMG_NO_FOLD_SOLUTION", "IPMG_NO_FOLD_RN2"])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_pcg_folded_solution_update_is_exact(fp32, monkeypatch):
-    # With the register-blocked direction kernel the step's z += alpha p is done
-    # by the next step's direction kernel, and the last step's by a flush after
-    # the loop (converged, stopped at maxit, or zero steps).  Same additions in the
-    # same order: the iterates equal those of the separate update bit for bit.
+def test_pcg_folded_steps_are_exact(env, fp32, monkeypatch):
+    # With the register-blocked passes a PCG step's z += alpha p is done by the next
+    # step's direction kernel (the last step's by a flush after the loop: converged,
+    # stopped at maxit, or zero steps), and its ||r||^2 finalize by the first pass of
+    # the V-cycle.  Same arithmetic in the same order: the iterates and counts equal
+    # those of the separate kernels bit for bit.
     nel, levels = (96, 48), 4
     g, K0, x = _kproblem(nel)
     f = fem.load_vector(g, tip_load(nel))
     monkeypatch.setenv("IPMG_TILED_MIN_NODES", "0")
     out = {}
-    for fold in ("0", "1"):
-        monkeypatch.setenv("IPMG_NO_FOLD_SOLUTION", fold)
+    for off in ("0", "1"):
+        monkeypatch.setenv(env, off)
         s = _solver(nel, levels, fp32=fp32)
         s.set_density(T(x))
         u, info = s.pcg(T(f), rtol=1e-9)
         u2, info2 = s.pcg(T(f), rtol=1e-12, maxit=3, check=False)
         u3, info3 = s.pcg(T(f), u0=u, rtol=1e-3)
         assert info["true_relres"] <= 1e-9
-        out[fold] = (N(u), info["iters"], N(u2), info2["iters"], N(u3), info3["iters"])
-    monkeypatch.delenv("IPMG_NO_FOLD_SOLUTION")
+        out[off] = (N(u), info["iters"], N(u2), info2["iters"], N(u3), info3["iters"])
+    monkeypatch.delenv(env)
     a, b = out["0"], out["1"]
     assert a[1] == b[1] and a[3] == b[3] == 3 and a[5] == b[5] == 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2]) and np.array_equal(a[4], b[4])
