@@ -43,8 +43,8 @@ KERNEL_NAMES = {
     "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4, true>: p = -y + beta p, q = K p (FP64), p'q, "
                  "and the previous step's z += alpha p_old",
     "pcg_update": "k_pcg_update<float, false>: r += alpha q (FP64), FP32 copy of r, ||r||^2",
-    "sub_down": "k_down2d<float, OpCoarse2K<2,float>>: first coarse level, two Jacobi sweeps, residual and "
-                "restriction in one LDS-tiled pass",
+    "sub_down": "k_down2d<float, OpCoarse2K<2,float>, true>: first coarse level, its r = P' t from the finest "
+                "residual, two Jacobi sweeps, residual and restriction in one LDS-tiled pass",
     "sub_up": "k_up2d_staged<true, 16, 8, 256>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
               "pass, element matrices formed from the densities in LDS",
     "fine_down": "k_down2d_fine<float>: finest level, two Jacobi sweeps, residual and restriction in one "
@@ -76,6 +76,8 @@ def class_bytes(nel, fp32, kind):
         return 3 * 2 * w * Nc + w * m
     Nc2 = (nx // 4 + 1) * (ny // 4 + 1)    # second coarse level nodes
     if kind == "sub_down":                      # read r, fine x; write z2, coarse residual
+        if os.environ.get("IPMG_NO_FOLD_RESTRICT", "0") != "1":    # r = P' t formed in the pass: read the
+            return 2 * w * N + w * m + 4 * w * Nc + 2 * w * Nc2     # finest t instead, write r for the up pass
         return 2 * w * Nc + w * m + 2 * w * Nc + 2 * w * Nc2
     if kind == "sub_up":                        # read z2, r, coarse correction, fine x; write z
         return 3 * 2 * w * Nc + 2 * w * Nc2 + w * m

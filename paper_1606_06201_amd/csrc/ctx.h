@@ -58,6 +58,9 @@ struct Ops {
   //   down: lev.r -> z2 (into z), coarse residual (into lev-1 .r)
   //   up:   z2 (in z), coarse correction zc -> out
   virtual bool fused_applies(const Ctx& c, int lev, int op) const = 0;
+  // The fused down pass of lev forms its r as P' t from the finest residual t
+  // (passed in Ctx::down_from_t) instead of reading a restricted one.
+  virtual bool down_restricts(const Ctx& c, int lev, int op) const = 0;
   virtual void fused_down(Ctx& c, int lev, const int* gate) = 0;
   virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate,
                         const double* beta64 = nullptr) = 0;
@@ -99,6 +102,8 @@ struct Ctx {
   bool staged_big = false;           // first coarse level: staged passes on the large tiles
   bool fold_solution = true;         // PCG solution update folded into the next direction kernel
   bool fold_rn2_fin = true;          // PCG ||r||^2 finalize done by the V-cycle's first pass
+  bool fold_restrict = true;         // finest residual restricted inside the first coarse down pass
+  const void* down_from_t = nullptr; // ... the residual, pending for that pass
   unsigned rn2_fin_blocks = 0;       // pending ||r||^2 finalize (partials of the update kernel) ...
   bool rn2_fin_zpend = false;        // ... and whether it marks z += alpha p pending
   bool fold_prolong = true;          // 2D tiled levels: prolongation folded into the first post-sweep, and

@@ -200,6 +200,43 @@ struct DownLoads {
       load_node<2, T>(rg, (int64_t)min(max(gj, 0), d.ny1 - 1) * d.nx1 + (fr ? gi : 0), r[u]);
     }
   }
+  // The first coarse level under the finest: r = P' t formed here from the finest
+  // residual t (df its grid) with the weights, masks and summation order of
+  // k_restrict, and stored (rout) on the nodes the tile owns, for the up pass.
+  __device__ inline void load_restrict(const Dims& d, const Dims& df, int CI0, int CJ0, const T* __restrict__ tf,
+                                       T* __restrict__ rout) {
+    const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
+#pragma unroll
+    for (int u = 0; u < P1; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int gi = ox + t % W1, gj = oy + t / W1;
+      T vv[9][2];
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int i = 2 * gi + dx, j = 2 * gj + dy;
+          const int ic = min(max(i, 0), df.nx1 - 1), jc = min(max(j, 0), df.ny1 - 1);
+          load_node<2, T>(tf, (int64_t)jc * df.nx1 + ic, vv[3 * (dy + 1) + dx + 1]);
+        }
+      T acc[2] = {T(0), T(0)};
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int i = 2 * gi + dx, j = 2 * gj + dy;
+          const bool ok = gi > 0 && i >= 1 && i < df.nx1 && j >= 0 && j < df.ny1;
+          const T w = T(w1(dx) * w1(dy));
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc[c] += ok ? w * vv[3 * (dy + 1) + dx + 1][c] : T(0);
+        }
+      r[u][0] = acc[0];
+      r[u][1] = acc[1];
+      const bool own = t < W1 * H1 && gi >= 2 * CI0 && gi < 2 * CI0 + 2 * CX && gi < d.nx1 && gj >= 2 * CJ0 &&
+                       gj < 2 * CJ0 + 2 * CY && gj < d.ny1;
+      if (own) store_node<2, T>(rout, (int64_t)gj * d.nx1 + gi, acc);
+    }
+  }
 };
 
 template <typename T, int TX, int TY, int NT>
@@ -398,16 +435,20 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
 }
 
 // Grid: (ceil(dc.nx1 / FCX), ceil(dc.ny1 / FCY)); d is level k, dc level k-1.
-template <typename T, class Op>
+// FROM_T: r is not read but restricted from the finest residual tf (grid df) in
+// the tile (DownLoads::load_restrict) and stored into rw for the up pass.
+template <typename T, class Op, bool FROM_T = false>
 __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
                                                 T* __restrict__ z2out, T* __restrict__ rc,
-                                                const double* __restrict__ omg, const int* gate) {
+                                                const double* __restrict__ omg, const int* gate, Dims df,
+                                                const T* __restrict__ tf, T* __restrict__ rw) {
   if (gate && *gate) return;
   constexpr int W1 = 2 * FCX + 5, H1 = 2 * FCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
   const Tile tl = xcd_tile();
   DownLoads<T, FCX, FCY, FBS> pre;
-  pre.load(d, (int)tl.x * FCX, (int)tl.y * FCY, r);
+  if constexpr (FROM_T) pre.load_restrict(d, df, (int)tl.x * FCX, (int)tl.y * FCY, tf, rw);
+  else pre.load(d, (int)tl.x * FCX, (int)tl.y * FCY, r);
   down_tile<T, Op, FCX, FCY, FBS>(op, d, dc, (int)tl.x * FCX, (int)tl.y * FCY, pre, z2out, rc, T(*omg), sr, sd, s1,
                                   s2, s3);
 }

@@ -693,14 +693,36 @@ struct OpsImpl : Ops {
         return;
       }
     }
-    if (lev == c.L - 2 && c.coarse_from_x)
-      k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, d, dc,
-                                                               (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
-                                                               (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
-    else
+    const Dims& df = c.fine();
+    if (lev == c.L - 2 && c.coarse_from_x) {
+      const OpCoarse2K<2, T> op{(const T*)c.xT, c.fine().nx, c.fine().m};
+      if (c.down_from_t) {   // restriction of the finest residual done in the tile
+        k_down2d<T, OpCoarse2K<2, T>, true><<<g, FBS, 0, c.stream>>>(
+            op, d, dc, nullptr, (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
+            (const T*)c.down_from_t, (T*)c.lev[lev].r);
+        c.down_from_t = nullptr;
+      } else {
+        k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(op, d, dc, (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
+                                                                (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
+                                                                nullptr, nullptr);
+      }
+    } else {
       k_down2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
                                                              (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
-                                                             (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+                                                             (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
+                                                             nullptr, nullptr);
+    }
+  }
+  // The down pass of level lev (the first coarse level) restricts the finest
+  // residual itself: the plain register-blocked fused pass for K formed from the
+  // densities, in FP32 (the other variants read the restricted residual).
+  bool down_restricts(const Ctx& c, int lev, int op) const override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      return c.fold_restrict && c.fp32 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x &&
+             fused_applies(c, lev, op) && !(c.fused_staged && (c.staged_big || c.staged_down_from_x));
+    }
   }
   template <typename T>
   void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate, const double* beta64) {

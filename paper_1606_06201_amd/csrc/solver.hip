@@ -121,6 +121,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_FOLD_PROLONG")) c.fold_prolong = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_SOLUTION")) c.fold_solution = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_RN2")) c.fold_rn2_fin = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_FOLD_RESTRICT")) c.fold_restrict = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -386,8 +387,10 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
     ProfTag pt(c, fine ? PC_FINE_RESID : -1);
     c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);     // restricted residual
   }
-  c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
+  if (c.ops->down_restricts(c, k - 1, op)) c.down_from_t = l.t;             // restricted in the next pass
+  else c.ops->restrict_to(c, k, l.t, c.lev[k - 1].r, aug, gate);
   void* vc = vcycle_level(c, op, k - 1, gate, nullptr);                       // coarse correction
+  IPMG_REQUIRE(!c.down_from_t, IPMG_E_STATE, "restriction left pending");
   int s0 = 0;
   if (c.desc.nu_post >= 2) {                  // solution update folded into the first post-sweep
     ProfTag pt(c, fine ? PC_FINE_PJACOBI : jac);

@@ -234,7 +234,7 @@ def test_element_sensitivities_match_oracle():
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
                                      ("IPMG_UNSTAGED", "1"), ("IPMG_FUSED_FINE", "1"), ("IPMG_STAGED_BIG", "1"),
                                      ("IPMG_STAGED_DOWN_FROM_X", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
-                                     ("IPMG_NO_FOLD_PROLONG", "1")])
+                                     ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
                                                   ((8, 4, 4), 3, False, 1e-11), ((128, 64), 4, False, 1e-11),
                                                   ((128, 64), 4, True, 2e-4)])
