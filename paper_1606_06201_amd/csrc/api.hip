@@ -204,8 +204,8 @@ int ipmg_profile_begin(ipmg_ctx* ctx, unsigned class_mask, int max_launches) {
   return guard(ctx, [&](Ctx& c) {
     ipmg::sync(c);
     while ((int)c.prof_ev.size() < 2 * max_launches) {
-      hipEvent_t e;
-      IPMG_HIP(hipEventCreate(&e));
+      hipEvent_t e;   // timing only: no system-scope fence (no cache writeback around the kernel)
+      IPMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       c.prof_ev.push_back(e);
     }
     c.prof_cls.assign(max_launches, -1);

@@ -12,6 +12,13 @@ inline int vgrid(int64_t n) {
   int64_t b = (n + BS - 1) / BS;
   return (int)(b < VBLOCKS ? (b < 1 ? 1 : b) : VBLOCKS);
 }
+// The residual update runs one entry pair per thread (2048x1024: 22.3 us against
+// 23.8 us for a grid-stride loop over 1024 blocks).
+constexpr int UBLOCKS = 16384;
+inline int ugrid(int64_t n) {
+  int64_t b = ((n + 1) / 2 + BS - 1) / BS;
+  return (int)(b < UBLOCKS ? (b < 1 ? 1 : b) : UBLOCKS);
+}
 
 // Post-processing done by the last block of a reduction.
 enum Fin { FIN_STORE = 0, FIN_ALPHA = 1, FIN_RN2 = 2, FIN_BETA = 3, FIN_RN2_ZPEND = 4 };
@@ -276,13 +283,13 @@ void vdot_store(hipStream_t st, const double* r, const T* y, int64_t n, const Re
 template <typename T>
 void vpcg_update(hipStream_t st, double* z, double* r, const double* p, const double* q, T* rT, int64_t n,
                  const Red& red, const int* gate) {
-  if (z) k_pcg_update<T, true><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
-  else k_pcg_update<T, false><<<vgrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+  if (z) k_pcg_update<T, true><<<ugrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
+  else k_pcg_update<T, false><<<ugrid(n), BS, 0, st>>>(z, r, p, q, rT, n, red, gate);
 }
 void vpcg_update_fin(hipStream_t st, int64_t n, const Red& red, const int* gate, bool zpend) {
-  k_fin1<<<1, BS, 0, st>>>(red, vgrid(n), zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
+  k_fin1<<<1, BS, 0, st>>>(red, ugrid(n), zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
 }
-unsigned vpcg_update_blocks(int64_t n) { return (unsigned)vgrid(n); }
+unsigned vpcg_update_blocks(int64_t n) { return (unsigned)ugrid(n); }
 void vpcg_update_fin_nb(hipStream_t st, unsigned nblocks, const Red& red, const int* gate, bool zpend) {
   k_fin1<<<1, BS, 0, st>>>(red, nblocks, zpend ? FIN_RN2_ZPEND : FIN_RN2, 0, gate);
 }
