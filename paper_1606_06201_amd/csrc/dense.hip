@@ -105,31 +105,34 @@ __global__ __launch_bounds__(DTT) void k_dense_init(double* __restrict__ A, int 
   }
 }
 
-// L_kk = chol(A_kk) and X_kk = L_kk^-1, right-looking, one barrier per step;
-// X_kk goes to X, its transpose to W's diagonal tile (A_kk is symmetric there).
-// Lane r of wave w keeps entries 16w..16w+15 of row r of the tile and of column r
-// of X (the forward substitution L x = e_r) in registers.  Step j: the wave that
-// holds column j takes the pivot from lane j, forms L_rj (lane r) and x_j = y_j /
-// L_jj, and puts both in LDS; then every wave updates its part of the row
-// (a_rc -= L_rj L_cj, c > j) and of the column of X (y_t -= L_tj x_j, t > j) from
-// broadcast reads of L_.j.  A pivot that is not positive sets the breakdown flag
-// and continues with 1.
+// L_kk = chol(A_kk) and X_kk = L_kk^-1, right-looking in four panels of 16
+// columns; X_kk goes to X, its transpose to W's diagonal tile (A_kk is symmetric
+// there).  Lane r of wave w keeps entries 16w..16w+15 of row r of the tile and of
+// column r of X (the forward substitution L x = e_r) in registers.  Panel W: the
+// wave that holds it takes its 16 steps alone, with no barrier: step j takes the
+// pivot from lane j, forms L_rj (lane r) and x_j = y_j / L_jj, and updates the
+// panel's later columns (a_rc -= L_rj L_cj, y_c -= L_cj x_j) with L_cj read from
+// lane c; then it puts the panel's L and x in LDS and, after one barrier, every
+// later wave applies the 16 steps to its columns from broadcast reads.  Each
+// entry sees the same fused multiply-adds in the same order as with one barrier
+// per step.  A pivot that is not positive sets the breakdown flag and continues
+// with 1.
 __device__ inline double lane_value(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
 
-constexpr int DW = DT / 4;   // tile columns per wave of k_dense_diag
+constexpr int DW = DT / 4;   // tile columns per wave of the diagonal factor
 
 template <int W>
-__device__ inline void diag_steps(double (&row)[DW], double (&y)[DW], double (*Lc)[DT + 2], double (*Xc)[DT + 2],
+__device__ inline void diag_panel(double (&row)[DW], double (&y)[DW], double (*Lc)[DT + 2], double (*Xc)[DT + 2],
                                   bool& bad) {
   const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (w == W) {                             // this wave holds the panel: its 16 steps
 #pragma unroll
-  for (int jj = 0; jj < DW; ++jj) {
-    const int j = W * DW + jj;
-    if (w == W) {                           // this wave holds column j
+    for (int jj = 0; jj < DW; ++jj) {
+      const int j = W * DW + jj;
       double d = lane_value(row[jj], j);
       if (!(d > 0.0) || !isfinite(d)) {
         bad = true;
@@ -139,16 +142,31 @@ __device__ inline void diag_steps(double (&row)[DW], double (&y)[DW], double (*L
       inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
       inv = fma(0.5 * inv, fma(-d * inv, inv, 1.0), inv);
       const double sd = d * inv;
-      Lc[j][r] = r > j ? row[jj] * inv : (r == j ? sd : 0.0);
-      Xc[j][r] = y[jj] * inv;
-      y[jj] *= inv;
+      const double lr = r > j ? row[jj] * inv : (r == j ? sd : 0.0);
+      const double xj = y[jj] * inv;
+      row[jj] = lr;                                          // column j of L
+      y[jj] = xj;
+#pragma unroll
+      for (int c = jj + 1; c < DW; ++c) {
+        const double l = lane_value(lr, W * DW + c);         // L_cj
+        row[c] = fma(-lr, l, row[c]);
+        y[c] = fma(-l, xj, y[c]);
+      }
     }
-    __syncthreads();
-    if (w >= W) {
+#pragma unroll
+    for (int jj = 0; jj < DW; ++jj) {
+      Lc[W * DW + jj][r] = row[jj];
+      Xc[W * DW + jj][r] = y[jj];
+    }
+  }
+  __syncthreads();
+  if (w > W) {
+#pragma unroll
+    for (int jj = 0; jj < DW; ++jj) {
+      const int j = W * DW + jj;
       const double lr = Lc[j][r], xj = Xc[j][r];
 #pragma unroll
       for (int c = 0; c < DW; ++c) {
-        if (W * DW + c <= j && w == W) continue;   // columns already done (compile-time for w == W)
         const double l = Lc[j][w * DW + c];
         row[c] = fma(-lr, l, row[c]);
         y[c] = fma(-l, xj, y[c]);
@@ -173,10 +191,10 @@ __device__ __attribute__((always_inline)) inline void diag_factor(DiagRows* Lc, 
   }
   __syncthreads();
   bool bad = false;
-  diag_steps<0>(row, y, Lc, Xc, bad);
-  diag_steps<1>(row, y, Lc, Xc, bad);
-  diag_steps<2>(row, y, Lc, Xc, bad);
-  diag_steps<3>(row, y, Lc, Xc, bad);
+  diag_panel<0>(row, y, Lc, Xc, bad);
+  diag_panel<1>(row, y, Lc, Xc, bad);
+  diag_panel<2>(row, y, Lc, Xc, bad);
+  diag_panel<3>(row, y, Lc, Xc, bad);
   if (bad && r == 0) red.flags[F_BAD] = 1;
   double* x = X + dense_tile_off(k, k);
   double* xt = W + dense_tile_off(k, k);
