@@ -200,6 +200,33 @@ def test_pcg_folded_steps_are_exact(env, fp32, monkeypatch):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2]) and np.array_equal(a[4], b[4])
 
 
+@pytest.mark.parametrize("nj32,nj64,nj_dir", [("1", "1", "1"), ("2", "4", "2"), ("8", "8", "3")])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_register_block_widths_match_oracle(nj32, nj64, nj_dir, fp32, monkeypatch):
+    # Nodes per thread of the register-blocked level passes (FP32 / FP64) and of the
+    # PCG direction kernel, on every level (several tiles and ragged tails at each
+    # width): V-cycle and PCG as the oracle's.
+    nel, levels = (96, 48), 4
+    g, K0, x = _kproblem(nel)
+    H = mg.kstiffness_hierarchy(g, x, K0, levels)
+    r = np.random.default_rng(6).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    for k, v in (("IPMG_TILED_MIN_NODES", "0"), ("IPMG_NJ32", nj32), ("IPMG_NJ64", nj64), ("IPMG_NJ_DIR", nj_dir)):
+        monkeypatch.setenv(k, v)
+    s = _solver(nel, levels, fp32=fp32)
+    for k in ("IPMG_TILED_MIN_NODES", "IPMG_NJ32", "IPMG_NJ64", "IPMG_NJ_DIR"):
+        monkeypatch.delenv(k)
+    s.set_density(T(x))
+    s.mg_setup()
+    z = N(s.vcycle(T(r)))
+    assert relerr(fem.to_free(g, z), mg.vcycle(H, fem.to_free(g, r))) < (2e-4 if fp32 else 1e-11)
+    f = fem.load_vector(g, tip_load(nel))
+    u, info = s.pcg(T(f), rtol=1e-8)
+    assert info["true_relres"] <= 1e-8
+    ref = opcg.mg_pcg(H, fem.to_free(g, f), rtol=1e-8)
+    assert abs(info["iters"] - ref.iters) <= (2 if fp32 else 1), (info["iters"], ref.iters)
+
+
 def test_invalid_arguments_raise():
     import torch
     from paper_1606_06201_amd import IPMGError, Solver
