@@ -409,7 +409,16 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   return cur;
 }
 
-void* vcycle(Ctx& c, int op, const int* gate) { return vcycle_level(c, op, c.L - 1, gate, nullptr); }
+// Work a previous call left pending when it stopped on an error is dropped.
+static void clear_pending(Ctx& c) {
+  c.rn2_fin_blocks = 0;
+  c.down_from_t = nullptr;
+}
+
+void* vcycle(Ctx& c, int op, const int* gate) {
+  clear_pending(c);
+  return vcycle_level(c, op, c.L - 1, gate, nullptr);
+}
 
 void vcycle64(Ctx& c, int op, const double* r, double* z) {
   IPMG_REQUIRE(c.hier_op == op, IPMG_E_STATE, "multigrid hierarchy not set up for this operator");
@@ -474,6 +483,7 @@ static void pcg_restart_direction(Ctx& c, int op, int64_t n) {
 }
 
 int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info) {
+  clear_pending(c);
   IPMG_REQUIRE(rtol > 0.0 && maxit >= 0, IPMG_E_INVALID, "rtol > 0 and maxit >= 0 required");
   IPMG_REQUIRE(c.have_x, IPMG_E_STATE, "set the densities first");
   double setup_ms = 0.0;
