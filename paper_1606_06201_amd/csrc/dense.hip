@@ -1,7 +1,8 @@
 // Dense solve on the coarsest level (Algorithm MG, Sec. 5.1, exact solve with A_1):
 // FP64 Cholesky factor A = L L', the inverse X = L^-1 and A^-1 = X' X, computed
 // on DT x DT tiles of the packed lower block triangle (the layout is declared
-// beside dense_tiles), and the product z = A^-1 r applied once per V-cycle.
+// beside dense_tiles), and the product z = A^-1 r applied once per V-cycle (the
+// FP32 V-cycle reads A^-1 rounded to FP32, written by the product kernel).
 //
 // One sweep over the block columns k does the factorization and the triangular
 // inverse together, two launches per k:
