@@ -212,7 +212,11 @@ __global__ __launch_bounds__(DTT) void k_dense_diag(double* __restrict__ W, doub
   DiagRows* Lc = reinterpret_cast<DiagRows*>(smemA);
   DiagRows* Xc = reinterpret_cast<DiagRows*>(smemB);
   const double* a = W + dense_tile_off(k, k);
-  for (int t = threadIdx.x; t < DT * DT; t += DTT) Lc[t / DT][t % DT] = a[t];
+#pragma unroll   // all sixteen loads in flight (a rolled loop waited for each)
+  for (int u = 0; u < DT * DT / DTT; ++u) {
+    const int t = threadIdx.x + u * DTT;
+    Lc[t / DT][t % DT] = a[t];
+  }
   __syncthreads();
   diag_factor(Lc, Xc, W, X, k, red);
 }
