@@ -119,6 +119,8 @@ struct Ctx {
   void* xT = nullptr;          // V-cycle copy (aliases x64 in FP64 mode)
   double* h64 = nullptr;       // Z rank-one factors h_e (ND * m)
   void* hT = nullptr;
+  void* hsbuf = nullptr;       // per-element h_e'v_e (m values, FP64 or FP32) for the 3D Z passes
+  bool elem_hv = true;         // form h_e'v_e per element before each 3D Z pass
   double* bZ64 = nullptr;      // border of Z on the finest grid (n_slots)
   double cZ = 0.0;             // corner of Z
   bool have_x = false;

@@ -244,12 +244,22 @@ struct OpFineZ {
   const T* x;
   const T* h;
   int64_t m;
+  const T* hs = nullptr;   // h_e'v_e per element, formed beforehand by k_elem_hv (same sum)
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
+    rows_keep(e, a, ve, T(1), acc);
+  }
+  // keep = 0: an element outside the grid that the gather maps to element 0 (its
+  // ve is zero, but hs[0] is element 0's value, so that term is scaled away).
+  __device__ inline void rows_keep(int64_t e, int a, const T* ve, T keep, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
     T hv = 0;
+    if (hs) {
+      hv = hs[e] * keep;
+    } else {
 #pragma unroll
-    for (int col = 0; col < ND; ++col) hv += h[col * m + e] * ve[col];
+      for (int col = 0; col < ND; ++col) hv += h[col * m + e] * ve[col];
+    }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int r = a * DIM + c;
@@ -683,7 +693,8 @@ __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, in
 #pragma unroll
         for (int c = 0; c < 3; ++c) ve[b * 3 + c] = v[3 * qn + c];
       }
-      op.rows(e, ei, ej, ek, a, ve, acc);
+      if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) op.rows_keep(e, a, ve, ok ? T(1) : T(0), acc);
+      else op.rows(e, ei, ej, ek, a, ve, acc);
     }
     if constexpr (DIAG) {
       T dt[3] = {T(0), T(0), T(0)};

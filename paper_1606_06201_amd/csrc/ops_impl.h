@@ -71,6 +71,31 @@ __device__ inline void gather_elem(const double* __restrict__ v, const Dims& d, 
   }
 }
 
+// s_e = h_e' v_e for every element, summed as OpFineZ::rows sums it, so that the
+// node passes of the augmented operator read one value per element instead of
+// all of h_e (each element is visited by all of its nodes).
+template <int DIM, typename T>
+__global__ __launch_bounds__(BS) void k_elem_hv(Dims d, const T* __restrict__ h, const T* __restrict__ v,
+                                                T* __restrict__ s) {
+  constexpr int NN = Geo<DIM>::NN;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= d.m) return;
+  int ei, ej, ek;
+  elem_coords<DIM>(d, e, ei, ej, ek);
+  T ve[NN * DIM];
+#pragma unroll
+  for (int b = 0; b < NN; ++b) {
+    const int i = ei + loc_x(b), j = ej + loc_y(b), k = DIM == 3 ? ek + loc_z(b) : 0;
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) ve[b * DIM + c] = (i == 0) ? T(0) : v[q * DIM + c];
+  }
+  T hv = 0;
+#pragma unroll
+  for (int col = 0; col < NN * DIM; ++col) hv += h[col * d.m + e] * ve[col];
+  s[e] = hv;
+}
+
 // g_e = scale * w_e' K0 u_e  (B(u)' w scaled).
 template <int DIM>
 __global__ __launch_bounds__(BS) void k_elem_sens(Dims d, const double* __restrict__ w, const double* __restrict__ u,
@@ -520,6 +545,20 @@ struct OpsImpl : Ops {
 #undef IPMG_LEVEL_CASE
   }
 
+  // The finest-level augmented operator for a pass over v (null: the pass reads
+  // no v).  In 3D, h_e'v_e is formed per element first (k_elem_hv) and the pass
+  // reads it, instead of every node of an element summing all of h_e again.
+  template <typename T>
+  OpFineZ<DIM, T> fine_z(Ctx& c, const T* h, const T* v) {
+    const Dims& d = c.fine();
+    OpFineZ<DIM, T> o{(const T*)(sizeof(T) == 8 ? (const void*)c.x64 : c.xT), h, d.m};
+    if (DIM == 3 && c.elem_hv && v) {
+      k_elem_hv<DIM, T><<<lin_grid(d.m), BS, 0, c.stream>>>(d, h, v, (T*)c.hsbuf);
+      o.hs = (const T*)c.hsbuf;
+    }
+    return o;
+  }
+
   template <typename T>
   void level_t(Ctx& c, int lev, int op, int mode, const void* v, const void* r, void* out, const double* omg,
                int sidx, int sidx_in, const int* gate, const double* dot64) {
@@ -530,8 +569,8 @@ struct OpsImpl : Ops {
         launch_level<T>(c, d, OpFineK<DIM, T>{(const T*)c.xT, d.m}, mode, (const T*)v, (const T*)r, (T*)out, omg,
                         aug, sidx, sidx_in, gate, dot64);
       else
-        launch_level<T>(c, d, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, mode, (const T*)v, (const T*)r,
-                        (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
+        launch_level<T>(c, d, fine_z<T>(c, (const T*)c.hT, mode != M_JACOBI0 ? (const T*)v : nullptr), mode,
+                        (const T*)v, (const T*)r, (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else if (DIM == 2 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x) {
       launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, mode, (const T*)v, (const T*)r,
                       (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
@@ -577,8 +616,10 @@ struct OpsImpl : Ops {
     IPMG_REQUIRE(!zs, IPMG_E_STATE, "solution update folded into an untiled direction kernel");
     if constexpr (DIM == 3) {
       k_pdir3<TY><<<lin_grid(d.nslots), BS, 0, c.stream>>>(d, y, pold, p, c.red, first, gate);
+      Op o = op;
+      if constexpr (std::is_same<Op, OpFineZ<DIM, double>>::value) o = fine_z<double>(c, c.h64, p);   // h_e'p_e
       ProfScope ps(c, PC_DIR_APPLY);
-      k_dir_apply3<TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
+      k_dir_apply3<TY, Op><<<g, BS, 0, c.stream>>>(o, d, y, pold, p, q, aug, c.red, first, gate);
     } else {
       ProfScope ps(c, PC_DIR_APPLY);
       k_dir_apply<DIM, TY, Op><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate);
@@ -610,7 +651,7 @@ struct OpsImpl : Ops {
       launch_level<double>(c, d, OpFineK<DIM, double>{c.x64, d.m}, M_APPLY, v, nullptr, y, nullptr,
                            Aug<double>{nullptr, 0.0, d.nslots}, 0, -1, gate);
     } else {
-      launch_level<double>(c, d, OpFineZ<DIM, double>{c.x64, c.h64, d.m}, M_APPLY, v, nullptr, y, nullptr,
+      launch_level<double>(c, d, fine_z<double>(c, c.h64, v), M_APPLY, v, nullptr, y, nullptr,
                            Aug<double>{c.bZ64, c.cZ, d.nslots}, 0, -1, gate);
     }
   }

@@ -58,6 +58,7 @@ static void ensure_z_buffers(Ctx& c) {
   dalloc(c.h64, sizeof(double) * c.nd * m);
   if (c.fp32) dalloc(c.hT, sizeof(float) * c.nd * m);
   else c.hT = c.h64;
+  dalloc(c.hsbuf, sizeof(double) * m);   // h_e'v_e of the operator pass in flight
   dalloc(c.bZ64, sizeof(double) * n1);
   if (c.fp32) dalloc(c.lev[c.L - 1].bZ, sizeof(float) * n1);
   else c.lev[c.L - 1].bZ = c.bZ64;
@@ -122,6 +123,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_FOLD_SOLUTION")) c.fold_solution = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_RN2")) c.fold_rn2_fin = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_RESTRICT")) c.fold_restrict = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_ELEM_HV")) c.elem_hv = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -227,7 +229,7 @@ void ctx_free(Ctx& c) {
   c.xT = nullptr;
   if (c.hT != (void*)c.h64) dfree(c.hT);
   c.hT = nullptr;
-  dfree(c.x64); dfree(c.h64); dfree(c.bZ64);
+  dfree(c.x64); dfree(c.h64); dfree(c.bZ64); dfree(c.hsbuf);
   dfree(c.pr); dfree(c.pp); dfree(c.pq); dfree(c.pt); dfree(c.pb); dfree(c.pu); dfree(c.pp2);
   dfree(c.dA); dfree(c.dLi); dfree(c.dAi); dfree(c.dAif); dfree(c.dpart); dfree(c.omega_dev);
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
