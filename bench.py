@@ -177,6 +177,8 @@ def bench_secondary(args, w, dev):
                 gst, log = s.ip_run(f, params)
                 info = {"newton": log["newton"], "barrier_updates": log["barrier_updates"],
                         "pcg_iters": int(sum(log["pcg_iters"])), "status": log["status"],
+                        "short_solves": log["short_solves"],
+                        "max_pcg_iters": int(max(log["pcg_iters"])),
                         "compliance": float(torch.dot(f, gst["u"]))}
             else:
                 x = torch.from_numpy(inputs.density_for(args.workload)).to(dev).requires_grad_(True)

@@ -78,7 +78,14 @@ typedef struct {
   double true_relres;  /* ||A u - b|| / ||b|| recomputed at exit                  */
   double setup_ms;     /* hierarchy setup time for this system (0 if reused)      */
   double solve_ms;     /* PCG wall time                                           */
+  double bu;           /* b'u of the returned u (the compliance f'u when b = f)   */
 } ipmg_pcg_info;
+
+typedef struct {
+  double lambda;       /* multiplier of the last bisection trial                  */
+  double volume;       /* sum of the new densities                                */
+  int trials;          /* bisection trials                                        */
+} ipmg_oc_info;
 
 /* Interior-point state (Sec. 3.1): caller-owned device arrays plus host scalars. */
 typedef struct {
@@ -102,6 +109,11 @@ typedef struct {
                          Newton test; 1: max(s, r) <= tau_ip (eq. (crit:ip))       */
   double kkt_tol, tau_ip;
   int max_newton;     /* safety cap on Newton steps                               */
+  double accept_rtol; /* a Newton solve stopped by pcg_maxit is taken as an inexact
+                         direction only if its true relative residual is at most
+                         this (1e-2: the paper's own inexact stopping rule, eq.
+                         (cgstop)); otherwise, and after any breakdown, the step
+                         fails and leaves the state unchanged                      */
 } ipmg_ip_params;
 
 typedef struct {
@@ -111,12 +123,17 @@ typedef struct {
   double volume_res;  /* sum x - V after the step                                  */
   double compliance;  /* f'u after the step                                        */
   int pcg_iters;      /* PCG iterations of the Newton system                       */
-  int pcg_status;     /* IPMG_OK, or IPMG_E_NOT_CONVERGED / IPMG_E_BREAKDOWN when the
-                         solve stopped early: the step then used the last PCG
-                         iterate as an inexact Newton direction                     */
+  int pcg_status;     /* IPMG_OK, or IPMG_E_NOT_CONVERGED when the solve stopped at
+                         pcg_maxit within accept_rtol (the step then used the last
+                         iterate as an inexact Newton direction), or the status of
+                         a failed solve (the step then returns it)                  */
   int barrier_updated;/* 1 if s, r were multiplied by sigma after this step        */
   int converged;      /* 1 if the stop rule holds                                  */
   double setup_ms, solve_ms;
+  double pcg_true_relres; /* true relative residual of the Newton solve          */
+  int pcg_retries;    /* 1 if the solve broke down and was continued from its last
+                         iterate after the damping of every level was estimated
+                         again (four times the power steps, product 1.2)           */
 } ipmg_ip_info;
 
 /* Create a context: grid, element matrix, level hierarchy storage and scratch.
@@ -156,7 +173,8 @@ int ipmg_mg_setup(ipmg_ctx* ctx, int op);
 
 /* Damping weight and spectral-radius estimate of the Jacobi smoother on a level after
  * the last ipmg_mg_setup: omega_k = min(omega, 1.6 / rho_k), rho_k the Rayleigh
- * quotient of D_k^-1 A_k after 12 power iterations from the vector (-1)^(i+j+k)(1+c)
+ * quotient of D_k^-1 A_k after 12 power iterations (30 for the augmented system Z)
+ * from the vector (-1)^(i+j+k)(1+c)
  * (damped Jacobi diverges once omega * rho >= 2; Sec. 5.1 leaves the smoother open).
  * omega, rho: [host] outputs (rho = 0 on the coarsest level, which is solved directly). */
 int ipmg_level_damping(ipmg_ctx* ctx, int level, double* omega, double* rho);
@@ -198,10 +216,34 @@ int ipmg_ip_prepare(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm,
 /* One Newton step (Sec. 3.1 steps 1-4): prepare, MG-PCG on Z, recovery of d_x,
  * d_phi, d_psi, step length (Sec. 3.3), update, Newton test and barrier update
  * (Sec. 3.2, 3.4), stop rule.  Updates st in place.  info: [host] may be NULL.
- * A Newton solve that stops early does not fail the step (see pcg_status).
- * Returns IPMG_OK, IPMG_E_STALLED, IPMG_E_DOMAIN (non-finite iterate) or an error. */
+ * A Newton solve that breaks down is continued once from its last iterate with
+ * the damping estimated again (pcg_retries).  A Newton solve stopped by pcg_maxit
+ * with a true relative residual within
+ * accept_rtol gives an inexact direction (pcg_status IPMG_E_NOT_CONVERGED, the
+ * step proceeds).  Returns IPMG_OK; IPMG_E_BREAKDOWN or IPMG_E_NOT_CONVERGED when
+ * the Newton solve broke down or stopped above accept_rtol; IPMG_E_STALLED when
+ * the step length is below 1e-14 or the direction is not finite; IPMG_E_DOMAIN
+ * (non-finite iterate) or another error.  On every status but IPMG_OK and
+ * IPMG_E_DOMAIN the state is left unchanged. */
 int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg_ip_state* st,
                  ipmg_ip_info* info);
+
+/* One density update of the Optimality Conditions methods (Sec. 4, Algorithms OC,
+ * DOC, AOC): with the element energies E_e = u_e'K0u_e of the displacements u
+ * (solved at the densities x),
+ *   x_new_e = min(x_e E_e^q / lambda, xbar),
+ * lambda from the bisection of Algorithm OC: bracket [0, lam_hi] (1e4 in the paper),
+ * while it is wider than tau (1e-11) its midpoint is tried and the lower end is
+ * raised when sum x_new > V, the upper end lowered otherwise; x_new is formed from
+ * the fixed x at every trial and the last trial gives the result.  q = 1: OC;
+ * q < 1: DOC (damping exponent, 1/2 in the paper).  blend (nullable): the AOC mean,
+ * x_new = (blend + update) / 2.  The bisection runs on the device, OC_LEVELS
+ * (5) levels of trials per pass, in the order of sequential bisection.
+ * u: [device] n_slots; x, x_new, blend: [device] m (x_new may alias blend, not x);
+ * info: [host] nullable.  Errors: IPMG_E_INVALID (V, xbar, q, lam_hi, tau not
+ * positive and finite, or tau >= lam_hi). */
+int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, double xbar, double q,
+                   double lam_hi, double tau, const double* blend, double* x_new, ipmg_oc_info* info);
 
 /* Kernel timing for roofline measurements.  Between begin and end, the launch of
  * the main kernel of every selected class (bit k of class_mask selects class k) is

@@ -21,6 +21,12 @@ fifth block row; the d_x recovery (nwtr2Za) uses d_u, d_lambda where the
 residuals are printed.  The dense full-system solve in the tests checks all
 of this mechanically.
 
+Newton-system solves (Sec. 6, stopping rule): a solve that reaches pcg_rtol
+gives the direction; one stopped by the iteration limit is taken as an inexact
+direction only if its true relative residual is within accept_rtol (1e-2, the
+paper's own inexact stopping rule, eq. (cgstop)); a breakdown, or a larger
+residual, ends the run with status "solve_failed".
+
 Step length (Sec. 3.3): fraction 0.9 of the distance to the bounds 0 < x < xbar,
 alpha <= 1; by default the same rule keeps phi, psi > 0 (the text asks for
 strict feasibility of all of (KKT6); flag `step_all_blocks`).
@@ -49,7 +55,8 @@ from . import fem, mg, pcg as pcg_mod
 class IPParams:
     def __init__(self, sigma=0.2, tau_nwt=0.1, pcg_rtol=1e-8, pcg_maxit=1000,
                  frac=0.9, stop="kkt", kkt_tol=1e-6, tau_ip=1e-8, max_newton=300,
-                 step_all_blocks=True, solver="mg", levels=4, omega=0.6, nu1=2, nu2=2):
+                 step_all_blocks=True, solver="mg", levels=4, omega=0.6, nu1=2, nu2=2,
+                 accept_rtol=1e-2, cg_tol_factor=1.0):
         self.__dict__.update(locals())
         del self.__dict__["self"]
 
@@ -187,9 +194,15 @@ def step_length(st, dx, dphi, dpsi, xbar, frac=0.9, all_blocks=True):
     return a
 
 
+class NewtonSolveError(RuntimeError):
+    """A Newton system whose PCG solve broke down, or stopped at the iteration
+    limit with a true relative residual above the acceptance bound."""
+
+
 class IPLog:
     def __init__(self):
         self.newton = 0
+        self.short_solves = 0      # Newton solves accepted short of pcg_rtol
         self.barrier_updates = 0
         self.pcg_iters = []
         self.alpha = []
@@ -200,26 +213,54 @@ class IPLog:
 
 
 def solve_linear(Z, rhs, params, grid, augmented, x0=None):
-    """MG-PCG (or a sparse direct solve)."""
+    """MG-PCG (or a sparse direct solve); returns (solution, iterations, status,
+    true relative residual), status "ok", "maxit" or "breakdown"."""
     if params.solver == "direct":
-        return spla.spsolve(Z.tocsc(), rhs), 0
+        return spla.spsolve(Z.tocsc(), rhs), 0, "ok", 0.0
     H = mg.Hierarchy(grid, Z, params.levels, augmented=augmented, omega=params.omega)
     res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, None,
                          params.nu1, params.nu2)
-    return res.z, res.iters
+    iters = res.iters
+    if res.status == "breakdown":
+        # the V-cycle was not positive definite (the estimate of rho came out too
+        # low): damping estimated again, more steps and a smaller product, and the
+        # solve continued from its last iterate
+        H.damping(mg.RETRY_POWER_FACTOR * mg.POWER_STEPS_Z, mg.SAFE_PRODUCT_RETRY)
+        res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, res.z, params.nu1, params.nu2)
+        iters += res.iters
+    return res.z, iters, res.status, res.true_relres
 
 
 def initial_state(prob, params):
     m = prob.grid.m
     x = np.full(m, prob.V / m)
-    u, it = solve_linear(prob.K(x), prob.f, params, prob.grid, False)
+    u, it, status, _ = solve_linear(prob.K(x), prob.f, params, prob.grid, False)
+    if status != "ok":
+        raise NewtonSolveError(f"initial equilibrium solve: {status}")
     st = IPState(u, 1.0, x, np.ones(m), np.ones(m), 1.0, 1.0)
     return st, it
 
 
-def newton_step(prob, st, params):
+def accept_solve(status, true_relres, params):
+    """Acceptance of a Newton-system solve as the search direction (Sec. 6, stopping
+    rule): a solve that reached pcg_rtol; or one stopped by the iteration limit whose
+    true relative residual is within accept_rtol, an inexact Newton direction (the
+    paper stops every Newton solve at a relative residual of 1e-2, eq. (cgstop)).
+    A breakdown of the recurrence is never accepted.  Returns True for a solve
+    accepted short of pcg_rtol."""
+    if status == "ok":
+        return False
+    if status == "maxit" and true_relres <= params.accept_rtol:
+        return True
+    raise NewtonSolveError(f"Newton system solve: {status}, true relative residual {true_relres:.3e}")
+
+
+def newton_step(prob, st, params, log=None):
     Z, rhs, parts = prob.z_system(st)
-    sol, iters = solve_linear(Z, rhs, params, prob.grid, True)
+    sol, iters, status, true_rel = solve_linear(Z, rhs, params, prob.grid, True)
+    short = accept_solve(status, true_rel, params)
+    if log is not None:
+        log.short_solves += int(short)
     du, dlam = sol[:-1], float(sol[-1])
     dx, dphi, dpsi = prob.recover(st, du, dlam, parts)
     alpha = step_length(st, dx, dphi, dpsi, prob.xbar, params.frac, params.step_all_blocks)
@@ -229,14 +270,22 @@ def newton_step(prob, st, params):
 
 
 def run(prob, params, state=None, log=None, callback=None):
-    """Interior-point loop of Sec. 3.1; returns (state, log)."""
+    """Interior-point loop of Sec. 3.1; returns (state, log).  With
+    params.cg_tol_factor < 1 the PCG tolerance is multiplied by it after every
+    barrier update (the "CG tol decreasing" variant of Sec. 8.1, factor 0.5)."""
+    import copy
+    params = copy.copy(params)
     log = log or IPLog()
     if state is None:
         state, it = initial_state(prob, params)
         log.pcg_iters.append(it)
     st = state
     while log.newton < params.max_newton:
-        st, alpha, iters = newton_step(prob, st, params)
+        try:
+            st, alpha, iters = newton_step(prob, st, params, log)
+        except NewtonSolveError:
+            log.status = "solve_failed"
+            return st, log
         log.newton += 1
         log.pcg_iters.append(iters)
         log.alpha.append(alpha)
@@ -256,6 +305,8 @@ def run(prob, params, state=None, log=None, callback=None):
             st.s *= params.sigma
             st.r *= params.sigma
             log.barrier_updates += 1
+            if params.cg_tol_factor != 1.0:       # "CG tol decreasing" (Sec. 8.1)
+                params.pcg_rtol *= params.cg_tol_factor
             if params.stop == "barrier" and max(st.s, st.r) <= params.tau_ip:
                 log.status = "converged"
                 return st, log

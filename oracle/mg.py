@@ -76,6 +76,9 @@ def prolongation_free(fine, coarse):
 SAFE_PRODUCT = 1.6
 POWER_STEPS = 12
 POWER_STEPS_Z = 30
+# after a breakdown of a solve: four times the power steps and the product 1.2
+RETRY_POWER_FACTOR = 4
+SAFE_PRODUCT_RETRY = 1.2
 
 
 def power_start(grid, augmented):
@@ -128,11 +131,17 @@ class Hierarchy:
         self.chol = sla.cho_factor(A[0].toarray(), lower=True)
         self.omega = [omega] * levels
         self.rho = [None] * levels
+        self.omega0 = omega
         if safeguard:
-            for k in range(1, levels):
-                self.rho[k] = jacobi_radius(A[k], self.diag[k], power_start(grids[k], augmented),
-                                            POWER_STEPS_Z if augmented else POWER_STEPS)
-                self.omega[k] = min(omega, SAFE_PRODUCT / self.rho[k])
+            self.damping(POWER_STEPS_Z if augmented else POWER_STEPS, SAFE_PRODUCT)
+
+    def damping(self, steps, product):
+        """omega_k = min(omega, product / rho_k) on every non-coarsest level, rho_k
+        estimated with `steps` power iterations."""
+        for k in range(1, self.L):
+            self.rho[k] = jacobi_radius(self.A[k], self.diag[k], power_start(self.grids[k], self.augmented),
+                                        steps)
+            self.omega[k] = min(self.omega0, product / self.rho[k])
 
 
 def jacobi(A, d, b, z, omega, sweeps):
@@ -165,30 +174,6 @@ def vcycle_matrix(H, nu1=2, nu2=2):
     """Dense matrix of the V-cycle operator (tiny grids only)."""
     n = H.A[-1].shape[0]
     return np.stack([vcycle(H, e, nu1, nu2) for e in np.eye(n)], axis=1)
-
-
-def vcycle_f32(H, b, nu1=2, nu2=2):
-    """Same V-cycle with smoothing and transfers rounded to float32 and the
-    coarsest solve kept in float64; used only to predict mixed-precision
-    iteration counts, not part of the FP64 contract."""
-    A32 = [a.astype(np.float32) for a in H.A]
-    d32 = [d.astype(np.float32) for d in H.diag]
-    P32 = [None] + [p.astype(np.float32) for p in H.P[1:]]
-
-    def rec(k, r):
-        if k == 0:
-            return sla.cho_solve(H.chol, r.astype(np.float64)).astype(np.float32)
-        z = np.zeros_like(r)
-        w = np.float32(H.omega[k])
-        for _ in range(nu1):
-            z = z + w * (r - A32[k] @ z) / d32[k]
-        v = rec(k - 1, (P32[k].T @ (r - A32[k] @ z)).astype(np.float32))
-        z = z + P32[k] @ v
-        for _ in range(nu2):
-            z = z + w * (r - A32[k] @ z) / d32[k]
-        return z
-
-    return rec(H.L - 1, np.asarray(b, dtype=np.float32)).astype(np.float64)
 
 
 def kstiffness_hierarchy(grid, x, K0, levels, omega=0.6):

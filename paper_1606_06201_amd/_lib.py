@@ -18,7 +18,12 @@ class Desc(C.Structure):
 
 class PCGInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("status", C.c_int), ("relres", C.c_double),
-                ("true_relres", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("true_relres", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("bu", C.c_double)]
+
+
+class OCInfo(C.Structure):
+    _fields_ = [("lam", C.c_double), ("volume", C.c_double), ("trials", C.c_int)]
 
 
 class IPState(C.Structure):
@@ -30,14 +35,15 @@ class IPParams(C.Structure):
     _fields_ = [("V", C.c_double), ("xbar", C.c_double), ("sigma", C.c_double), ("tau_nwt", C.c_double),
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int), ("frac", C.c_double),
                 ("step_all_blocks", C.c_int), ("stop_rule", C.c_int), ("kkt_tol", C.c_double),
-                ("tau_ip", C.c_double), ("max_newton", C.c_int)]
+                ("tau_ip", C.c_double), ("max_newton", C.c_int), ("accept_rtol", C.c_double)]
 
 
 class IPInfo(C.Structure):
     _fields_ = [("alpha", C.c_double), ("nwt", C.c_double), ("gap", C.c_double), ("volume_res", C.c_double),
                 ("compliance", C.c_double), ("pcg_iters", C.c_int), ("pcg_status", C.c_int),
                 ("barrier_updated", C.c_int), ("converged", C.c_int), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("pcg_true_relres", C.c_double),
+                ("pcg_retries", C.c_int)]
 
 
 SIGNATURES = {
@@ -58,6 +64,8 @@ SIGNATURES = {
     "ipmg_apply_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ipmg_pcg": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                            C.POINTER(PCGInfo)]),
+    "ipmg_oc_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(OCInfo)]),
     "ipmg_element_sens": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "ipmg_ip_init": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.POINTER(IPState),
                                C.POINTER(PCGInfo)]),

@@ -1,5 +1,6 @@
 // C ABI entry points (include/ipmg.h).  Every call catches internal errors and
 // turns them into status codes with a per-context message.
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -188,6 +189,17 @@ int ipmg_pcg(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int
   });
 }
 
+int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, double xbar, double q,
+                   double lam_hi, double tau, const double* blend, double* x_new, ipmg_oc_info* info) {
+  if (!u || !x || !x_new || x_new == x) return IPMG_E_INVALID;
+  auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+  if (!pos(V) || !pos(xbar) || !pos(q) || !pos(lam_hi) || !pos(tau) || !(tau < lam_hi)) return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) {
+    ipmg::oc_update(c, u, x, V, xbar, q, lam_hi, tau, blend, x_new, info);
+    return IPMG_OK;
+  });
+}
+
 int ipmg_element_sens(ipmg_ctx* ctx, const double* w, const double* u, double scale, double* g) {
   if (!w || !u || !g) return IPMG_E_INVALID;
   return guard(ctx, [&](Ctx& c) {
@@ -236,7 +248,7 @@ int ipmg_profile_end(ipmg_ctx* ctx, double* durations_ms, int* classes, int capa
 static int check_ip(const ipmg_ip_params* p, const ipmg_ip_state* st) {
   if (!p || !st || !st->u || !st->x || !st->phi || !st->psi) return IPMG_E_INVALID;
   if (!(p->sigma > 0.0 && p->sigma < 1.0) || !(p->frac > 0.0 && p->frac < 1.0) || !(p->pcg_rtol > 0.0) ||
-      p->pcg_maxit < 1 || !(p->xbar > 0.0))
+      p->pcg_maxit < 1 || !(p->xbar > 0.0) || !(p->accept_rtol >= 0.0))
     return IPMG_E_INVALID;
   return IPMG_OK;
 }

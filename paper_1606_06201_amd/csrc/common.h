@@ -79,12 +79,19 @@ enum Scal {
   S_TMP3, S_TMP4, S_TMP5, S_TMP6, S_TMP7, S_MIN0, S_MIN1, S_MIN2, S_MIN3,
   S_QY,    // q'y of the current PCG step (q = A p, y the preconditioned residual)
   S_FLEX,  // 1: Polak-Ribiere ratio in PCG, 0: the ratio of Algorithm PCG
+  // bisection of the OC update: bracket, last trial, trial count, sum of x_new
+  S_OCLO, S_OCHI, S_OCLAM, S_OCSTEPS, S_OCSUM,
   S_COUNT = 32
 };
 // Indices into the int device flag array.
 // F_ZPEND: the solution update z += alpha p of the last PCG step is pending (it
 // is folded into the next step's direction kernel).
-enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_ZPEND, F_COUNT = 8 };
+// F_OCDONE: the bisection of the OC update has narrowed its bracket to tau.
+enum Flag { F_DONE = 0, F_ITERS, F_STATUS, F_BAD, F_ZPEND, F_OCDONE, F_COUNT = 8 };
+// Trial multipliers of one bisection pass: the midpoints of the next OC_LEVELS
+// levels of the bisection tree.
+constexpr int OC_LEVELS = 5;
+constexpr int OC_CAND = (1 << OC_LEVELS) - 1;
 // Reduction counters (one per concurrently pending reduction kind).
 enum { C_MAIN = 0, C_AUX, C_COUNT = 8 };
 

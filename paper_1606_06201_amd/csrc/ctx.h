@@ -65,6 +65,8 @@ struct Ops {
   virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate,
                         const double* beta64 = nullptr) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
+  // t_e = x_e (u_e'K0u_e)^q of the OC update (Sec. 4)
+  virtual void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) = 0;
   // Interior point kernels (FP64).
   virtual void ip_elements(Ctx& c, const double* u, const double* x, const double* phi, const double* psi,
                            double lam, double s, double r, double xbar) = 0;
@@ -164,6 +166,11 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 
+  // OC update: t_e = x_e E_e^q (m) and the trial multipliers of a bisection pass
+  double* oc_t = nullptr;
+  double* oc_cand = nullptr;
+
+
   // kernel timing (ipmg_profile_*): HIP event pairs around every launch of the
   // selected classes; prof_tag is the class of the next level pass
   unsigned prof_mask = 0;
@@ -233,5 +240,7 @@ void read_scalars(Ctx& c);
 int ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_pcg_info* info);
 void ip_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, const ipmg_ip_state& st);
 int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_ip_info* info);
+void oc_update(Ctx& c, const double* u, const double* x, double V, double xbar, double q, double lam_hi,
+               double tau, const double* blend, double* x_new, ipmg_oc_info* info);
 
 }  // namespace ipmg

@@ -245,16 +245,18 @@ struct OpFineZ {
   const T* h;
   int64_t m;
   const T* hs = nullptr;   // h_e'v_e per element, formed beforehand by k_elem_hv (same sum)
+  // rows() sums h_e'v_e over ve itself: its callers may map an element outside the
+  // grid to element 0 with a zero ve, where hs[0] would not be zero.
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
-    rows_keep(e, a, ve, T(1), acc);
+    rows_keep(e, a, ve, T(1), acc, false);
   }
   // keep = 0: an element outside the grid that the gather maps to element 0 (its
   // ve is zero, but hs[0] is element 0's value, so that term is scaled away).
-  __device__ inline void rows_keep(int64_t e, int a, const T* ve, T keep, T* acc) const {
+  __device__ inline void rows_keep(int64_t e, int a, const T* ve, T keep, T* acc, bool use_hs = true) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
     T hv = 0;
-    if (hs) {
+    if (hs && use_hs) {
       hv = hs[e] * keep;
     } else {
 #pragma unroll

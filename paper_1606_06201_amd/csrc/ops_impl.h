@@ -119,6 +119,30 @@ __global__ __launch_bounds__(BS) void k_elem_sens(Dims d, const double* __restri
   g[e] = scale * s;
 }
 
+// OC update (Sec. 4): t_e = x_e * E_e^q with the element energy E_e = u_e'K0u_e
+// (negative rounding residue of a zero energy taken as 0).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_oc_energy(Dims d, const double* __restrict__ u, const double* __restrict__ x,
+                                                  double q, double* __restrict__ t) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= d.m) return;
+  int ei, ej, ek;
+  elem_coords<DIM>(d, e, ei, ej, ek);
+  double ue[ND];
+  gather_elem<DIM>(u, d, ei, ej, ek, ue);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < ND; ++r) {
+    double tr = 0.0;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) tr += cK0d[r * ND + c] * ue[c];
+    s += ue[r] * tr;
+  }
+  s = fmax(s, 0.0);
+  t[e] = x[e] * (q == 1.0 ? s : (q == 0.5 ? sqrt(s) : pow(s, q)));
+}
+
 // Start vector of the spectral-radius estimate: (-1)^(i+j+k) (1 + c), 0 on clamped
 // slots, 1 on lambda.
 template <int DIM, typename T>
@@ -289,6 +313,7 @@ __global__ __launch_bounds__(BS) void k_ip_recover(Dims d, const double* __restr
     const double ddphi = (-F4 - ph * ddx) / xe;
     const double ddpsi = (-F5 + ps * ddx) / xt;
     dx[e] = ddx; dphi[e] = ddphi; dpsi[e] = ddpsi;
+    if (!isfinite(ddx) || !isfinite(ddphi) || !isfinite(ddpsi) || !isfinite(dl)) red.flags[F_BAD] = 1;
     if (ddx < 0.0) mins[0] = -xe / ddx;
     if (ddx > 0.0) mins[1] = xt / ddx;
     if (ddphi < 0.0) mins[2] = -ph / ddphi;
@@ -926,6 +951,11 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     if (c.fp32) k_power_start<DIM, float><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (float*)v);
     else k_power_start<DIM, double><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (double*)v);
+  }
+
+  void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) override {
+    const Dims& d = c.fine();
+    k_oc_energy<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, x, q, t);
   }
 
   void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) override {

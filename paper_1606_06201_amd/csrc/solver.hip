@@ -40,6 +40,12 @@ constexpr int POWER_STEPS = 12;
 // which power iteration approaches slowly from below (12 steps: rho = 6.2 where
 // it is about 7.9, so omega * rho > 2 and PCG broke down).
 constexpr int POWER_STEPS_Z = 30;
+// After a breakdown of a Newton-system solve (the V-cycle was not positive definite:
+// omega * rho reached 2 because the estimate of rho came out too low), the damping
+// of every level is estimated again with four times the power steps and the
+// smaller product 1.2, and the solve continues from its last iterate.
+constexpr int RETRY_POWER_FACTOR = 4;
+constexpr double SAFE_PRODUCT_RETRY = 1.2;
 
 }  // namespace
 
@@ -200,6 +206,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   vfill(st, c.pp, 0.0, (int64_t)n1);    // the direction kernel reads p_old (times 0) on the first iteration
   vfill(st, c.pp2, 0.0, (int64_t)n1);
   dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
+  dalloc(c.oc_cand, sizeof(double) * OC_CAND);
   vfill_small(st, c.omega_dev, c.L, d.omega);
 
   // element matrix on the GPU, mirrored to the host and to constant memory
@@ -235,6 +242,7 @@ void ctx_free(Ctx& c) {
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
+  dfree(c.oc_t); dfree(c.oc_cand);
   if (c.hscal) (void)hipHostFree(c.hscal);
   if (c.hflags) (void)hipHostFree(c.hflags);
   c.hscal = nullptr; c.hflags = nullptr;
@@ -265,14 +273,13 @@ void set_density(Ctx& c, const double* x) {
 // Damping of level k from the spectral-radius estimate of D^-1 A (power iteration
 // with the normalisation folded into the next step, then the Rayleigh quotient);
 // everything stays on the device.
-static void jacobi_damping(Ctx& c, int k, int op) {
+static void jacobi_damping(Ctx& c, int k, int op, int steps, double product) {
   Level& l = c.lev[k];
   const int aug = op == IPMG_OP_Z;
   c.ops->power_start(c, k, aug, l.z);
   void* v = l.z;
   void* w = l.z2;
   int sin = -1, sout = S_TMP4;
-  const int steps = op == IPMG_OP_Z ? c.power_steps_z : c.power_steps;
   for (int it = 0; it < steps; ++it) {
     c.ops->level(c, k, op, M_POWER, v, nullptr, w, nullptr, sout, sin, nullptr);
     std::swap(v, w);
@@ -280,7 +287,7 @@ static void jacobi_damping(Ctx& c, int k, int op) {
     sout = sout == S_TMP4 ? S_TMP5 : S_TMP4;
   }
   c.ops->level(c, k, op, M_RAYLEIGH, v, nullptr, nullptr, nullptr, S_TMP6, -1, nullptr);
-  vset_omega(c.stream, c.red, c.omega_dev + k, c.omega_dev + c.L + k, S_TMP6, S_TMP7, c.desc.omega, SAFE_PRODUCT);
+  vset_omega(c.stream, c.red, c.omega_dev + k, c.omega_dev + c.L + k, S_TMP6, S_TMP7, c.desc.omega, product);
 }
 
 static void ensure_dense(Ctx& c) {
@@ -314,7 +321,8 @@ void mg_setup(Ctx& c, int op, double* ms) {
   }
   IPMG_HIP(hipGetLastError());
   ensure_dense(c);
-  for (int k = 1; k < L; ++k) jacobi_damping(c, k, op);
+  const int steps = op == IPMG_OP_Z ? c.power_steps_z : c.power_steps;
+  for (int k = 1; k < L; ++k) jacobi_damping(c, k, op, steps, SAFE_PRODUCT);
   const int n = c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);
   IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
   dense_init(c.stream, c.dA, n, 1);
@@ -565,9 +573,10 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
   }
   read_scalars(c);
   const double relres_rec = std::sqrt(c.hscal[S_RN2] / bn2);
-  // true residual at exit
+  // true residual and b'u at exit
   c.ops->fine_apply64(c, op, c.pu, c.pq, nullptr);
   vsub_norm(c.stream, c.pq, c.pb, c.pt, n, c.red, S_TMP2);
+  vdot(c.stream, c.pb, c.pu, n, c.red, S_TMP3, nullptr);
   IPMG_HIP(hipMemcpyAsync(u, c.pu, sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream));
   read_scalars(c);
   auto t1 = std::chrono::steady_clock::now();
@@ -576,9 +585,37 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
   inf.status = status;
   inf.relres = relres_rec;
   inf.true_relres = std::sqrt(c.hscal[S_TMP2] / bn2);
+  inf.bu = c.hscal[S_TMP3];
   inf.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (info) *info = inf;
   return status;
+}
+
+// ------------------------------------------------------------------ OC update --
+void oc_update(Ctx& c, const double* u, const double* x, double V, double xbar, double q, double lam_hi,
+               double tau, const double* blend, double* x_new, ipmg_oc_info* info) {
+  const Dims& d = c.fine();
+  if (!c.oc_t) dalloc(c.oc_t, sizeof(double) * (size_t)d.m);
+  c.ops->oc_energy(c, u, x, q, c.oc_t);
+  voc_init(c.stream, c.red, c.oc_cand, lam_hi);
+  // trials of sequential bisection in exact arithmetic, plus two for rounding;
+  // passes past the end are gated on the device
+  const int trials = (int)std::ceil(std::log2(lam_hi / tau)) + 2;
+  for (;;) {
+    for (int p = 0; p < (trials + OC_LEVELS - 1) / OC_LEVELS; ++p)
+      voc_pass(c.stream, c.oc_t, d.m, xbar, V, tau, c.oc_cand, c.red);
+    IPMG_HIP(hipGetLastError());
+    read_scalars(c);
+    if (c.hflags[F_OCDONE]) break;
+  }
+  voc_apply(c.stream, c.oc_t, d.m, xbar, blend, x_new, c.red);
+  IPMG_HIP(hipGetLastError());
+  read_scalars(c);
+  if (info) {
+    info->lambda = c.hscal[S_OCLAM];
+    info->volume = c.hscal[S_OCSUM];
+    info->trials = (int)c.hscal[S_OCSTEPS];
+  }
 }
 
 // ------------------------------------------------------------ interior point --
@@ -621,21 +658,41 @@ int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st,
   mg_setup(c, IPMG_OP_Z, &setup_ms);
   IPMG_HIP(hipMemsetAsync(c.ipD, 0, sizeof(double) * (d.nslots + 1), c.stream));
   ipmg_pcg_info pin{};
-  // A solve that stops early (iteration limit, or a breakdown of the recurrence)
-  // leaves its last iterate in ipD: an inexact Newton direction, which the step
-  // length and the following steps accept (Sec. 6, stopping rule).
-  const int ps = pcg(c, IPMG_OP_Z, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, &pin);
+  // A solve stopped by the iteration limit leaves its last iterate in ipD.  It is
+  // taken as an inexact Newton direction (Sec. 6, stopping rule) only when its
+  // true relative residual is within accept_rtol; a breakdown of the recurrence,
+  // or a residual above that bound, fails the step with the state unchanged.
+  int ps = pcg(c, IPMG_OP_Z, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, &pin);
+  if (ps == IPMG_E_BREAKDOWN) {
+    const int first = pin.iters;
+    const double first_ms = pin.solve_ms;
+    for (int k = 1; k < c.L; ++k)
+      jacobi_damping(c, k, IPMG_OP_Z, RETRY_POWER_FACTOR * c.power_steps_z, SAFE_PRODUCT_RETRY);
+    IPMG_HIP(hipGetLastError());
+    ps = pcg(c, IPMG_OP_Z, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, &pin);
+    pin.iters += first;
+    pin.solve_ms += first_ms;
+    inf.pcg_retries = 1;
+  }
   inf.pcg_iters = pin.iters;
   inf.pcg_status = ps;
+  inf.pcg_true_relres = pin.true_relres;
   inf.setup_ms = setup_ms;
   inf.solve_ms = pin.solve_ms;
+  if (ps != IPMG_OK && !(ps == IPMG_E_NOT_CONVERGED && pin.true_relres <= p.accept_rtol)) {
+    if (info) *info = inf;
+    return ps;
+  }
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
   c.ops->ip_recover(c, c.ipD, st.x, st.phi, st.psi, st.s, st.r, p.xbar, p.frac, p.step_all_blocks);
   double dlam = 0.0;
   IPMG_HIP(hipMemcpyAsync(&dlam, c.ipD + d.nslots, sizeof(double), hipMemcpyDeviceToHost, c.stream));
   read_scalars(c);
   const double alpha = c.hscal[S_ALPHA];
   inf.alpha = alpha;
-  if (!(alpha >= 1e-14) || !std::isfinite(dlam)) {
+  // a non-finite entry of (d_u, d_lambda, d_x, d_phi, d_psi) sets F_BAD: the
+  // comparisons of the step-length rule would skip it and leave alpha at 1
+  if (!(alpha >= 1e-14) || !std::isfinite(dlam) || c.hflags[F_BAD]) {
     if (info) *info = inf;
     return IPMG_E_STALLED;
   }

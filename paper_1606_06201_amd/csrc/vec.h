@@ -35,5 +35,16 @@ void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, c
 void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
                 double product);
 void vfill_small(hipStream_t st, double* w, int n, double value);   // n <= 64
+// Bisection of the OC update (Sec. 4): x_new(lambda) = min(t / lambda, xbar) with
+// sum x_new = V.  voc_init sets the bracket [0, lam_hi] and the first pass's trial
+// tree; each voc_pass evaluates the sums at the OC_CAND trials of the next
+// OC_LEVELS bisection levels and walks them in the order of sequential bisection
+// (gated once the bracket is narrower than tau); voc_apply writes x_new at the last
+// trial (blend: x_new = (blend + x_new) / 2) and its sum into scal[S_OCSUM].
+void voc_init(hipStream_t st, const Red& red, double* cand, double lam_hi);
+void voc_pass(hipStream_t st, const double* t, int64_t m, double xbar, double V, double tau, double* cand,
+              const Red& red);
+void voc_apply(hipStream_t st, const double* t, int64_t m, double xbar, const double* blend, double* x_new,
+               const Red& red);
 
 }  // namespace ipmg

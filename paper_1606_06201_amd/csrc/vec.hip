@@ -329,6 +329,149 @@ void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_va
   k_set_omega<<<1, 64, 0, st>>>(red, w, rho, s_vav, s_vdv, omega, product);
 }
 void vfill_small(hipStream_t st, double* w, int n, double value) { k_fill_value<<<1, 64, 0, st>>>(w, n, value); }
+
+// ------------------------------------------------------------ OC bisection --
+namespace {
+
+// Trials of one pass: node 0 is the midpoint of [lo, hi]; node i has children 2i+1
+// (the lower half of its interval) and 2i+2 (the upper half), each midpoint formed
+// as (a + b) / 2 from its interval, exactly as sequential bisection forms it on
+// that path.  One thread.
+__device__ void oc_tree(double lo, double hi, double* cand) {
+  double a[OC_CAND], b[OC_CAND];
+  a[0] = lo;
+  b[0] = hi;
+  for (int i = 0; i < OC_CAND; ++i) {
+    const double mid = (b[i] + a[i]) / 2.0;
+    cand[i] = mid;
+    if (2 * i + 2 < OC_CAND) {
+      a[2 * i + 1] = a[i]; b[2 * i + 1] = mid;
+      a[2 * i + 2] = mid;  b[2 * i + 2] = b[i];
+    }
+  }
+}
+
+__global__ void k_oc_init(Red red, double* cand, double lam_hi) {
+  if (threadIdx.x != 0) return;
+  red.scal[S_OCLO] = 0.0;
+  red.scal[S_OCHI] = lam_hi;
+  red.scal[S_OCLAM] = 0.0;
+  red.scal[S_OCSTEPS] = 0.0;
+  red.flags[F_OCDONE] = 0;
+  oc_tree(0.0, lam_hi, cand);
+}
+
+// sum_e min(t_e / lambda_j, xbar) for every trial j of the pass.
+__global__ __launch_bounds__(BS) void k_oc_sums(const double* __restrict__ t, int64_t m, double xbar,
+                                                const double* __restrict__ cand, Red red) {
+  if (red.flags[F_OCDONE]) return;
+  double lam[OC_CAND], acc[OC_CAND];
+#pragma unroll
+  for (int j = 0; j < OC_CAND; ++j) {
+    lam[j] = cand[j];
+    acc[j] = 0.0;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < m; e += (int64_t)gridDim.x * BS) {
+    const double te = t[e];
+#pragma unroll
+    for (int j = 0; j < OC_CAND; ++j) acc[j] += fmin(te / lam[j], xbar);
+  }
+  // block sums, stored trial-major: partials[j * gridDim.x + block]
+  __shared__ double sh[OC_CAND][BS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < OC_CAND; ++j) {
+    const double w = wave_sum(acc[j]);
+    if (lane == 0) sh[j][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < OC_CAND) {
+    double v = sh[threadIdx.x][0];
+    for (int w = 1; w < BS / 64; ++w) v += sh[threadIdx.x][w];
+    red.partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// Walk the pass's trials in sequential order: while hi - lo > tau, take the node's
+// midpoint, raise lo when its sum exceeds V (go to the upper half), else lower hi.
+__global__ __launch_bounds__(BS) void k_oc_walk(Red red, unsigned nblocks, double V, double tau, double* cand) {
+  if (red.flags[F_OCDONE]) return;
+  // totals of every trial over the blocks of k_oc_sums, in a fixed order
+  __shared__ double sh[OC_CAND][BS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = 0; j < OC_CAND; ++j) {
+    double a = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += BS) a += red.partials[(size_t)j * nblocks + b];
+    a = wave_sum(a);
+    if (lane == 0) sh[j][wid] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[OC_CAND];
+  for (int j = 0; j < OC_CAND; ++j) {
+    double v = sh[j][0];
+    for (int w = 1; w < BS / 64; ++w) v += sh[j][w];
+    tot[j] = v;
+  }
+  double lo = red.scal[S_OCLO], hi = red.scal[S_OCHI], lam = red.scal[S_OCLAM], steps = red.scal[S_OCSTEPS];
+  int node = 0;
+  bool done = false;
+  for (int lvl = 0; lvl < OC_LEVELS; ++lvl) {
+    if (!(hi - lo > tau)) { done = true; break; }
+    lam = cand[node];
+    steps += 1.0;
+    if (tot[node] > V) {
+      lo = lam;
+      node = 2 * node + 2;
+    } else {
+      hi = lam;
+      node = 2 * node + 1;
+    }
+  }
+  if (!(hi - lo > tau)) done = true;
+  red.scal[S_OCLO] = lo;
+  red.scal[S_OCHI] = hi;
+  red.scal[S_OCLAM] = lam;
+  red.scal[S_OCSTEPS] = steps;
+  if (done) red.flags[F_OCDONE] = 1;
+  else oc_tree(lo, hi, cand);
+}
+
+__global__ __launch_bounds__(BS) void k_oc_apply(const double* __restrict__ t, int64_t m, double xbar,
+                                                 const double* __restrict__ blend, double* __restrict__ xn, Red red) {
+  const double lam = red.scal[S_OCLAM];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < m; e += (int64_t)gridDim.x * BS) {
+    double v = fmin(t[e] / lam, xbar);
+    if (blend) v = 0.5 * (blend[e] + v);
+    xn[e] = v;
+    s += v;
+  }
+  const double a[1] = {s};
+  block_partials<1>(a, red);
+}
+
+__global__ __launch_bounds__(BS) void k_oc_apply_fin(Red red, unsigned nblocks) {
+  double tot[1];
+  sum_partials<1>(red, nblocks, tot);
+  if (threadIdx.x == 0) red.scal[S_OCSUM] = tot[0];
+}
+
+}  // namespace
+
+void voc_init(hipStream_t st, const Red& red, double* cand, double lam_hi) {
+  k_oc_init<<<1, 64, 0, st>>>(red, cand, lam_hi);
+}
+void voc_pass(hipStream_t st, const double* t, int64_t m, double xbar, double V, double tau, double* cand,
+              const Red& red) {
+  k_oc_sums<<<vgrid(m), BS, 0, st>>>(t, m, xbar, cand, red);
+  k_oc_walk<<<1, BS, 0, st>>>(red, vgrid(m), V, tau, cand);
+}
+void voc_apply(hipStream_t st, const double* t, int64_t m, double xbar, const double* blend, double* x_new,
+               const Red& red) {
+  k_oc_apply<<<vgrid(m), BS, 0, st>>>(t, m, xbar, blend, x_new, red);
+  k_oc_apply_fin<<<1, BS, 0, st>>>(red, vgrid(m));
+}
 template void vdot_beta<float>(hipStream_t, const double*, const float*, int64_t, const Red&, const int*);
 template void vdot_beta<double>(hipStream_t, const double*, const double*, int64_t, const Red&, const int*);
 template void vdot_store<float>(hipStream_t, const double*, const float*, int64_t, const Red&, int, const int*);

@@ -107,6 +107,25 @@ def point_load(nel):
     return out
 
 
+# The paper's own examples (Sec. 7): coarsest mesh 2x2 (Example 1, square) or 4x2
+# (Example 2, slender), left edge clamped, vertical load (-1/2, -1, -1/2) on the
+# right-edge middle node and its two neighbours on that edge, upper bound xbar = 2.
+# Problem "ab k" is the a x b coarsest mesh refined k - 1 times (k levels), which
+# reproduces the variable counts of Tables 1 and 3 (e.g. 423: 16 x 8 elements,
+# 288 free DOFs).  The volume is not stated in the paper; V = m (the start point
+# x = V/m = 1 is the middle of [0, xbar]).
+PAPER_COARSEST = {1: (2, 2), 2: (4, 2)}
+
+
+def paper_problem(example, k):
+    """(nel, levels, loads, V, xbar) of problem "<coarsest>k" of Example 1 or 2."""
+    cx, cy = PAPER_COARSEST[int(example)]
+    s = 2 ** (int(k) - 1)
+    nx, ny = cx * s, cy * s
+    loads = [((nx, ny // 2 - 1), 1, -0.5), ((nx, ny // 2), 1, -1.0), ((nx, ny // 2 + 1), 1, -0.5)]
+    return (nx, ny), int(k), loads, float(nx * ny), 2.0
+
+
 WORKLOADS = {
     "ip64x32": dict(nel=(64, 32), levels=4, kind="ip", vfrac=0.5, xbar=1.0),
     "grf1024x512": dict(nel=(1024, 512), levels=7, kind="solve", density="logistic", seed=1),

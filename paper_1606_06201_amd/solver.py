@@ -160,13 +160,68 @@ class Solver:
         rc = self._call(self.lib.ipmg_pcg, int(op), self._ptr(b, n, "b"), self._ptr(u, n, "u"),
                         float(rtol), int(maxit), C.byref(info), allow=allow)
         return u, dict(iters=info.iters, restarts=info.restarts, status=info.status, relres=info.relres,
-                       true_relres=info.true_relres, setup_ms=info.setup_ms, solve_ms=info.solve_ms, rc=rc)
+                       true_relres=info.true_relres, setup_ms=info.setup_ms, solve_ms=info.solve_ms, bu=info.bu,
+                       rc=rc)
 
     def element_sens(self, w, u, scale=1.0, out=None):
         out = self._empty(self.m) if out is None else out
         self._call(self.lib.ipmg_element_sens, self._ptr(w, self.n_slots, "w"), self._ptr(u, self.n_slots, "u"),
                    float(scale), self._ptr(out, self.m, "g"))
         return out
+
+    # ------------------------------------------------------------------- OC --
+    def oc_update(self, u, x, V, xbar, q=1.0, lam_hi=1e4, tau=1e-11, blend=None, out=None):
+        """One density update of Algorithm OC (q = 1) / DOC (q < 1), Sec. 4, with the
+        device bisection for lambda; blend: AOC mean (blend + update) / 2.
+        Returns (x_new, info dict)."""
+        out = self._empty(self.m) if out is None else out
+        info = L.OCInfo()
+        bl = None if blend is None else self._ptr(blend, self.m, "blend")
+        self._call(self.lib.ipmg_oc_update, self._ptr(u, self.n_slots, "u"), self._ptr(x, self.m, "x"),
+                   float(V), float(xbar), float(q), float(lam_hi), float(tau), bl, self._ptr(out, self.m, "x_new"),
+                   C.byref(info))
+        return out, dict(lam=info.lam, volume=info.volume, trials=info.trials)
+
+    def oc_run(self, f, x0, V, xbar, variant="oc", q=0.5, tau_oc=1e-5, cg_tol=1e-4, max_outer=10000,
+               lam_hi=1e4, tau_lam=1e-11, maxit=1000):
+        """Algorithm OC / DOC / AOC (Sec. 4) with the multigrid CG of Sec. 6.2: stop when
+        |f'u_k - f'u_{k-1}| <= tau_oc (eq. (OCstop)); the relative tolerance of the
+        solves starts at cg_tol and is multiplied by 0.1 whenever the compliance
+        increases.  AOC: x1 = OC(x), x2 = OC(x1), x = (x1 + x2)/2.  Returns (x, u, log);
+        log["feval"] counts the linear systems solved."""
+        qq = q if variant == "doc" else 1.0
+        x = x0.clone()
+        log = dict(outer=0, feval=0, pcg_iters=[], compliance=[], cg_tol=[], lam=[], status="max_outer")
+        tol = [float(cg_tol)]
+
+        def solve_at(y):
+            self.set_density(y)
+            u, inf = self.pcg(f, rtol=tol[0], maxit=maxit)
+            log["feval"] += 1
+            log["pcg_iters"].append(inf["iters"])
+            return u, inf["bu"]
+
+        u, c_prev = solve_at(x)
+        log["compliance"].append(c_prev)
+        while log["outer"] < max_outer:
+            if variant == "aoc":
+                x1, _ = self.oc_update(u, x, V, xbar, 1.0, lam_hi, tau_lam)
+                u1, _ = solve_at(x1)
+                x, oi = self.oc_update(u1, x1, V, xbar, 1.0, lam_hi, tau_lam, blend=x1, out=x)
+            else:
+                x, oi = self.oc_update(u, x, V, xbar, qq, lam_hi, tau_lam, out=torch.empty_like(x))
+            u, c = solve_at(x)
+            log["outer"] += 1
+            log["compliance"].append(c)
+            log["lam"].append(oi["lam"])
+            log["cg_tol"].append(tol[0])
+            if c > c_prev:
+                tol[0] *= 0.1
+            if abs(c - c_prev) <= tau_oc:
+                log["status"] = "converged"
+                break
+            c_prev = c
+        return x, u, log
 
     # ------------------------------------------------------------------ timing --
     KERNEL_CLASSES = {"fine_jacobi": 0, "dir_apply": 1, "fine_resid": 2, "pcg_update": 3, "sub_jacobi": 4,
@@ -199,14 +254,23 @@ class Solver:
     # ------------------------------------------------------------ interior point --
     @staticmethod
     def ip_params(V, xbar=1.0, sigma=0.2, tau_nwt=0.1, pcg_rtol=1e-8, pcg_maxit=1000, frac=0.9,
-                  step_all_blocks=True, stop="kkt", kkt_tol=1e-6, tau_ip=1e-8, max_newton=300):
+                  step_all_blocks=True, stop="kkt", kkt_tol=1e-6, tau_ip=1e-8, max_newton=300,
+                  accept_rtol=1e-2):
         p = L.IPParams()
         p.V, p.xbar, p.sigma, p.tau_nwt = float(V), float(xbar), float(sigma), float(tau_nwt)
         p.pcg_rtol, p.pcg_maxit, p.frac = float(pcg_rtol), int(pcg_maxit), float(frac)
         p.step_all_blocks = int(bool(step_all_blocks))
         p.stop_rule = {"kkt": 0, "barrier": 1}[stop]
         p.kkt_tol, p.tau_ip, p.max_newton = float(kkt_tol), float(tau_ip), int(max_newton)
+        p.accept_rtol = float(accept_rtol)
         return p
+
+    @classmethod
+    def ip_params_paper(cls, V, xbar=2.0, cg_tol=1e-2, tau_ip=1e-8):
+        """The paper's own inexact settings (Sec. 3, Sec. 6.1, Sec. 7): every Newton
+        system solved to the relative residual 1e-2 (eq. (cgstop)), tau_NWT = 0.1,
+        sigma = 0.2, stop at max(s, r) <= tau_IP = 1e-8 (eq. (crit:ip)), xbar = 2."""
+        return cls.ip_params(V, xbar, pcg_rtol=cg_tol, stop="barrier", tau_ip=tau_ip, accept_rtol=cg_tol)
 
     def new_ip_state(self):
         return dict(u=self._zeros(self.n_slots), x=self._zeros(self.m), phi=self._zeros(self.m),
@@ -245,23 +309,39 @@ class Solver:
         s = self._state_struct(st)
         info = L.IPInfo()
         rc = self._call(self.lib.ipmg_ip_step, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
-                        C.byref(info), allow=(L.E_STALLED,))
+                        C.byref(info), allow=(L.E_STALLED, L.E_BREAKDOWN, L.E_NOT_CONVERGED))
         self._state_back(s, st)
         return dict(alpha=info.alpha, nwt=info.nwt, gap=info.gap, volume_res=info.volume_res,
                     compliance=info.compliance, pcg_iters=info.pcg_iters, pcg_status=info.pcg_status,
-                    barrier_updated=info.barrier_updated, converged=info.converged, setup_ms=info.setup_ms,
-                    solve_ms=info.solve_ms, rc=rc)
+                    pcg_true_relres=info.pcg_true_relres, pcg_retries=info.pcg_retries,
+                    barrier_updated=info.barrier_updated,
+                    converged=info.converged, setup_ms=info.setup_ms, solve_ms=info.solve_ms, rc=rc)
 
-    def ip_run(self, f, params, callback=None):
-        """Interior-point loop (Sec. 3.1): init, then Newton steps until the stop rule."""
+    def ip_run(self, f, params, callback=None, cg_tol_factor=1.0):
+        """Interior-point loop (Sec. 3.1): init, then Newton steps until the stop rule.
+        log["short_solves"] counts Newton systems whose solve stopped at pcg_maxit and
+        was taken as an inexact direction (true residual within accept_rtol); a solve
+        that broke down or stopped above that bound ends the run ("solve_failed").
+        cg_tol_factor < 1: the "CG tol decreasing" variant of Sec. 8.1, the PCG
+        tolerance multiplied by this factor after every barrier update (0.5 there)."""
+        params = L.IPParams.from_buffer_copy(params)
         st, init = self.ip_init(f, params)
-        log = dict(newton=0, barrier_updates=0, pcg_iters=[init["iters"]], steps=[], status="max_newton")
+        log = dict(newton=0, barrier_updates=0, pcg_iters=[init["iters"]], steps=[], status="max_newton",
+                   short_solves=0, retries=0)
         while log["newton"] < params.max_newton:
             inf = self.ip_step(f, params, st)
+            if inf["rc"] in (L.E_BREAKDOWN, L.E_NOT_CONVERGED):
+                log["steps"].append(inf)
+                log["status"] = "solve_failed"
+                break
             log["newton"] += 1
             log["pcg_iters"].append(inf["pcg_iters"])
             log["steps"].append(inf)
             log["barrier_updates"] += inf["barrier_updated"]
+            log["short_solves"] += int(inf["pcg_status"] != L.OK)
+            log["retries"] += inf["pcg_retries"]
+            if inf["barrier_updated"] and cg_tol_factor != 1.0:
+                params.pcg_rtol *= cg_tol_factor
             if callback:
                 callback(st, inf)
             if inf["rc"] == L.E_STALLED:

@@ -113,6 +113,12 @@ def test_ip_run_64x32_matches_oracle(fp32):
     params = s.ip_params(prob.V, prob.xbar, stop="kkt", kkt_tol=1e-6)
     gst, log = s.ip_run(T(prob.f_slots), params)
     assert log["status"] == "converged"
+    # the last Newton systems reach the 1000-step limit in both (taken as inexact
+    # directions within the 1e-2 acceptance bound); as many here as in the oracle
+    print(f"64x32 fp32={fp32}: short solves {log['short_solves']} (oracle {log_o.short_solves}), "
+          f"PCG {log['pcg_iters']} (oracle {log_o.pcg_iters})", flush=True)
+    assert abs(log["short_solves"] - log_o.short_solves) <= 1
+    assert all(st["pcg_true_relres"] <= 1e-2 for st in log["steps"])
     assert abs(log["newton"] - log_o.newton) <= 1
     assert abs(log["barrier_updates"] - log_o.barrier_updates) <= 1
     c = float(prob.f_slots @ N(gst["u"]))
