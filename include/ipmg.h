@@ -196,6 +196,26 @@ int ipmg_apply_Z(ipmg_ctx* ctx, const double* v, double* y);
 int ipmg_pcg(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int maxit,
              ipmg_pcg_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ipmg_pcg with its work
+ * vectors (seven of n_slots + 1 doubles) and its reduction scratch in a static
+ * device array of IPMG_NOALLOC_SCRATCH_BYTES that the library holds on each GPU
+ * it runs on until the process ends, instead of the context's buffers.  The call
+ * allocates nothing: it needs the hierarchy of op already built (ipmg_mg_setup,
+ * or an earlier solve of the same operator at the current data), else
+ * IPMG_E_STATE; a grid whose scratch (ipmg_pcg_noalloc_bytes) exceeds the array
+ * gives IPMG_E_INVALID (in 2D up to about 1.1M DOF slots, e.g. 1024 x 512
+ * elements).  Results equal those of ipmg_pcg bit for bit.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (two contexts on
+ * different streams or threads) race and must be serialised by the caller.
+ * Arguments, return values and the stream synchronisation as for ipmg_pcg. */
+#define IPMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ipmg_pcg_noalloc(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int maxit,
+                     ipmg_pcg_info* info);
+/* Bytes of the static scratch ipmg_pcg_noalloc needs for this context's grid (-1 for a
+ * null context). */
+int64_t ipmg_pcg_noalloc_bytes(const ipmg_ctx* ctx);
+
 /* Element sensitivities g_e = scale * w_e' K0 u_e (B(u)' w of Sec. 2 scaled; with
  * w = lambda, scale = -1 this is the adjoint gradient -lambda_e' K_e u_e).
  * w, u: [device] n_slots; g: [device] m. */

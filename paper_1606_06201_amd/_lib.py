@@ -64,6 +64,9 @@ SIGNATURES = {
     "ipmg_apply_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ipmg_pcg": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                            C.POINTER(PCGInfo)]),
+    "ipmg_pcg_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                   C.POINTER(PCGInfo)]),
+    "ipmg_pcg_noalloc_bytes": (C.c_int64, [C.c_void_p]),
     "ipmg_oc_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(OCInfo)]),
     "ipmg_element_sens": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),

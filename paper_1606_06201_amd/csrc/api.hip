@@ -189,6 +189,20 @@ int ipmg_pcg(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int
   });
 }
 
+int ipmg_pcg_noalloc(ipmg_ctx* ctx, int op, const double* b, double* u, double rtol, int maxit,
+                     ipmg_pcg_info* info) {
+  if (!b || !u || (op != IPMG_OP_K && op != IPMG_OP_Z)) return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) {
+    if (op == IPMG_OP_Z && !c.have_z) throw Error(IPMG_E_STATE, "prepare the Newton system first");
+    return ipmg::pcg_noalloc(c, op, b, u, rtol, maxit, info);
+  });
+}
+
+int64_t ipmg_pcg_noalloc_bytes(const ipmg_ctx* ctx) {
+  if (!ctx) return -1;
+  return (int64_t)ipmg::pcg_noalloc_bytes(ctx->c);
+}
+
 int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, double xbar, double q,
                    double lam_hi, double tau, const double* blend, double* x_new, ipmg_oc_info* info) {
   if (!u || !x || !x_new || x_new == x) return IPMG_E_INVALID;

@@ -170,6 +170,8 @@ struct Ctx {
   double* oc_t = nullptr;
   double* oc_cand = nullptr;
 
+  // this device's copy of the scratch array of the allocation-free PCG entry point
+  unsigned char* noalloc_scratch = nullptr;
 
   // kernel timing (ipmg_profile_*): HIP event pairs around every launch of the
   // selected classes; prof_tag is the class of the next level pass
@@ -235,6 +237,10 @@ void mg_setup(Ctx& c, int op, double* ms);
 void* vcycle(Ctx& c, int op, const int* gate);    // lev[L-1].r -> returned level buffer
 void vcycle64(Ctx& c, int op, const double* r, double* z);
 int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info);
+// pcg with its work vectors and reduction scratch in the library's static device
+// array (no allocation); needs the hierarchy of op set up.
+int pcg_noalloc(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info);
+size_t pcg_noalloc_bytes(const Ctx& c);
 void sync(Ctx& c);
 void read_scalars(Ctx& c);
 int ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_pcg_info* info);

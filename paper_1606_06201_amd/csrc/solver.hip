@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "ctx.h"
 #include "kernels.h"
@@ -46,6 +47,29 @@ constexpr int POWER_STEPS_Z = 30;
 // smaller product 1.2, and the solve continues from its last iterate.
 constexpr int RETRY_POWER_FACTOR = 4;
 constexpr double SAFE_PRODUCT_RETRY = 1.2;
+
+// Scratch of ipmg_pcg_noalloc: the PCG work vectors and the reduction arrays of a
+// solve, for callers that cannot allocate device memory.  Each GPU the library runs
+// on holds its own copy until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns for that device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[IPMG_NOALLOC_SCRATCH_BYTES];
+
+// Device address of this device's copy of `scratch`, looked up once per device with
+// that device current (the array's name is only a host-side stand-in).
+unsigned char* scratch_address() {
+  static std::mutex mu;
+  static unsigned char* addr[64] = {nullptr};
+  int dev = 0;
+  IPMG_HIP(hipGetDevice(&dev));
+  IPMG_REQUIRE(dev >= 0 && dev < 64, IPMG_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    IPMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = (unsigned char*)p;
+  }
+  return addr[dev];
+}
 
 }  // namespace
 
@@ -166,6 +190,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
     throw Error(IPMG_E_NOMEM, "pinned allocation failed");
   IPMG_HIP(hipEventCreate(&c.ev0));
   IPMG_HIP(hipEventCreate(&c.ev1));
+  c.noalloc_scratch = scratch_address();
 
   // level vectors
   const int nsym = c.nd * (c.nd + 1) / 2;
@@ -589,6 +614,67 @@ int pcg(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg
   inf.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (info) *info = inf;
   return status;
+}
+
+// Layout of the allocation-free PCG's scratch: seven vectors of n_slots + 1 doubles
+// (r, p, q, t, b, u, second p), then the reduction partials, the scalars, the flags
+// and the counters; every part starts on a 256-byte boundary.
+namespace {
+struct NoallocLayout {
+  size_t vec, partials, scal, flags, counter, total;
+};
+NoallocLayout noalloc_layout(const Ctx& c) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  NoallocLayout l;
+  l.vec = up(sizeof(double) * ((size_t)c.fine().nslots + 1));
+  l.partials = 7 * l.vec;
+  l.scal = l.partials + up(sizeof(double) * 8 * MAX_PARTIALS);
+  l.flags = l.scal + sizeof(double) * S_COUNT;
+  l.counter = l.flags + sizeof(int) * F_COUNT;
+  l.total = up(l.counter + sizeof(unsigned) * C_COUNT);
+  return l;
+}
+}  // namespace
+
+size_t pcg_noalloc_bytes(const Ctx& c) { return noalloc_layout(c).total; }
+
+int pcg_noalloc(Ctx& c, int op, const double* b, double* u, double rtol, int maxit, ipmg_pcg_info* info) {
+  IPMG_REQUIRE(c.have_x, IPMG_E_STATE, "set the densities first");
+  IPMG_REQUIRE(c.hier_op == op, IPMG_E_STATE,
+               "set up the multigrid hierarchy of this operator first (ipmg_mg_setup or a solve)");
+  const NoallocLayout l = noalloc_layout(c);
+  IPMG_REQUIRE(l.total <= (size_t)IPMG_NOALLOC_SCRATCH_BYTES, IPMG_E_INVALID,
+               "grid too large for the scratch of the allocation-free PCG");
+  IPMG_REQUIRE(c.noalloc_scratch, IPMG_E_STATE, "scratch address not set");
+  unsigned char* s = c.noalloc_scratch;
+  // the context's own buffers, restored however the call ends
+  struct Saved {
+    Ctx& c;
+    double *pr, *pp, *pq, *pt, *pb, *pu, *pp2;
+    Red red;
+    explicit Saved(Ctx& cc)
+        : c(cc), pr(cc.pr), pp(cc.pp), pq(cc.pq), pt(cc.pt), pb(cc.pb), pu(cc.pu), pp2(cc.pp2), red(cc.red) {}
+    ~Saved() {
+      c.pr = pr; c.pp = pp; c.pq = pq; c.pt = pt; c.pb = pb; c.pu = pu; c.pp2 = pp2;
+      c.red = red;
+    }
+  } saved(c);
+  double* v[7];
+  for (int k = 0; k < 7; ++k) v[k] = (double*)(s + k * l.vec);
+  c.pr = v[0]; c.pp = v[1]; c.pq = v[2]; c.pt = v[3]; c.pb = v[4]; c.pu = v[5]; c.pp2 = v[6];
+  c.red.partials = (double*)(s + l.partials);
+  c.red.scal = (double*)(s + l.scal);
+  c.red.flags = (int*)(s + l.flags);
+  c.red.counter = (unsigned*)(s + l.counter);
+  // The array keeps the last call's contents: the direction kernel reads p_old
+  // (times 0) on the first step, so both direction buffers start at zero, as do
+  // the scalars, flags and counters (cleared with fill kernels, not memset nodes).
+  const int64_t n1 = c.fine().nslots + 1;
+  vfill(c.stream, c.pp, 0.0, n1);
+  vfill(c.stream, c.pp2, 0.0, n1);
+  vfill(c.stream, c.red.scal, 0.0, (int64_t)((l.total - l.scal) / sizeof(double)));
+  IPMG_HIP(hipGetLastError());
+  return pcg(c, op, b, u, rtol, maxit, info);
 }
 
 // ------------------------------------------------------------------ OC update --

@@ -163,6 +163,22 @@ class Solver:
                        true_relres=info.true_relres, setup_ms=info.setup_ms, solve_ms=info.solve_ms, bu=info.bu,
                        rc=rc)
 
+    def pcg_noalloc(self, b, op=OP_K, u0=None, rtol=1e-8, maxit=1000, check=True):
+        """pcg through ipmg_pcg_noalloc: the library's static scratch array instead of
+        the context's work vectors (the hierarchy of op must be set up already)."""
+        n = self._n(op)
+        u = self._zeros(n) if u0 is None else u0.clone()
+        info = L.PCGInfo()
+        allow = () if check else (L.E_NOT_CONVERGED, L.E_BREAKDOWN)
+        rc = self._call(self.lib.ipmg_pcg_noalloc, int(op), self._ptr(b, n, "b"), self._ptr(u, n, "u"),
+                        float(rtol), int(maxit), C.byref(info), allow=allow)
+        return u, dict(iters=info.iters, restarts=info.restarts, status=info.status, relres=info.relres,
+                       true_relres=info.true_relres, setup_ms=info.setup_ms, solve_ms=info.solve_ms, bu=info.bu,
+                       rc=rc)
+
+    def pcg_noalloc_bytes(self):
+        return int(self.lib.ipmg_pcg_noalloc_bytes(self.h))
+
     def element_sens(self, w, u, scale=1.0, out=None):
         out = self._empty(self.m) if out is None else out
         self._call(self.lib.ipmg_element_sens, self._ptr(w, self.n_slots, "w"), self._ptr(u, self.n_slots, "u"),

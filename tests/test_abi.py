@@ -20,7 +20,7 @@ def declared():
 def test_header_declares_the_entry_points():
     names = declared()
     for must in ("ipmg_create", "ipmg_apply_K", "ipmg_vcycle", "ipmg_pcg", "ipmg_ip_step",
-                 "ipmg_element_sens"):
+                 "ipmg_element_sens", "ipmg_pcg_noalloc"):
         assert must in names
 
 
