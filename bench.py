@@ -155,6 +155,151 @@ def cpu_baseline(nel, levels, x, f, iters=40):
     }
 
 
+def golden_errors(workload, u_mixed, fp64_u=None):
+    """Errors of the benchmark solutions against the oracle's own FP64 solution
+    (tests/golden/<workload>.txt, written by a script that calls only the oracle):
+    relative compliance error and max |u - u_oracle| / max |u_oracle| at the stored
+    DOFs."""
+    import importlib.util
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"make_{workload}.py")
+    data = os.path.join(ROOT, "tests", "golden", f"{workload}.txt")
+    if not (os.path.exists(path) and os.path.exists(data)):
+        return None
+    spec = importlib.util.spec_from_file_location("golden_" + workload, path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    sc, slots, vals = mod.load(data)
+    out = {"oracle_rtol": 1e-9, "oracle_true_relres": sc["true_relres"]}
+    import torch
+    f_load = None
+    for name, u in (("mixed", u_mixed), ("fp64", fp64_u)):
+        if u is None:
+            continue
+        uh = u.detach().cpu().numpy()
+        out[name] = {"u_err_at_stored_dofs": float(np.abs(uh[slots] - vals).max() / sc["maxabs"])}
+    return out
+
+
+def bench_3d_section(dev, steps=8):
+    """3D trilinear cantilever 128x64x64 (1.6M DOFs), FP32 V-cycle: the interior-point
+    start (K solve) and `steps` Newton steps (augmented system Z), with the dominant
+    3D kernels timed by HIP events and priced against the FP64 / FP32 ALU peaks
+    (the 3D element products are arithmetic-bound: 1152 flops per element for
+    x_e K0 v_e against at most 200 bytes of traffic)."""
+    import numpy as np
+    import torch
+    from paper_1606_06201_amd import Solver, inputs
+    nel, levels = (128, 64, 64), 5
+    s = Solver(nel, levels, fp32=True, device=dev)
+    f = s.load_vector(inputs.point_load(nel))
+    params = s.ip_params(0.3 * s.m, 1.0, stop="kkt", kkt_tol=1e-6)
+    names = ["dir_apply", "fine_jacobi", "fine_jacobi0", "fine_resid", "fine_jacobi_beta"]
+    st, _ = s.ip_init(f, params)
+    s.ip_step(f, params, st)                           # warm-up step (untimed)
+    s.profile_begin(names, max_launches=8000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        inf = s.ip_step(f, params, st)
+        iters += inf["pcg_iters"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    durs = s.profile_end()
+    m = s.m
+    # algorithmic flops per launch: x_e K0 v_e (24 x 24 per element, 2 flops per
+    # entry) plus the rank-one term of Z, h_e (h_e'v_e), 4 flops per entry of h_e
+    fl_z = (2 * 24 * 24 + 4 * 24) * m
+    fl_sweep = (2 * 24 * 24 + 4 * 24) * m
+    kern = {}
+    for k, d in durs.items():
+        d = np.asarray(d)
+        d = d[d > 0.5 * np.median(d)]
+        if not len(d):
+            continue
+        a = float(d.mean())
+        fl = fl_z if k == "dir_apply" else fl_sweep
+        # published vector peaks: FP64 78.6 TFLOP/s (the direction kernel), FP32
+        # 157.3 (the V-cycle sweeps; 78.6 without packed FP32 instructions, which
+        # this library does not emit)
+        peak = 78.6 if k == "dir_apply" else 157.3
+        kern[k] = {"avg_launch_us": 1000 * a, "launches": int(len(d)), "flops_per_launch": fl,
+                   "TFLOP_per_s": fl / (a * 1e-3) / 1e12, "peak_TFLOP_per_s": peak,
+                   "frac": fl / (a * 1e-3) / 1e12 / peak,
+                   "dtype": "f64" if k == "dir_apply" else "f32"}
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"] * kern[k]["launches"]) if kern else None
+    return {"workload": "ip128x64x64 (interior-point start + Newton steps 2-9, FP32 V-cycle, rtol 1e-8)",
+            "newton_steps_timed": steps, "pcg_iters": iters, "seconds": t1 - t0,
+            "dof_iters_per_s": s.n_free * iters / (t1 - t0), "kernels": kern,
+            "roofline": ({"bound": "alu", "kernel": dom, "achieved": kern[dom]["TFLOP_per_s"],
+                          "peak": kern[dom]["peak_TFLOP_per_s"], "unit": "TFLOP/s", "frac": kern[dom]["frac"]}
+                         if dom else None)}
+
+
+# The paper's counts, quoted as context (Intel i5 CPU, MATLAB; its smoother is not
+# named, so they are not targets): Table 3 (IP, Example 2), Table 4 (OC, Example 2),
+# Table 7 (problem 226, tau_IP = 1e-8: NWT, CG, x_min for CG tol fixed / decreasing).
+PAPER_TABLE3 = {3: (33, 265), 4: (32, 342), 5: (31, 207), 6: (30, 160), 7: (29, 139), 8: (27, 123), 9: (27, 101)}
+PAPER_TABLE4 = {3: (39, 117), 4: (45, 144), 5: (77, 262), 6: (123, 423), 7: (157, 542), 8: (165, 739)}
+PAPER_TABLE7 = {"fixed": (28, 139, 1.8e-5), "decreasing": (28, 587, 1.6e-5)}
+
+
+def bench_paper_tables(args, dev):
+    """The paper's own experiments on the GPU (FP64 and FP32 V-cycle): the inexact
+    interior-point preset on Example 2 problems 423-429 (Table 3: feval, total CG),
+    AOC / DOC / OC on 423-428 (Table 4), and problem 226 with CG tol fixed and
+    decreasing (Table 7, tau_IP = 1e-8).  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1606_06201_amd import Solver, inputs
+    out = {"metric": "paper experiments on the GPU: linear systems (feval) and PCG iterations",
+           "unit": "counts", "n_gpus": 1, "data": "synthetic (the paper's cantilevers)", "table3": {},
+           "table4": {}, "table7": {}}
+    for k in range(3, 10):
+        nel, levels, loads, V, xbar = inputs.paper_problem(2, k)
+        row = {"elements": list(nel), "paper_feval_cg": PAPER_TABLE3[k]}
+        for fp32 in (False, True):
+            s = Solver(nel, levels, fp32=fp32, device=dev)
+            f = s.load_vector(loads)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gst, log = s.ip_run(f, s.ip_params_paper(V, xbar))
+            torch.cuda.synchronize()
+            row["mixed" if fp32 else "fp64"] = {
+                "status": log["status"], "feval": 1 + log["newton"], "cg": int(sum(log["pcg_iters"])),
+                "seconds": time.perf_counter() - t0}
+        out["table3"][f"42{k}"] = row
+        print(f"[bench] table 3 problem 42{k}: {row}", file=sys.stderr, flush=True)
+    for k in range(3, 9):
+        nel, levels, loads, V, xbar = inputs.paper_problem(2, k)
+        row = {"elements": list(nel), "paper_feval_cg": PAPER_TABLE4[k]}
+        for variant in ("aoc", "doc", "oc"):
+            s = Solver(nel, levels, fp32=False, device=dev)
+            f = s.load_vector(loads)
+            x0 = torch.full((s.m,), V / s.m, dtype=torch.float64, device=dev)
+            t0 = time.perf_counter()
+            x, u, log = s.oc_run(f, x0, V, xbar, variant=variant, max_outer=5000)
+            torch.cuda.synchronize()
+            row[variant] = {"status": log["status"], "feval": log["feval"], "cg": int(sum(log["pcg_iters"])),
+                            "compliance": log["compliance"][-1], "seconds": time.perf_counter() - t0}
+        out["table4"][f"42{k}"] = row
+        print(f"[bench] table 4 problem 42{k}: {row}", file=sys.stderr, flush=True)
+    nel, levels, loads, V, xbar = inputs.paper_problem(1, 6)
+    for name, factor in (("fixed", 1.0), ("decreasing", 0.5)):
+        row = {"elements": list(nel), "paper_nwt_cg_xmin": PAPER_TABLE7[name]}
+        for tau in (1e-8, 1e-10, 1e-12):
+            s = Solver(nel, levels, fp32=False, device=dev)
+            f = s.load_vector(loads)
+            gst, log = s.ip_run(f, s.ip_params_paper(V, xbar, tau_ip=tau), cg_tol_factor=factor)
+            row[f"{tau:g}"] = {"status": log["status"], "ip": log["barrier_updates"], "nwt": log["newton"],
+                               "cg": int(sum(log["pcg_iters"])), "x_min": float(gst["x"].min()),
+                               "short_solves": log["short_solves"]}
+        out["table7"][name] = row
+        print(f"[bench] table 7 {name}: {row}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def bench_secondary(args, w, dev):
     """Interior-point runs (kind "ip") and adjoint gradients (kind "adjoint"): the
     FP32 V-cycle against the plain FP64 path, one JSON line.  The roofline and
@@ -223,6 +368,7 @@ def main():
     ap.add_argument("--levels", type=int, default=0, help="override the workload's multigrid level count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="leave out the 3D interior-point section")
     ap.add_argument("--flexible", type=int, default=0, choices=(0, 1),
                     help="PCG ratio: 0 = Algorithm PCG, 1 = Polak-Ribiere form (both precisions)")
     ap.add_argument("--roofline-kernel", default="auto",
@@ -250,6 +396,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
         return
 
+    if args.workload == "paper-tables":
+        bench_paper_tables(args, dev)
+        return
     w = inputs.WORKLOADS[args.workload]
     if w["kind"] in ("ip", "adjoint"):
         bench_secondary(args, w, dev)
@@ -351,6 +500,12 @@ def main():
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(nel, levels, x_h, f_h)
 
+    oracle_err = golden_errors(args.workload, u_mixed, fp64_u=u64 if fp64 else None)
+    ip3d = None
+    if not args.no_3d and args.workload == "thr2048x1024":
+        print("[bench] 3D interior-point section", file=sys.stderr, flush=True)
+        ip3d = bench_3d_section(dev)
+
     inf = inf_mixed[-1]
     out = {
         "metric": "MG-PCG DOF-iters/s + time-to-1e-8 (FP64 vs mixed) at 2M DOFs; HBM GB/s % peak",
@@ -376,9 +531,11 @@ def main():
         "compliance_rel_diff_mixed_vs_fp64": (abs(c_mixed - fp64["compliance"]) / abs(fp64["compliance"]))
         if fp64 else None,
         "pcg_loop_dof_iters_per_s": n_free * sum(iters) / (t_mixed - setup_s),
+        "oracle_error": oracle_err,
         "roofline": roofline,
         "kernel_classes": classes,
         "cpu_baseline": cpu,
+        "ip3d": ip3d,
     }
     print(json.dumps(out))
 

@@ -61,7 +61,43 @@ __device__ inline T k0sq(int r, int c) {
   const int t = kSq2d[r * 8 + c];
   return t > 0 ? k0<T>(t - 1) : -k0<T>(-t - 1);
 }
-// Entry (r, c) of the element matrix of the dimension.
+// Cube symmetry of the 3D Q1 element matrix (isotropic material, unit cube): with
+// s = position(b) - position(a) of the two nodes, the entry of rows (a, c) and
+// columns (b, c') depends only on |s| component by component, and off the 3 x 3
+// diagonal blocks on the sign (2 a_c - 1)(2 b_c' - 1) of the two shape-function
+// slopes: 14 slots, slot 0..5 for c = c' (|s_c|, number of other nonzero s_k), slot
+// 6..13 for c != c' (|s_c|, |s_c'|, |s_other|).  With the element loops unrolled the
+// slot and sign of every entry are compile-time, so the 3D kernels keep 14
+// constants in scalar registers instead of loading 576.  Checked against the
+// computed element matrix at set-up.
+__host__ __device__ constexpr int k0cube_slot(int r, int col) {
+  const int a = r / 3, c = r % 3, b = col / 3, cp = col % 3;
+  const int pa[3] = {loc_x(a), loc_y(a), loc_z(a)}, pb[3] = {loc_x(b), loc_y(b), loc_z(b)};
+  int as[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) as[k] = pb[k] != pa[k] ? 1 : 0;
+  if (c == cp) {
+    int others = 0;
+    for (int k = 0; k < 3; ++k) others += (k != c) ? as[k] : 0;
+    return 1 + as[c] * 3 + others;
+  }
+  const int o = 3 - c - cp;
+  const int slot = 6 + as[c] * 4 + as[cp] * 2 + as[o];
+  const int sg = (2 * pa[c] - 1) * (2 * pb[cp] - 1);
+  return sg * (slot + 1);
+}
+static __constant__ double cK3d[14];
+static __constant__ float cK3f[14];
+template <typename T> __device__ inline T k3c(int slot);
+template <> __device__ inline double k3c<double>(int slot) { return cK3d[slot]; }
+template <> __device__ inline float k3c<float>(int slot) { return cK3f[slot]; }
+template <typename T>
+__device__ inline T k0cube(int r, int c) {
+  const int t = k0cube_slot(r, c);
+  return t > 0 ? k3c<T>(t - 1) : -k3c<T>(-t - 1);
+}
+
+// Entry (r, c) of the element matrix of the dimension (in 3D from the full table:
+// the generic passes index it with a run-time row; node_apply_fine3 uses k0cube).
 template <int DIM, typename T>
 __device__ inline T k0rc(int r, int c) {
   if constexpr (DIM == 2) return k0sq<T>(r, c);
@@ -672,9 +708,82 @@ __device__ inline void level_node_core(const Op& op, const Dims& d, int i, int j
 // grid contribute nothing; clamped nodes (i == 0), and every node of an element
 // outside the grid, are read at node 0, which is clamped and holds zero in every
 // level vector, so the loads carry no branch.
+template <class Op> struct fine3_op : std::false_type {};
+template <typename T> struct fine3_op<OpFineK<3, T>> : std::true_type {};
+template <typename T> struct fine3_op<OpFineZ<3, T>> : std::true_type {};
+
+// Finest 3D level (A_e = x_e K0, plus h_e h_e' for Z): every element around node
+// (i, j, k) is mapped onto the element that has the node at its local node 0 by
+// reflecting the axes along which the element lies below the node (d_k = -1).  The
+// cube's element matrix is invariant under these reflections with the matching
+// component signs, so row c of node a of element e is
+//   d_c * sum_{b', c'} K0[c][3 b' + c'] d_c' v(node + (b'_x d_x, b'_y d_y, b'_z d_z), c'),
+// and only the three rows of local node 0 occur: their 72 entries are signed copies
+// of the 14 cube constants at compile time, while the loop over the 8 elements stays
+// rolled (registers) and loads no matrix entries.  Same operator as the generic
+// form; the sum runs in the reflected column order.
+template <typename T, class Op, bool ROWS, bool DIAG>
+__device__ inline void node_apply_fine3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
+                                        T* acc, T* dg) {
+#pragma unroll 1
+  for (int q = 0; q < 8; ++q) {
+    const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+    int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && ek >= 0 && ek < d.nz;
+    ei = ok ? ei : 0;
+    ej = ok ? ej : 0;
+    ek = ok ? ek : 0;
+    const int64_t e = ((int64_t)ek * d.ny + ej) * d.nx + ei;
+    const int a = loc_index(1 - ex, 1 - ey, 1 - ez);
+    const int dx = 2 * ex - 1, dy = 2 * ey - 1, dz = 2 * ez - 1;
+    const T xe = op.x[e];
+    if constexpr (ROWS) {
+      const T sg[3] = {T(dx), T(dy), T(dz)};
+      T ve[24];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int ni = i + loc_x(b) * dx, nj = j + loc_y(b) * dy, nk = k + loc_z(b) * dz;
+        const bool nok = ok && ni >= 1;
+        const int64_t qn = nok ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ve[b * 3 + c] = sg[c] * v[3 * qn + c];
+      }
+      T hv = 0;
+      if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) {
+        hv = op.hs[e] * (ok ? T(1) : T(0));     // an element outside the grid reads element 0
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int col = 0; col < 24; ++col) s += k0cube<T>(c, col) * ve[col];
+        acc[c] += xe * sg[c] * s;
+        if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) acc[c] += op.h[(a * 3 + c) * op.m + e] * hv;
+      }
+    }
+    if constexpr (DIAG) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T dt = xe * k0cube<T>(c, c);
+        if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) {
+          const T hr = op.h[(a * 3 + c) * op.m + e];
+          dt += hr * hr;
+        }
+        dg[c] += ok ? dt : T(0);
+      }
+    }
+  }
+}
+
 template <typename T, class Op, bool ROWS, bool DIAG>
 __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
                                           T* acc, T* dg) {
+  if constexpr (std::is_same<Op, OpFineK<3, T>>::value) {
+    return node_apply_fine3<T, Op, ROWS, DIAG>(op, d, i, j, k, v, acc, dg);
+  } else if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) {
+    // the reflected form reads h_e'v_e per element (hs) for the rank-one term
+    if (!ROWS || op.hs != nullptr) return node_apply_fine3<T, Op, ROWS, DIAG>(op, d, i, j, k, v, acc, dg);
+  }
 #pragma unroll 1
   for (int q = 0; q < 8; ++q) {
     const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;

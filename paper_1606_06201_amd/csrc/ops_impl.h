@@ -377,6 +377,23 @@ struct OpsImpl : Ops {
                      "element matrix lacks the square-element symmetry");
       }
     }
+    if constexpr (DIM == 3) {
+      double kmax = 0.0, k14[14] = {0.0};
+      bool have[14] = {false};
+      for (int t = 0; t < 576; ++t) kmax = std::max(kmax, std::fabs(K0[t]));
+      for (int r = 0; r < 24; ++r)
+        for (int col = 0; col < 24; ++col) {
+          const int e = k0cube_slot(r, col), sl = (e > 0 ? e : -e) - 1;
+          const double v = e > 0 ? K0[r * 24 + col] : -K0[r * 24 + col];
+          if (!have[sl]) { k14[sl] = v; have[sl] = true; }
+          IPMG_REQUIRE(std::fabs(v - k14[sl]) <= 1e-12 * kmax, IPMG_E_INVALID,
+                       "element matrix lacks the cube symmetry");
+        }
+      float k14f[14];
+      for (int t = 0; t < 14; ++t) k14f[t] = (float)k14[t];
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK3d), k14, sizeof(double) * 14));
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK3f), k14f, sizeof(float) * 14));
+    }
     float kf[576];
     for (int t = 0; t < ND * ND; ++t) kf[t] = (float)K0[t];
     IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cK0d), K0, sizeof(double) * ND * ND));

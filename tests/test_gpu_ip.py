@@ -159,10 +159,12 @@ def test_adjoint_gradient_matches_oracle(fp32):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
-def test_z3d_element_hv_pass_is_exact(fp32, monkeypatch):
-    # 3D augmented operator: h_e'v_e formed per element before each pass (default)
-    # or by every node of the element inside the pass: the same sum, so Z v, the
-    # V-cycle on Z and a PCG solve on Z agree bit for bit.
+def test_z3d_element_hv_pass_matches_gather(fp32, monkeypatch):
+    # 3D augmented operator: h_e'v_e formed per element before each pass and the
+    # element rows taken in the reflected order of the cube symmetry (default), or
+    # the generic gather that sums h_e'v_e at every node with the stored K0 rows:
+    # the same operator summed in two orders, so Z v, the V-cycle on Z and a PCG
+    # solve on Z agree to rounding (against the oracle's assembled Z as well).
     from paper_1606_06201_amd import Solver
     nel, levels = (8, 4, 4), 2
     prob = _problem(nel)
@@ -183,8 +185,11 @@ def test_z3d_element_hv_pass_is_exact(fp32, monkeypatch):
         out[off] = (zv, zc, N(u), info["iters"])
     monkeypatch.delenv("IPMG_NO_ELEM_HV")
     a, b = out["0"], out["1"]
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    assert a[3] == b[3] and np.array_equal(a[2], b[2])
+    tol = 1e-5 if fp32 else 1e-12           # the V-cycle rounds in its own precision
+    assert relerr(a[0], b[0]) < 1e-14 and relerr(a[1], b[1]) < tol
+    # PCG to 1e-10: the FP32 V-cycles' different rounding moves the count a little
+    assert abs(a[3] - b[3]) <= (1 if not fp32 else max(2, 0.05 * b[3]))
+    assert relerr(a[2], b[2]) < 1e-8
     Z, zrhs, parts = prob.z_system(st)
     free = g.free_to_slot()
     ref = Z @ np.concatenate([v[:-1][free], v[-1:]])
@@ -215,3 +220,35 @@ def test_z_vcycle_alternative_paths_match_oracle(env, val, fp32, monkeypatch):
     zc = N(s.vcycle(T(v), op=1))
     zref = mg.vcycle(H, np.concatenate([v[:-1][free], v[-1:]]))
     assert relerr(np.concatenate([zc[free], zc[-1:]]), zref) < (2e-4 if fp32 else 1e-9)
+
+
+@pytest.fixture(scope="module")
+def oracle_ip3d():
+    from paper_1606_06201_amd import inputs
+    nel, levels = (16, 8, 8), 3
+    g = fem.Grid(nel)
+    prob = oip.Problem(g, fem.element_stiffness(3), fem.load_vector(g, inputs.point_load(nel)), 0.3 * g.m, 1.0)
+    st, log = oip.run(prob, oip.IPParams(stop="kkt", kkt_tol=1e-6, solver="mg", levels=levels))
+    return prob, nel, levels, st, log
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ip_run_3d_16x8x8_matches_oracle(oracle_ip3d, fp32):
+    # A 3D interior-point run (trilinear hexahedra, V = 0.3 m, 3 levels) against the
+    # oracle's own run of the same algorithm: Newton and barrier counts, the
+    # systems accepted at the iteration limit, and the optimal compliance.
+    from paper_1606_06201_amd import Solver
+    prob, nel, levels, st_o, log_o = oracle_ip3d
+    s = Solver(nel, levels, fp32=fp32)
+    gst, log = s.ip_run(T(prob.f_slots), s.ip_params(prob.V, prob.xbar, stop="kkt", kkt_tol=1e-6))
+    c, c_o = float(prob.f_slots @ N(gst["u"])), float(prob.f @ st_o.u)
+    print(f"3D 16x8x8 fp32={fp32}: Newton {log['newton']} (oracle {log_o.newton}), barrier {log['barrier_updates']} "
+          f"({log_o.barrier_updates}), short {log['short_solves']} ({log_o.short_solves}), retries {log['retries']}, "
+          f"compliance rel diff {abs(c - c_o) / c_o:.2e}, PCG {log['pcg_iters']} oracle {log_o.pcg_iters}", flush=True)
+    assert log["status"] == log_o.status == "converged"
+    assert abs(log["newton"] - log_o.newton) <= 1
+    assert abs(log["barrier_updates"] - log_o.barrier_updates) <= 1
+    assert abs(log["short_solves"] - log_o.short_solves) <= 1
+    assert abs(c - c_o) <= 1e-6 * c_o
+    x = N(gst["x"])
+    assert abs(x.sum() - prob.V) <= 1e-6 * prob.V and x.min() > 0 and x.max() < prob.xbar
