@@ -194,6 +194,8 @@ def _golden_thr():
     import importlib.util
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_thr2048x1024.py")
+    if not os.path.exists(os.path.join(os.path.dirname(path), "thr2048x1024.txt")):
+        pytest.skip("tests/golden/thr2048x1024.txt not written yet (make_thr2048x1024.py)")
     spec = importlib.util.spec_from_file_location("make_thr2048x1024", path)
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
