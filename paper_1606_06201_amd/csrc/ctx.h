@@ -166,6 +166,12 @@ struct Ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 
+  // 3D stored levels: element products y_e = E_e v of the level pass in flight
+  // (24 values per element of the largest stored level, V-cycle precision)
+  void* ye = nullptr;
+  bool elem_apply3 = true;
+  int64_t elem_apply3_min = 8192;   // ... on levels with at least this many elements
+
   // OC update: t_e = x_e E_e^q (m) and the trial multipliers of a bisection pass
   double* oc_t = nullptr;
   double* oc_cand = nullptr;

@@ -325,10 +325,15 @@ struct OpFineZ {
 
 // Coarse level: general symmetric element matrices from the Galerkin products,
 // packed upper-triangular, stored E[sym(r,c) * m + e].
+// ye (3D): the element products y_e = E_e v_e of the pass's vector, formed
+// beforehand by k_elem_apply3 (component-major, ye[r * m + e]); the node passes
+// then read three values per element instead of its 72 matrix entries and 24
+// nodal values.
 template <int DIM, typename T>
 struct OpCoarse {
   const T* E;
   int64_t m;
+  const T* ye = nullptr;
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
 #pragma unroll
@@ -775,9 +780,63 @@ __device__ inline void node_apply_fine3(const Op& op, const Dims& d, int i, int 
   }
 }
 
+// Element products of a stored 3D level, y_e = E_e v_e.  A block of 8 waves takes
+// 64 consecutive elements; wave a forms the three rows of local node a for all of
+// them (every matrix load coalesced over 64 elements, 72 entries and the 24 nodal
+// values per thread).  Nodal values of clamped nodes are read at node 0 (zero).
+constexpr int EA3_THREADS = 512;
+template <typename T>
+__global__ __launch_bounds__(EA3_THREADS) void k_elem_apply3(Dims d, const T* __restrict__ E,
+                                                             const T* __restrict__ v, T* __restrict__ ye,
+                                                             const int* gate) {
+  if (gate && *gate) return;
+  const int64_t e = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int a = threadIdx.x >> 6;
+  if (e >= d.m) return;
+  const int ei = (int)(e % d.nx), ej = (int)((e / d.nx) % d.ny), ek = (int)(e / ((int64_t)d.nx * d.ny));
+  T ve[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int ni = ei + loc_x(b), nj = ej + loc_y(b), nk = ek + loc_z(b);
+    const int64_t qn = ni >= 1 ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ve[b * 3 + c] = v[3 * qn + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int r = a * 3 + c;
+    T y = T(0);
+#pragma unroll
+    for (int col = 0; col < 24; ++col) y += E[sym_index(r, col, 24) * d.m + e] * ve[col];
+    ye[r * d.m + e] = y;
+  }
+}
+
+// Node rows and diagonal of a stored 3D level from the element products ye.
+template <typename T, bool ROWS, bool DIAG>
+__device__ inline void node_apply_ye3(const OpCoarse<3, T>& op, const Dims& d, int i, int j, int k, T* acc, T* dg) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+    int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && ek >= 0 && ek < d.nz;
+    const int64_t e = ok ? ((int64_t)ek * d.ny + ej) * d.nx + ei : 0;
+    const int a = loc_index(1 - ex, 1 - ey, 1 - ez);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int r = a * 3 + c;
+      if constexpr (ROWS) acc[c] += ok ? op.ye[r * op.m + e] : T(0);
+      if constexpr (DIAG) dg[c] += ok ? op.E[sym_index(r, r, 24) * op.m + e] : T(0);
+    }
+  }
+}
+
 template <typename T, class Op, bool ROWS, bool DIAG>
 __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
                                           T* acc, T* dg) {
+  if constexpr (std::is_same<Op, OpCoarse<3, T>>::value) {
+    if (!ROWS || op.ye) return node_apply_ye3<T, ROWS, DIAG>(op, d, i, j, k, acc, dg);
+  }
   if constexpr (std::is_same<Op, OpFineK<3, T>>::value) {
     return node_apply_fine3<T, Op, ROWS, DIAG>(op, d, i, j, k, v, acc, dg);
   } else if constexpr (std::is_same<Op, OpFineZ<3, T>>::value) {

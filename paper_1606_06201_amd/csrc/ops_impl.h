@@ -617,8 +617,15 @@ struct OpsImpl : Ops {
       launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, mode, (const T*)v, (const T*)r,
                       (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     } else {
-      launch_level<T>(c, d, OpCoarse<DIM, T>{(const T*)c.lev[lev].E, d.m}, mode, (const T*)v, (const T*)r, (T*)out,
-                      omg, aug, sidx, sidx_in, gate, dot64);
+      OpCoarse<DIM, T> o{(const T*)c.lev[lev].E, d.m};
+      // element products first (levels of 8192 elements and more: below, the
+      // extra launch costs more than the gathers it saves)
+      if (DIM == 3 && c.ye && mode != M_JACOBI0 && v && d.m >= c.elem_apply3_min) {
+        k_elem_apply3<T><<<(unsigned)((d.m + 63) / 64), EA3_THREADS, 0, c.stream>>>(d, o.E, (const T*)v,
+                                                                                     (T*)c.ye, gate);
+        o.ye = (const T*)c.ye;
+      }
+      launch_level<T>(c, d, o, mode, (const T*)v, (const T*)r, (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
     }
   }
 

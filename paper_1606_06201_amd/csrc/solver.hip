@@ -154,6 +154,8 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_FOLD_RN2")) c.fold_rn2_fin = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_RESTRICT")) c.fold_restrict = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_ELEM_HV")) c.elem_hv = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_ELEM_APPLY3")) c.elem_apply3 = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_ELEM_APPLY3_MIN")) c.elem_apply3_min = std::max<int64_t>(0, std::atoll(e));
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -232,6 +234,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   vfill(st, c.pp2, 0.0, (int64_t)n1);
   dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
   dalloc(c.oc_cand, sizeof(double) * OC_CAND);
+  if (d.dim == 3 && c.L >= 2 && c.elem_apply3) dalloc(c.ye, c.tsz * 24 * (size_t)c.lev[c.L - 2].d.m);
   vfill_small(st, c.omega_dev, c.L, d.omega);
 
   // element matrix on the GPU, mirrored to the host and to constant memory
@@ -267,7 +270,7 @@ void ctx_free(Ctx& c) {
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
-  dfree(c.oc_t); dfree(c.oc_cand);
+  dfree(c.oc_t); dfree(c.oc_cand); dfree(c.ye);
   if (c.hscal) (void)hipHostFree(c.hscal);
   if (c.hflags) (void)hipHostFree(c.hflags);
   c.hscal = nullptr; c.hflags = nullptr;

@@ -1,8 +1,9 @@
 """Writes tests/golden/thr2048x1024.txt: the oracle's own FP64 solution of
 K(x) u = f on the 2048x1024 two-phase workload (contrast 1e6, 6 multigrid
-levels), solved by the oracle's MG-PCG to a relative residual of 1e-9, ten
-times below the 1e-8 tolerance of the GPU solves, so that the GPU solutions can
-be compared with it.
+levels), solved by the oracle's MG-PCG aiming at a relative residual of 1e-9 so
+that the GPU solutions (1e-8) can be compared with it.  At this contrast the FP64
+recurrence does not reach 1e-9: the run stops at its 2000-step limit with a true
+relative residual of 4.1e-9, which is what the stored file records.
 
 Calls only oracle/ and the seeded input generators (no GPU, no library code).
 Stored: the iteration count and both residuals, the compliance f'u, ||u||_2,

@@ -288,3 +288,27 @@ def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol,
     f = fem.load_vector(g, tip_load(nel))
     u, info = s.pcg(T(f), rtol=1e-8)
     assert info["true_relres"] <= 1e-8
+
+
+@pytest.mark.parametrize("env,val", [("IPMG_ELEM_APPLY3_MIN", "0"), ("IPMG_NO_ELEM_APPLY3", "1")])
+@pytest.mark.parametrize("nel,levels,fp32,tol", [((16, 8, 8), 3, False, 1e-11), ((16, 8, 8), 3, True, 2e-4),
+                                                  ((12, 8, 4), 3, False, 1e-11)])
+def test_vcycle_3d_element_products_match_oracle(env, val, nel, levels, fp32, tol, monkeypatch):
+    # 3D stored coarse levels: element products y_e = E_e v_e formed by a pass of
+    # their own and gathered three per element by the node passes (forced on every
+    # stored level), or the node passes' own gathers of E_e and v_e; both against
+    # the oracle's V-cycle (a ragged 12 x 8 x 4 grid included).
+    g, K0, x = _kproblem(nel)
+    H = mg.kstiffness_hierarchy(g, x, K0, levels)
+    r = np.random.default_rng(8).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    monkeypatch.setenv(env, val)
+    s = _solver(nel, levels, fp32=fp32)
+    monkeypatch.delenv(env)
+    s.set_density(T(x))
+    s.mg_setup()
+    for k in range(1, levels):
+        w, rho = s.level_damping(k)
+        assert abs(rho - H.rho[k]) <= (1e-9 if not fp32 else 1e-4) * H.rho[k]
+    z = N(s.vcycle(T(r)))
+    assert relerr(fem.to_free(g, z), mg.vcycle(H, fem.to_free(g, r))) < tol
