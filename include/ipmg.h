@@ -282,6 +282,8 @@ int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, do
  *  10: fused prolongation and post-smoothing on the finest level (with the PCG ratio)
  *  11: prolongation folded into the first post-smoothing sweep on the finest level
  *  12: the first two pre-smoothing sweeps on the finest level in one pass
+ *  13: 3D finest level, element products of a V-cycle pass (before its node pass)
+ *  14: 3D finest level, element products of the FP64 PCG direction
  * Launches skipped on device after convergence are recorded too (with near-zero
  * duration).  max_launches: event pairs to keep (further launches are not timed).
  * durations_ms: [host] capacity entries, each launch's duration; classes: [host,

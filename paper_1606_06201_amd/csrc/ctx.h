@@ -65,6 +65,9 @@ struct Ops {
   virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate,
                         const double* beta64 = nullptr) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
+  // 3D finest level: the diagonal of the hierarchy's operator per DOF slot (V-cycle
+  // precision), formed once per set-up (no-op elsewhere)
+  virtual void fine_diag(Ctx& c, int op) = 0;
   // t_e = x_e (u_e'K0u_e)^q of the OC update (Sec. 4)
   virtual void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) = 0;
   // Interior point kernels (FP64).
@@ -170,6 +173,12 @@ struct Ctx {
   // (24 values per element of the largest stored level, V-cycle precision)
   void* ye = nullptr;
   bool elem_apply3 = true;
+  // 3D finest level: element products of the pass's vector (V-cycle precision and
+  // FP64, aliased in FP64 mode) and the set-up diagonal
+  void* fine_ye = nullptr;
+  double* fine_ye64 = nullptr;
+  void* fine_dg = nullptr;
+  bool elem_fine3 = true;
   int64_t elem_apply3_min = 8192;   // ... on levels with at least this many elements
 
   // OC update: t_e = x_e E_e^q (m) and the trial multipliers of a bisection pass
@@ -205,7 +214,9 @@ enum ProfClass {
   PC_FINE_UP = 10,          // finest level, fused prolongation + post-smoothing (+ PCG ratio)
   PC_FINE_PJACOBI = 11,     // finest level, prolongation folded into the first post-smoothing sweep
   PC_FINE_JACOBI2 = 12,     // finest level, the first two pre-smoothing sweeps in one pass
-  PC_COUNT = 13
+  PC_ELEM3 = 13,            // 3D finest level, element products of a V-cycle pass
+  PC_ELEM3_DIR = 14,        // 3D finest level, element products of the FP64 direction
+  PC_COUNT = 15
 };
 
 // Sets the class of the level passes enqueued in its scope.

@@ -249,6 +249,8 @@ template <int DIM, typename T>
 struct OpFineK {
   const T* x;
   int64_t m;
+  const T* ye = nullptr;    // 3D: element products of the pass's vector (k_elem_fine3)
+  const T* dgn = nullptr;   // 3D: the diagonal per DOF slot, formed at set-up (k_fine_diag3)
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
     const T xe = x[e];
@@ -281,6 +283,8 @@ struct OpFineZ {
   const T* h;
   int64_t m;
   const T* hs = nullptr;   // h_e'v_e per element, formed beforehand by k_elem_hv (same sum)
+  const T* ye = nullptr;   // 3D: element products of the pass's vector (k_elem_fine3)
+  const T* dgn = nullptr;  // 3D: the diagonal per DOF slot, formed at set-up (k_fine_diag3)
   // rows() sums h_e'v_e over ve itself: its callers may map an element outside the
   // grid to element 0 with a zero ve, where hs[0] would not be zero.
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
@@ -831,9 +835,90 @@ __device__ inline void node_apply_ye3(const OpCoarse<3, T>& op, const Dims& d, i
   }
 }
 
+// Element products of the finest 3D level, y_e = x_e K0 v_e (+ h_e (h_e'v_e) for the
+// augmented system), 8 waves per 64 elements: wave a forms the rows of local node
+// a in the reflected form of node_apply_fine3 (the three rows of local node 0 as
+// compile-time constants, v gathered in the reflected order).  For Z each wave adds
+// its node's part of h_e'v_e into LDS and the eight parts are summed in node order.
+template <typename T, bool Z>
+__global__ __launch_bounds__(EA3_THREADS) void k_elem_fine3(Dims d, const T* __restrict__ x, const T* __restrict__ h,
+                                                            const T* __restrict__ v, T* __restrict__ ye,
+                                                            const int* gate) {
+  if (gate && *gate) return;
+  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * 64 + lane;
+  const bool in = e0 < d.m;
+  const int64_t e = in ? e0 : 0;
+  const int ei = (int)(e % d.nx), ej = (int)((e / d.nx) % d.ny), ek = (int)(e / ((int64_t)d.nx * d.ny));
+  const int pa0 = loc_x(a), pa1 = loc_y(a), pa2 = loc_z(a);
+  const T sg[3] = {T(1 - 2 * pa0), T(1 - 2 * pa1), T(1 - 2 * pa2)};
+  T vr[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int ni = ei + (pa0 ^ loc_x(b)), nj = ej + (pa1 ^ loc_y(b)), nk = ek + (pa2 ^ loc_z(b));
+    const int64_t qn = ni >= 1 ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vr[b * 3 + c] = sg[c] * v[3 * qn + c];
+  }
+  const T xe = x[e];
+  T y[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T t = 0;
+#pragma unroll
+    for (int col = 0; col < 24; ++col) t += k0cube<T>(c, col) * vr[col];
+    y[c] = xe * sg[c] * t;
+  }
+  if constexpr (Z) {
+    __shared__ T sh[8][64];
+    T hr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hr[c] = h[(a * 3 + c) * d.m + e];
+    sh[a][lane] = hr[0] * (sg[0] * vr[0]) + hr[1] * (sg[1] * vr[1]) + hr[2] * (sg[2] * vr[2]);
+    __syncthreads();
+    T hv = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) hv += sh[w][lane];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c] += hr[c] * hv;
+  }
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ye[(a * 3 + c) * d.m + e] = y[c];
+  }
+}
+
+// Rows (from the element products ye) and diagonal (per slot, dgn) of a node of the
+// finest 3D level.
+template <typename T, bool ROWS, bool DIAG>
+__device__ inline void node_apply_fine_ye3(const T* __restrict__ ye, const T* __restrict__ dgn, int64_t m,
+                                           const Dims& d, int i, int j, int k, T* acc, T* dg) {
+  if constexpr (ROWS) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+      const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+      const bool ok = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny && ek >= 0 && ek < d.nz;
+      const int64_t e = ok ? ((int64_t)ek * d.ny + ej) * d.nx + ei : 0;
+      const int a = loc_index(1 - ex, 1 - ey, 1 - ez);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += ok ? ye[(a * 3 + c) * m + e] : T(0);
+    }
+  }
+  if constexpr (DIAG) {
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dg[c] += dgn[3 * q + c];
+  }
+}
+
 template <typename T, class Op, bool ROWS, bool DIAG>
 __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, int j, int k, const T* __restrict__ v,
                                           T* acc, T* dg) {
+  if constexpr (fine3_op<Op>::value) {
+    if ((!ROWS || op.ye) && (!DIAG || op.dgn))
+      return node_apply_fine_ye3<T, ROWS, DIAG>(op.ye, op.dgn, op.m, d, i, j, k, acc, dg);
+  }
   if constexpr (std::is_same<Op, OpCoarse<3, T>>::value) {
     if (!ROWS || op.ye) return node_apply_ye3<T, ROWS, DIAG>(op, d, i, j, k, acc, dg);
   }
@@ -873,6 +958,21 @@ __device__ inline void node_apply_gather3(const Op& op, const Dims& d, int i, in
       for (int c = 0; c < 3; ++c) dg[c] += ok ? dt[c] : T(0);
     }
   }
+}
+
+// Diagonal of the finest 3D level per DOF slot (0 on clamped slots), formed once per
+// hierarchy set-up: the level passes then read three values per node.
+template <typename T, class Op>
+__global__ __launch_bounds__(BS) void k_fine_diag3(Op op, Dims d, T* __restrict__ dgn) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t >= d.nnodes) return;
+  const int i = (int)(t % d.nx1), j = (int)((t / d.nx1) % d.ny1), k = (int)(t / ((int64_t)d.nx1 * d.ny1));
+  T acc[3] = {T(0), T(0), T(0)}, dg[3] = {T(0), T(0), T(0)};
+  op.ye = nullptr;
+  op.dgn = nullptr;
+  if (i > 0) node_apply_fine3<T, Op, false, true>(op, d, i, j, k, nullptr, acc, dg);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dgn[3 * t + c] = dg[c];
 }
 
 // Generic form: gathers the neighbourhood with bounds checks first (2D); in 3D,

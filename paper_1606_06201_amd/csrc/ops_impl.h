@@ -587,6 +587,28 @@ struct OpsImpl : Ops {
 #undef IPMG_LEVEL_CASE
   }
 
+  // 3D finest level: element products of v into ye (the operator's rows for the
+  // node pass) and the set-up diagonal; false when the element passes are off.
+  template <typename T, class Op>
+  bool fine_elem3(Ctx& c, Op& o, const T* v, T* ye, const T* dgn, const int* gate, int cls) {
+    if constexpr (DIM != 3) {
+      return false;
+    } else {
+      if (!ye) return false;
+      const Dims& d = c.fine();
+      if (v) {
+        constexpr bool Z = std::is_same<Op, OpFineZ<3, T>>::value;
+        const T* h = nullptr;
+        if constexpr (Z) h = o.h;
+        ProfScope ps(c, cls);
+        k_elem_fine3<T, Z><<<(unsigned)((d.m + 63) / 64), EA3_THREADS, 0, c.stream>>>(d, o.x, h, v, ye, gate);
+        o.ye = ye;
+      }
+      o.dgn = dgn;
+      return true;
+    }
+  }
+
   // The finest-level augmented operator for a pass over v (null: the pass reads
   // no v).  In 3D, h_e'v_e is formed per element first (k_elem_hv) and the pass
   // reads it, instead of every node of an element summing all of h_e again.
@@ -607,12 +629,22 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     Aug<T> aug{op == IPMG_OP_Z ? (const T*)c.lev[lev].bZ : nullptr, c.cZ, d.nslots};
     if (lev == c.L - 1) {
-      if (op == IPMG_OP_K)
-        launch_level<T>(c, d, OpFineK<DIM, T>{(const T*)c.xT, d.m}, mode, (const T*)v, (const T*)r, (T*)out, omg,
-                        aug, sidx, sidx_in, gate, dot64);
-      else
-        launch_level<T>(c, d, fine_z<T>(c, (const T*)c.hT, mode != M_JACOBI0 ? (const T*)v : nullptr), mode,
+      // 3D: element products first, the diagonal from set-up (formed before the
+      // damping estimates)
+      const T* vv = mode != M_JACOBI0 ? (const T*)v : nullptr;
+      const bool elem = DIM == 3 && c.fine_ye && c.fine_dg;
+      if (op == IPMG_OP_K) {
+        OpFineK<DIM, T> o{(const T*)c.xT, d.m};
+        if (elem) fine_elem3<T>(c, o, vv, (T*)c.fine_ye, (const T*)c.fine_dg, gate, PC_ELEM3);
+        launch_level<T>(c, d, o, mode, (const T*)v, (const T*)r, (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
+      } else if (elem) {
+        OpFineZ<DIM, T> o{(const T*)(sizeof(T) == 8 ? (const void*)c.x64 : c.xT), (const T*)c.hT, d.m};
+        fine_elem3<T>(c, o, vv, (T*)c.fine_ye, (const T*)c.fine_dg, gate, PC_ELEM3);
+        launch_level<T>(c, d, o, mode, (const T*)v, (const T*)r, (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
+      } else {
+        launch_level<T>(c, d, fine_z<T>(c, (const T*)c.hT, vv), mode,
                         (const T*)v, (const T*)r, (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
+      }
     } else if (DIM == 2 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x) {
       launch_level<T>(c, d, OpCoarse2K<DIM, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, mode, (const T*)v, (const T*)r,
                       (T*)out, omg, aug, sidx, sidx_in, gate, dot64);
@@ -666,7 +698,9 @@ struct OpsImpl : Ops {
     if constexpr (DIM == 3) {
       k_pdir3<TY><<<lin_grid(d.nslots), BS, 0, c.stream>>>(d, y, pold, p, c.red, first, gate);
       Op o = op;
-      if constexpr (std::is_same<Op, OpFineZ<DIM, double>>::value) o = fine_z<double>(c, c.h64, p);   // h_e'p_e
+      if (!fine_elem3<double>(c, o, p, c.fine_ye64, nullptr, gate, PC_ELEM3_DIR)) {
+        if constexpr (std::is_same<Op, OpFineZ<DIM, double>>::value) o = fine_z<double>(c, c.h64, p);   // h_e'p_e
+      }
       ProfScope ps(c, PC_DIR_APPLY);
       k_dir_apply3<TY, Op><<<g, BS, 0, c.stream>>>(o, d, y, pold, p, q, aug, c.red, first, gate);
     } else {
@@ -697,12 +731,35 @@ struct OpsImpl : Ops {
   void fine_apply64(Ctx& c, int op, const double* v, double* y, const int* gate) override {
     const Dims& d = c.fine();
     if (op == IPMG_OP_K) {
-      launch_level<double>(c, d, OpFineK<DIM, double>{c.x64, d.m}, M_APPLY, v, nullptr, y, nullptr,
-                           Aug<double>{nullptr, 0.0, d.nslots}, 0, -1, gate);
+      OpFineK<DIM, double> o{c.x64, d.m};
+      fine_elem3<double>(c, o, v, c.fine_ye64, nullptr, gate, -1);
+      launch_level<double>(c, d, o, M_APPLY, v, nullptr, y, nullptr, Aug<double>{nullptr, 0.0, d.nslots}, 0, -1,
+                           gate);
     } else {
-      launch_level<double>(c, d, fine_z<double>(c, c.h64, v), M_APPLY, v, nullptr, y, nullptr,
-                           Aug<double>{c.bZ64, c.cZ, d.nslots}, 0, -1, gate);
+      OpFineZ<DIM, double> o{c.x64, c.h64, d.m};
+      if (!fine_elem3<double>(c, o, v, c.fine_ye64, nullptr, gate, -1)) o = fine_z<double>(c, c.h64, v);
+      launch_level<double>(c, d, o, M_APPLY, v, nullptr, y, nullptr, Aug<double>{c.bZ64, c.cZ, d.nslots}, 0, -1,
+                           gate);
     }
+  }
+
+  void fine_diag(Ctx& c, int op) override {
+    if constexpr (DIM == 3) {
+      if (!c.fine_dg) return;
+      const Dims& d = c.fine();
+      if (c.fp32) fine_diag_t<float>(c, op, d);
+      else fine_diag_t<double>(c, op, d);
+    }
+  }
+  template <typename T>
+  void fine_diag_t(Ctx& c, int op, const Dims& d) {
+    const unsigned g = lin_grid(d.nnodes);
+    if (op == IPMG_OP_K)
+      k_fine_diag3<T, OpFineK<DIM, T>><<<g, BS, 0, c.stream>>>(OpFineK<DIM, T>{(const T*)c.xT, d.m}, d, (T*)c.fine_dg);
+    else
+      k_fine_diag3<T, OpFineZ<DIM, T>><<<g, BS, 0, c.stream>>>(
+          OpFineZ<DIM, T>{(const T*)(sizeof(T) == 8 ? (const void*)c.x64 : c.xT), (const T*)c.hT, d.m}, d,
+          (T*)c.fine_dg);
   }
 
   void restrict_to(Ctx& c, int lev_f, const void* rf, void* rc, int aug, const int* gate) override {

@@ -156,6 +156,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_ELEM_HV")) c.elem_hv = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_ELEM_APPLY3")) c.elem_apply3 = e[0] != '1';
   if (const char* e = std::getenv("IPMG_ELEM_APPLY3_MIN")) c.elem_apply3_min = std::max<int64_t>(0, std::atoll(e));
+  if (const char* e = std::getenv("IPMG_NO_ELEM_FINE3")) c.elem_fine3 = e[0] != '1';
   if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
   if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
@@ -235,6 +236,12 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   dalloc(c.omega_dev, sizeof(double) * 2 * c.L);
   dalloc(c.oc_cand, sizeof(double) * OC_CAND);
   if (d.dim == 3 && c.L >= 2 && c.elem_apply3) dalloc(c.ye, c.tsz * 24 * (size_t)c.lev[c.L - 2].d.m);
+  if (d.dim == 3 && c.elem_fine3) {
+    dalloc(c.fine_ye64, sizeof(double) * 24 * (size_t)fd.m);
+    if (c.fp32) dalloc(c.fine_ye, sizeof(float) * 24 * (size_t)fd.m);
+    else c.fine_ye = c.fine_ye64;
+    dalloc(c.fine_dg, c.tsz * (size_t)fd.nslots);
+  }
   vfill_small(st, c.omega_dev, c.L, d.omega);
 
   // element matrix on the GPU, mirrored to the host and to constant memory
@@ -271,6 +278,9 @@ void ctx_free(Ctx& c) {
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
   dfree(c.oc_t); dfree(c.oc_cand); dfree(c.ye);
+  if (c.fine_ye != (void*)c.fine_ye64) dfree(c.fine_ye);
+  c.fine_ye = nullptr;
+  dfree(c.fine_ye64); dfree(c.fine_dg);
   if (c.hscal) (void)hipHostFree(c.hscal);
   if (c.hflags) (void)hipHostFree(c.hflags);
   c.hscal = nullptr; c.hflags = nullptr;
@@ -349,6 +359,7 @@ void mg_setup(Ctx& c, int op, double* ms) {
   }
   IPMG_HIP(hipGetLastError());
   ensure_dense(c);
+  c.ops->fine_diag(c, op);
   const int steps = op == IPMG_OP_Z ? c.power_steps_z : c.power_steps;
   for (int k = 1; k < L; ++k) jacobi_damping(c, k, op, steps, SAFE_PRODUCT);
   const int n = c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);

@@ -160,11 +160,12 @@ def test_adjoint_gradient_matches_oracle(fp32):
 
 @pytest.mark.parametrize("fp32", [False, True])
 def test_z3d_element_hv_pass_matches_gather(fp32, monkeypatch):
-    # 3D augmented operator: h_e'v_e formed per element before each pass and the
-    # element rows taken in the reflected order of the cube symmetry (default), or
-    # the generic gather that sums h_e'v_e at every node with the stored K0 rows:
-    # the same operator summed in two orders, so Z v, the V-cycle on Z and a PCG
-    # solve on Z agree to rounding (against the oracle's assembled Z as well).
+    # 3D augmented operator in three forms: element products formed by a pass of
+    # their own and gathered by the node passes (default); node passes in the
+    # reflected order of the cube symmetry reading h_e'v_e formed per element; the
+    # generic gather summing h_e'v_e at every node with the stored K0 rows.  The same
+    # operator summed in different orders, so Z v, the V-cycle on Z and a PCG solve
+    # on Z agree to rounding (against the oracle's assembled Z as well).
     from paper_1606_06201_amd import Solver
     nel, levels = (8, 4, 4), 2
     prob = _problem(nel)
@@ -173,8 +174,11 @@ def test_z3d_element_hv_pass_matches_gather(fp32, monkeypatch):
     v = np.random.default_rng(3).standard_normal(g.nslots + 1)
     v[:-1][g.clamped_mask()] = 0
     out = {}
-    for off in ("0", "1"):
-        monkeypatch.setenv("IPMG_NO_ELEM_HV", off)
+    # "e": element products of the finest level (default); "0": node passes reading
+    # h_e'v_e per element; "1": node passes summing it themselves
+    for off in ("e", "0", "1"):
+        monkeypatch.setenv("IPMG_NO_ELEM_FINE3", "0" if off == "e" else "1")
+        monkeypatch.setenv("IPMG_NO_ELEM_HV", "0" if off == "e" else off)
         s = Solver(nel, levels, fp32=fp32)
         params = s.ip_params(prob.V, prob.xbar)
         rhs = s.ip_prepare(T(prob.f_slots), params, _gpu_state(s, st, u_slots))
@@ -184,12 +188,15 @@ def test_z3d_element_hv_pass_matches_gather(fp32, monkeypatch):
         u, info = s.pcg(rhs, op=1, rtol=1e-10)
         out[off] = (zv, zc, N(u), info["iters"])
     monkeypatch.delenv("IPMG_NO_ELEM_HV")
-    a, b = out["0"], out["1"]
+    monkeypatch.delenv("IPMG_NO_ELEM_FINE3")
+    b = out["1"]
     tol = 1e-5 if fp32 else 1e-12           # the V-cycle rounds in its own precision
-    assert relerr(a[0], b[0]) < 1e-14 and relerr(a[1], b[1]) < tol
-    # PCG to 1e-10: the FP32 V-cycles' different rounding moves the count a little
-    assert abs(a[3] - b[3]) <= (1 if not fp32 else max(2, 0.05 * b[3]))
-    assert relerr(a[2], b[2]) < 1e-8
+    for a in (out["e"], out["0"]):
+        assert relerr(a[0], b[0]) < 1e-14 and relerr(a[1], b[1]) < tol
+        # PCG to 1e-10: the FP32 V-cycles' different rounding moves the count a little
+        assert abs(a[3] - b[3]) <= (1 if not fp32 else max(2, 0.05 * b[3]))
+        assert relerr(a[2], b[2]) < 1e-8
+    a = out["e"]
     Z, zrhs, parts = prob.z_system(st)
     free = g.free_to_slot()
     ref = Z @ np.concatenate([v[:-1][free], v[-1:]])

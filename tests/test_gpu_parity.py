@@ -290,7 +290,8 @@ def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol,
     assert info["true_relres"] <= 1e-8
 
 
-@pytest.mark.parametrize("env,val", [("IPMG_ELEM_APPLY3_MIN", "0"), ("IPMG_NO_ELEM_APPLY3", "1")])
+@pytest.mark.parametrize("env,val", [("IPMG_ELEM_APPLY3_MIN", "0"), ("IPMG_NO_ELEM_APPLY3", "1"),
+                                     ("IPMG_NO_ELEM_FINE3", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((16, 8, 8), 3, False, 1e-11), ((16, 8, 8), 3, True, 2e-4),
                                                   ((12, 8, 4), 3, False, 1e-11)])
 def test_vcycle_3d_element_products_match_oracle(env, val, nel, levels, fp32, tol, monkeypatch):
