@@ -249,7 +249,7 @@ template <int DIM, typename T>
 struct OpFineK {
   const T* x;
   int64_t m;
-  const T* ye = nullptr;    // 3D: element products of the pass's vector (k_elem_fine3)
+  const T* ye = nullptr;    // 3D: element products of the pass's vector (k_elem_fine3e)
   const T* dgn = nullptr;   // 3D: the diagonal per DOF slot, formed at set-up (k_fine_diag3)
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
@@ -283,7 +283,7 @@ struct OpFineZ {
   const T* h;
   int64_t m;
   const T* hs = nullptr;   // h_e'v_e per element, formed beforehand by k_elem_hv (same sum)
-  const T* ye = nullptr;   // 3D: element products of the pass's vector (k_elem_fine3)
+  const T* ye = nullptr;   // 3D: element products of the pass's vector (k_elem_fine3e)
   const T* dgn = nullptr;  // 3D: the diagonal per DOF slot, formed at set-up (k_fine_diag3)
   // rows() sums h_e'v_e over ve itself: its callers may map an element outside the
   // grid to element 0 with a zero ve, where hs[0] would not be zero.
@@ -836,55 +836,44 @@ __device__ inline void node_apply_ye3(const OpCoarse<3, T>& op, const Dims& d, i
 }
 
 // Element products of the finest 3D level, y_e = x_e K0 v_e (+ h_e (h_e'v_e) for the
-// augmented system), 8 waves per 64 elements: wave a forms the rows of local node
-// a in the reflected form of node_apply_fine3 (the three rows of local node 0 as
-// compile-time constants, v gathered in the reflected order).  For Z each wave adds
-// its node's part of h_e'v_e into LDS and the eight parts are summed in node order.
+// augmented system), one thread per element: all 24 rows, every matrix entry a
+// signed copy of one of the 14 cube constants at compile time (no matrix loads),
+// h_e'v_e summed in column order; 32-bit index arithmetic (the grid has < 2^31
+// slots).  Measured faster than 8 waves per 64 elements (one row group each, h_e'v_e
+// combined in LDS) and than the node passes gathering the element rows themselves.
 template <typename T, bool Z>
-__global__ __launch_bounds__(EA3_THREADS) void k_elem_fine3(Dims d, const T* __restrict__ x, const T* __restrict__ h,
-                                                            const T* __restrict__ v, T* __restrict__ ye,
-                                                            const int* gate) {
+__global__ __launch_bounds__(BS) void k_elem_fine3e(Dims d, const T* __restrict__ x, const T* __restrict__ h,
+                                                    const T* __restrict__ v, T* __restrict__ ye, const int* gate) {
   if (gate && *gate) return;
-  const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;
-  const int64_t e0 = (int64_t)blockIdx.x * 64 + lane;
-  const bool in = e0 < d.m;
-  const int64_t e = in ? e0 : 0;
-  const int ei = (int)(e % d.nx), ej = (int)((e / d.nx) % d.ny), ek = (int)(e / ((int64_t)d.nx * d.ny));
-  const int pa0 = loc_x(a), pa1 = loc_y(a), pa2 = loc_z(a);
-  const T sg[3] = {T(1 - 2 * pa0), T(1 - 2 * pa1), T(1 - 2 * pa2)};
-  T vr[24];
+  const int e = (int)(blockIdx.x * BS + threadIdx.x);
+  if (e >= (int)d.m) return;
+  const int ei = e % d.nx, t = e / d.nx, ej = t % d.ny, ek = t / d.ny;
+  T ve[24];
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const int ni = ei + (pa0 ^ loc_x(b)), nj = ej + (pa1 ^ loc_y(b)), nk = ek + (pa2 ^ loc_z(b));
-    const int64_t qn = ni >= 1 ? ((int64_t)nk * d.ny1 + nj) * d.nx1 + ni : 0;
+    const int ni = ei + loc_x(b), nj = ej + loc_y(b), nk = ek + loc_z(b);
+    const int qn = ni >= 1 ? (nk * d.ny1 + nj) * d.nx1 + ni : 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vr[b * 3 + c] = sg[c] * v[3 * qn + c];
+    for (int c = 0; c < 3; ++c) ve[b * 3 + c] = v[3 * qn + c];
+  }
+  const int m = (int)d.m;
+  T hh[Z ? 24 : 1];
+  T hv = 0;
+  if constexpr (Z) {
+#pragma unroll
+    for (int col = 0; col < 24; ++col) hh[col] = h[col * m + e];
+#pragma unroll
+    for (int col = 0; col < 24; ++col) hv += hh[col] * ve[col];
   }
   const T xe = x[e];
-  T y[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T t = 0;
+  for (int r = 0; r < 24; ++r) {
+    T y = 0;
 #pragma unroll
-    for (int col = 0; col < 24; ++col) t += k0cube<T>(c, col) * vr[col];
-    y[c] = xe * sg[c] * t;
-  }
-  if constexpr (Z) {
-    __shared__ T sh[8][64];
-    T hr[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) hr[c] = h[(a * 3 + c) * d.m + e];
-    sh[a][lane] = hr[0] * (sg[0] * vr[0]) + hr[1] * (sg[1] * vr[1]) + hr[2] * (sg[2] * vr[2]);
-    __syncthreads();
-    T hv = 0;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) hv += sh[w][lane];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) y[c] += hr[c] * hv;
-  }
-  if (in) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ye[(a * 3 + c) * d.m + e] = y[c];
+    for (int col = 0; col < 24; ++col) y += k0cube<T>(r, col) * ve[col];
+    y *= xe;
+    if constexpr (Z) y += hh[r] * hv;
+    ye[r * m + e] = y;
   }
 }
 

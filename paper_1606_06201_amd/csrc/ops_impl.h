@@ -601,7 +601,7 @@ struct OpsImpl : Ops {
         const T* h = nullptr;
         if constexpr (Z) h = o.h;
         ProfScope ps(c, cls);
-        k_elem_fine3<T, Z><<<(unsigned)((d.m + 63) / 64), EA3_THREADS, 0, c.stream>>>(d, o.x, h, v, ye, gate);
+        k_elem_fine3e<T, Z><<<lin_grid(d.m), BS, 0, c.stream>>>(d, o.x, h, v, ye, gate);
         o.ye = ye;
       }
       o.dgn = dgn;
