@@ -265,6 +265,26 @@ int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg
 int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, double xbar, double q,
                    double lam_hi, double tau, const double* blend, double* x_new, ipmg_oc_info* info);
 
+/* SIMP model with a density filter (Sec. 9).  Filtered densities x~ = W x, with
+ * W^_ij = max(0, rmin - dist(i, j)) for the Manhattan distance of element centres
+ * and every column of W scaled to sum one, W_:i = W^_:i / sum_j W^_ij (so
+ * sum x~ = sum x).  transpose = 0: out = W in; 1: out = W' in.  in, out: [device] m
+ * doubles, not aliased.  rmin in (0, 5].  Errors: IPMG_E_INVALID. */
+int ipmg_filter(ipmg_ctx* ctx, double rmin, const double* in, double* out, int transpose);
+
+/* Compliance and gradient of the SIMP model at the densities x (Sec. 9): x~ = W x,
+ * K^ = sum_e x~_e^p K_e (the context's densities are set to x~^p), u = K^-1 f by
+ * MG-PCG to rtol (zero start), c = f'u (info->bu), and
+ *   grad_i = dc/dx_i = -sum_j W_ji p x~_j^(p-1) u_j'K0u_j,
+ * the bracket of the paper's modified condition (KKT3).  x: [device] m, each in
+ * (0, inf); f: [device] n_slots; u: [device] n_slots output; grad: [device] m output;
+ * info: [host] nullable.  p >= 1, rmin in (0, 5].  Returns the status of the solve
+ * (u and info valid, grad only on IPMG_OK), IPMG_E_DOMAIN for x~^p not positive and
+ * finite, IPMG_E_INVALID for bad arguments.  The Newton system of the SIMP
+ * interior-point method (B^(u) of Sec. 9) is not provided. */
+int ipmg_simp_compliance(ipmg_ctx* ctx, const double* x, const double* f, double rmin, double p, double rtol,
+                         int maxit, double* u, double* grad, ipmg_pcg_info* info);
+
 /* Kernel timing for roofline measurements.  Between begin and end, the launch of
  * the main kernel of every selected class (bit k of class_mask selects class k) is
  * bracketed by a pair of HIP events on the context's stream; the one-block

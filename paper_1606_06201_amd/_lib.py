@@ -69,6 +69,9 @@ SIGNATURES = {
     "ipmg_pcg_noalloc_bytes": (C.c_int64, [C.c_void_p]),
     "ipmg_oc_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(OCInfo)]),
+    "ipmg_filter": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_int]),
+    "ipmg_simp_compliance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                       C.c_int, C.c_void_p, C.c_void_p, C.POINTER(PCGInfo)]),
     "ipmg_element_sens": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "ipmg_ip_init": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.POINTER(IPState),
                                C.POINTER(PCGInfo)]),

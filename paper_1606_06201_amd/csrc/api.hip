@@ -214,6 +214,25 @@ int ipmg_oc_update(ipmg_ctx* ctx, const double* u, const double* x, double V, do
   });
 }
 
+int ipmg_filter(ipmg_ctx* ctx, double rmin, const double* in, double* out, int transpose) {
+  if (!in || !out || in == out || !(rmin > 0.0 && rmin <= 5.0) || (transpose != 0 && transpose != 1))
+    return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) {
+    c.ops->filter(c, rmin, in, out, transpose);
+    IPMG_HIP(hipGetLastError());
+    ipmg::sync(c);
+    return IPMG_OK;
+  });
+}
+
+int ipmg_simp_compliance(ipmg_ctx* ctx, const double* x, const double* f, double rmin, double p, double rtol,
+                         int maxit, double* u, double* grad, ipmg_pcg_info* info) {
+  if (!x || !f || !u || !grad || !(rmin > 0.0 && rmin <= 5.0) || !(p >= 1.0 && std::isfinite(p)) ||
+      !(rtol > 0.0) || maxit < 0)
+    return IPMG_E_INVALID;
+  return guard(ctx, [&](Ctx& c) { return ipmg::simp_compliance(c, x, f, rmin, p, rtol, maxit, u, grad, info); });
+}
+
 int ipmg_element_sens(ipmg_ctx* ctx, const double* w, const double* u, double scale, double* g) {
   if (!w || !u || !g) return IPMG_E_INVALID;
   return guard(ctx, [&](Ctx& c) {

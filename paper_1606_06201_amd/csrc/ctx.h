@@ -68,6 +68,9 @@ struct Ops {
   // 3D finest level: the diagonal of the hierarchy's operator per DOF slot (V-cycle
   // precision), formed once per set-up (no-op elsewhere)
   virtual void fine_diag(Ctx& c, int op) = 0;
+  // SIMP model (Sec. 9): out = W in or W' in (density filter), and x~^p / p x~^(p-1) E
+  virtual void filter(Ctx& c, double rmin, const double* in, double* out, int transpose) = 0;
+  virtual void simp_pow(Ctx& c, const double* xt, double p, double* xp, double* q) = 0;
   // t_e = x_e (u_e'K0u_e)^q of the OC update (Sec. 4)
   virtual void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) = 0;
   // Interior point kernels (FP64).
@@ -181,6 +184,10 @@ struct Ctx {
   bool elem_fine3 = true;
   int64_t elem_apply3_min = 8192;   // ... on levels with at least this many elements
 
+  // SIMP model: filtered densities and the penalised ones (m each)
+  double* simp_xt = nullptr;
+  double* simp_xp = nullptr;
+
   // OC update: t_e = x_e E_e^q (m) and the trial multipliers of a bisection pass
   double* oc_t = nullptr;
   double* oc_cand = nullptr;
@@ -265,5 +272,7 @@ void ip_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, const ipmg_ip_
 int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_ip_info* info);
 void oc_update(Ctx& c, const double* u, const double* x, double V, double xbar, double q, double lam_hi,
                double tau, const double* blend, double* x_new, ipmg_oc_info* info);
+int simp_compliance(Ctx& c, const double* x, const double* f, double rmin, double p, double rtol, int maxit,
+                    double* u, double* grad, ipmg_pcg_info* info);
 
 }  // namespace ipmg

@@ -143,6 +143,56 @@ __global__ __launch_bounds__(BS) void k_oc_energy(Dims d, const double* __restri
   t[e] = x[e] * (q == 1.0 ? s : (q == 0.5 ? sqrt(s) : pow(s, q)));
 }
 
+// Density filter of the SIMP model (Sec. 9): W^_ij = max(0, rmin - dist(i, j)) with
+// the Manhattan distance of element centres, W_ji = W^_ji / s_i, s_i = sum_k W^_ki
+// (every column of W sums to one).  transpose = 0: out = W in, i.e.
+// out_j = sum_i W^_ji in_i / s_i; transpose = 1: out = W' in, out_i = sum_j W^_ji in_j / s_i.
+// The column sums are formed on the fly from the grid geometry; neighbours in a
+// fixed order, so the result is deterministic.
+template <int DIM>
+__device__ inline double filter_colsum(const Dims& d, int ei, int ej, int ek, double rmin, int R) {
+  double s = 0.0;
+  for (int dz = (DIM == 3 ? -R : 0); dz <= (DIM == 3 ? R : 0); ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int i = ei + dx, j = ej + dy, k = ek + dz;
+        if (i < 0 || i >= d.nx || j < 0 || j >= d.ny || (DIM == 3 && (k < 0 || k >= d.nz))) continue;
+        s += fmax(0.0, rmin - (double)(abs(dx) + abs(dy) + abs(dz)));
+      }
+  return s;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_filter(Dims d, double rmin, int R, const double* __restrict__ in,
+                                               double* __restrict__ out, int transpose) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= d.m) return;
+  int ei, ej, ek;
+  elem_coords<DIM>(d, e, ei, ej, ek);
+  double acc = 0.0;
+  for (int dz = (DIM == 3 ? -R : 0); dz <= (DIM == 3 ? R : 0); ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int i = ei + dx, j = ej + dy, k = ek + dz;
+        if (i < 0 || i >= d.nx || j < 0 || j >= d.ny || (DIM == 3 && (k < 0 || k >= d.nz))) continue;
+        const double w = rmin - (double)(abs(dx) + abs(dy) + abs(dz));
+        if (!(w > 0.0)) continue;
+        const int64_t o = ((int64_t)(DIM == 3 ? k : 0) * d.ny + j) * d.nx + i;
+        acc += transpose ? w * in[o] : w * in[o] / filter_colsum<DIM>(d, i, j, k, rmin, R);
+      }
+  out[e] = transpose ? acc / filter_colsum<DIM>(d, ei, ej, ek, rmin, R) : acc;
+}
+
+// SIMP penalisation: xp = x~^p, and the chain-rule factor q_e = p x~_e^(p-1) E_e of
+// the compliance gradient (E_e = u_e'K0u_e in q on entry).
+static __global__ __launch_bounds__(BS) void k_simp_pow(int64_t m, const double* __restrict__ xt, double p,
+                                                 double* __restrict__ xp, double* __restrict__ q) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= m) return;
+  if (xp) xp[e] = pow(xt[e], p);
+  if (q) q[e] = p * pow(xt[e], p - 1.0) * q[e];
+}
+
 // Start vector of the spectral-radius estimate: (-1)^(i+j+k) (1 + c), 0 on clamped
 // slots, 1 on lambda.
 template <int DIM, typename T>
@@ -1032,6 +1082,15 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     if (c.fp32) k_power_start<DIM, float><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (float*)v);
     else k_power_start<DIM, double><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (double*)v);
+  }
+
+  void filter(Ctx& c, double rmin, const double* in, double* out, int transpose) override {
+    const Dims& d = c.fine();
+    const int R = (int)std::ceil(rmin) - 1;
+    k_filter<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, rmin, R, in, out, transpose);
+  }
+  void simp_pow(Ctx& c, const double* xt, double p, double* xp, double* q) override {
+    k_simp_pow<<<lin_grid(c.fine().m), BS, 0, c.stream>>>(c.fine().m, xt, p, xp, q);
   }
 
   void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) override {

@@ -277,7 +277,7 @@ void ctx_free(Ctx& c) {
   dfree(c.red.partials); dfree(c.red.counter); dfree(c.red.scal); dfree(c.red.flags);
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
-  dfree(c.oc_t); dfree(c.oc_cand); dfree(c.ye);
+  dfree(c.oc_t); dfree(c.oc_cand); dfree(c.ye); dfree(c.simp_xt); dfree(c.simp_xp);
   if (c.fine_ye != (void*)c.fine_ye64) dfree(c.fine_ye);
   c.fine_ye = nullptr;
   dfree(c.fine_ye64); dfree(c.fine_dg);
@@ -716,6 +716,30 @@ void oc_update(Ctx& c, const double* u, const double* x, double V, double xbar, 
     info->volume = c.hscal[S_OCSUM];
     info->trials = (int)c.hscal[S_OCSTEPS];
   }
+}
+
+// --------------------------------------------------------------------- SIMP --
+// Compliance and gradient of the SIMP model with the density filter (Sec. 9):
+// x~ = W x, K^ = K(x~^p), u = K^-1 f by MG-PCG, c = f'u, grad = -W' (p x~^(p-1) o E).
+int simp_compliance(Ctx& c, const double* x, const double* f, double rmin, double p, double rtol, int maxit,
+                    double* u, double* grad, ipmg_pcg_info* info) {
+  const Dims& d = c.fine();
+  if (!c.simp_xt) dalloc(c.simp_xt, sizeof(double) * (size_t)d.m);
+  if (!c.simp_xp) dalloc(c.simp_xp, sizeof(double) * (size_t)d.m);
+  c.ops->filter(c, rmin, x, c.simp_xt, 0);
+  c.ops->simp_pow(c, c.simp_xt, p, c.simp_xp, nullptr);
+  IPMG_HIP(hipGetLastError());
+  set_density(c, c.simp_xp);
+  IPMG_HIP(hipMemsetAsync(u, 0, sizeof(double) * (size_t)d.nslots, c.stream));
+  const int st = pcg(c, IPMG_OP_K, f, u, rtol, maxit, info);
+  if (st != IPMG_OK) return st;
+  c.ops->element_sens(c, u, u, 1.0, c.simp_xp);               // E_e
+  c.ops->simp_pow(c, c.simp_xt, p, nullptr, c.simp_xp);        // p x~^(p-1) E
+  c.ops->filter(c, rmin, c.simp_xp, grad, 1);                  // W' (...)
+  vscale(c.stream, grad, -1.0, d.m);
+  IPMG_HIP(hipGetLastError());
+  sync(c);
+  return IPMG_OK;
 }
 
 // ------------------------------------------------------------ interior point --

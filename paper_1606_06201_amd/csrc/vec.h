@@ -31,6 +31,7 @@ void vset_rho(hipStream_t st, const Red& red, int sidx);
 template <typename T>
 void vnormalize(hipStream_t st, T* x, int64_t n, const Red& red, int sidx);
 void vfill(hipStream_t st, double* dst, double value, int64_t n);
+void vscale(hipStream_t st, double* v, double a, int64_t n);   // v *= a
 void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red);
 void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
                 double product);

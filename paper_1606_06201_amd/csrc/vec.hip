@@ -321,6 +321,13 @@ void vnormalize(hipStream_t st, T* x, int64_t n, const Red& red, int sidx) {
   k_normalize<T><<<vgrid(n), BS, 0, st>>>(x, n, red, sidx);
 }
 void vfill(hipStream_t st, double* dst, double value, int64_t n) { k_fill<<<vgrid(n), BS, 0, st>>>(dst, value, n); }
+
+namespace {
+__global__ __launch_bounds__(BS) void k_scale(double* __restrict__ v, double a, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) v[t] *= a;
+}
+}  // namespace
+void vscale(hipStream_t st, double* v, double a, int64_t n) { k_scale<<<vgrid(n), BS, 0, st>>>(v, a, n); }
 void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red) {
   k_copy_positive<<<vgrid(n), BS, 0, st>>>(src, dst, n, red);
 }

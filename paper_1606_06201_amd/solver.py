@@ -185,6 +185,23 @@ class Solver:
                    float(scale), self._ptr(out, self.m, "g"))
         return out
 
+    # ------------------------------------------------------------------ SIMP --
+    def filter(self, v, rmin=2.0, transpose=False, out=None):
+        """Density filter of the SIMP model (Sec. 9): W v, or W' v."""
+        out = self._empty(self.m) if out is None else out
+        self._call(self.lib.ipmg_filter, float(rmin), self._ptr(v, self.m, "in"), self._ptr(out, self.m, "out"),
+                   int(bool(transpose)))
+        return out
+
+    def simp_compliance(self, x, f, rmin=2.0, p=3.0, rtol=1e-8, maxit=1000):
+        """(u, gradient, info) of the SIMP compliance at x (Sec. 9); info["bu"] = f'u."""
+        u, grad = self._empty(self.n_slots), self._empty(self.m)
+        info = L.PCGInfo()
+        rc = self._call(self.lib.ipmg_simp_compliance, self._ptr(x, self.m, "x"), self._ptr(f, self.n_slots, "f"),
+                        float(rmin), float(p), float(rtol), int(maxit), self._ptr(u, self.n_slots, "u"),
+                        self._ptr(grad, self.m, "grad"), C.byref(info))
+        return u, grad, dict(iters=info.iters, status=info.status, true_relres=info.true_relres, bu=info.bu, rc=rc)
+
     # ------------------------------------------------------------------- OC --
     def oc_update(self, u, x, V, xbar, q=1.0, lam_hi=1e4, tau=1e-11, blend=None, out=None):
         """One density update of Algorithm OC (q = 1) / DOC (q < 1), Sec. 4, with the
