@@ -103,6 +103,7 @@ struct Ctx {
   // ... and on the finest level: opt-in, measured slower there than the separate
   // register-tiled passes (its barrier-separated phases do not hide memory latency)
   bool fused_fine = false;
+  int cus = 256;                // compute units of the device
   bool fine_small_tiles = false;  // finest-level fused passes on 256-thread tiles
   bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32; stored levels
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)

@@ -72,27 +72,38 @@ struct OpCoarseLDS {
 };
 
 // Copies the stored matrices of elements [ex0, ex0+LW) x [ey0, ey0+LH) of a level
-// into LDS (zero outside the grid).  Every thread issues all of its loads before
-// its first LDS store, so the copy costs one memory latency: indices are clamped
-// into the grid and the (finite) value is multiplied by 0 or 1, since a select on
-// the loaded value would be compiled back into a branch around each load.
+// into LDS (zero outside the grid), entry k of local element le at k NE + le.
+// Thread t takes the elements t, t + NT, ...: their offsets are formed once, and
+// entry k of each sits k m further on (a uniform step), so a load needs no index
+// arithmetic of its own.  Every thread issues all of its loads before its first
+// LDS store, so the copy costs one memory latency: indices are clamped into the
+// grid and the (finite) value is multiplied by 0 or 1, since a select on the
+// loaded value would be compiled back into a branch around each load.
 template <typename T, int NT, int LW, int LH>
 __device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, int ex0, int ey0, T* El) {
-  constexpr int NE = LW * LH, TOTAL = 36 * NE, PER = (TOTAL + NT - 1) / NT;
-  T v[PER];
+  constexpr int NE = LW * LH, PE = (NE + NT - 1) / NT;
+  uint32_t off[PE];
+  T keep[PE];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * NT;
-    const int s = min(t / NE, 35), le = t % NE;
+  for (int j = 0; j < PE; ++j) {
+    const int le = min((int)threadIdx.x + j * NT, NE - 1);
     const int ei = ex0 + le % LW, ej = ey0 + le / LW;
-    const bool in = t < TOTAL && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-    const int eic = min(max(ei, 0), d.nx - 1), ejc = min(max(ej, 0), d.ny - 1);
-    v[u] = Eg[(int64_t)s * d.m + (int64_t)ejc * d.nx + eic] * T(in ? 1 : 0);
+    const bool in = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+    off[j] = (uint32_t)(min(max(ej, 0), d.ny - 1) * d.nx + min(max(ei, 0), d.nx - 1));
+    keep[j] = T(in ? 1 : 0);
   }
+  T v[PE][36];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = threadIdx.x + u * NT;
-    if (t < TOTAL) El[t] = v[u];
+  for (int k = 0; k < 36; ++k)
+#pragma unroll
+    for (int j = 0; j < PE; ++j) v[j][k] = (Eg + k * d.m)[off[j]];
+#pragma unroll
+  for (int j = 0; j < PE; ++j) {
+    const int le = (int)threadIdx.x + j * NT;
+    if (le < NE) {
+#pragma unroll
+      for (int k = 0; k < 36; ++k) El[k * NE + le] = v[j][k] * keep[j];
+    }
   }
 }
 
@@ -437,35 +448,35 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
 // Grid: (ceil(dc.nx1 / FCX), ceil(dc.ny1 / FCY)); d is level k, dc level k-1.
 // FROM_T: r is not read but restricted from the finest residual tf (grid df) in
 // the tile (DownLoads::load_restrict) and stored into rw for the up pass.
-template <typename T, class Op, bool FROM_T = false>
+template <typename T, class Op, bool FROM_T = false, int CX = FCX, int CY = FCY>
 __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
                                                 T* __restrict__ z2out, T* __restrict__ rc,
                                                 const double* __restrict__ omg, const int* gate, Dims df,
                                                 const T* __restrict__ tf, T* __restrict__ rw) {
   if (gate && *gate) return;
-  constexpr int W1 = 2 * FCX + 5, H1 = 2 * FCY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
   const Tile tl = xcd_tile();
-  DownLoads<T, FCX, FCY, FBS> pre;
-  if constexpr (FROM_T) pre.load_restrict(d, df, (int)tl.x * FCX, (int)tl.y * FCY, tf, rw);
-  else pre.load(d, (int)tl.x * FCX, (int)tl.y * FCY, r);
-  down_tile<T, Op, FCX, FCY, FBS>(op, d, dc, (int)tl.x * FCX, (int)tl.y * FCY, pre, z2out, rc, T(*omg), sr, sd, s1,
-                                  s2, s3);
+  DownLoads<T, CX, CY, FBS> pre;
+  if constexpr (FROM_T) pre.load_restrict(d, df, (int)tl.x * CX, (int)tl.y * CY, tf, rw);
+  else pre.load(d, (int)tl.x * CX, (int)tl.y * CY, r);
+  down_tile<T, Op, CX, CY, FBS>(op, d, dc, (int)tl.x * CX, (int)tl.y * CY, pre, z2out, rc, T(*omg), sr, sd, s1,
+                                s2, s3);
 }
 
 // Grid: (ceil(d.nx1 / FTX), ceil(d.ny1 / FTY)).
-template <typename T, class Op>
+template <typename T, class Op, int TX = FTX, int TY = FTY>
 __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
                                               const T* __restrict__ z2, const T* __restrict__ zc,
                                               T* __restrict__ out, const double* __restrict__ omg,
                                               const int* gate) {
   if (gate && *gate) return;
-  constexpr int W0 = FTX + 4, H0 = FTY + 4, W1 = FTX + 2, H1 = FTY + 2;
+  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
   const Tile tl = xcd_tile();
-  UpLoads<T, FTX, FTY, FBS> pre;
-  pre.load(d, dc, (int)tl.x * FTX, (int)tl.y * FTY, r, z2, zc);
-  up_tile<T, Op, FTX, FTY, FBS>(op, d, dc, (int)tl.x * FTX, (int)tl.y * FTY, pre, out, T(*omg), s0, sr, sd, s1);
+  UpLoads<T, TX, TY, FBS> pre;
+  pre.load(d, dc, (int)tl.x * TX, (int)tl.y * TY, r, z2, zc);
+  up_tile<T, Op, TX, TY, FBS>(op, d, dc, (int)tl.x * TX, (int)tl.y * TY, pre, out, T(*omg), s0, sr, sd, s1);
 }
 
 // Stored FP32 element matrices staged in LDS, tiles of CX x CY coarse nodes and NT

@@ -338,23 +338,27 @@ struct OpCoarse {
   const T* E;
   int64_t m;
   const T* ye = nullptr;
+  // Entry k of every element starts at the uniform address E + k m, so a load is
+  // that base plus the element's 32-bit offset (no per-load 64-bit arithmetic).
   __device__ inline void rows(int64_t e, int, int, int, int a, const T* ve, T* acc) const {
     constexpr int ND = Geo<DIM>::ND;
+    const uint32_t e32 = (uint32_t)e;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int r = a * DIM + c;
       T s = 0;
 #pragma unroll
-      for (int col = 0; col < ND; ++col) s += E[sym_index(r, col, ND) * m + e] * ve[col];
+      for (int col = 0; col < ND; ++col) s += (E + sym_index(r, col, ND) * m)[e32] * ve[col];
       acc[c] += s;
     }
   }
   __device__ inline void diag(int64_t e, int, int, int, int a, T* dg) const {
     constexpr int ND = Geo<DIM>::ND;
+    const uint32_t e32 = (uint32_t)e;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int r = a * DIM + c;
-      dg[c] += E[sym_index(r, r, ND) * m + e];
+      dg[c] += (E + sym_index(r, r, ND) * m)[e32];
     }
   }
   __device__ inline double entry(int64_t e, int r, int c) const {

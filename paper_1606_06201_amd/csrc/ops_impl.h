@@ -3,7 +3,9 @@
 #pragma once
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 #include "ctx.h"
 #include "kernels.h"
 #include "tail.h"
@@ -181,6 +183,35 @@ __global__ __launch_bounds__(BS) void k_filter(Dims d, double rmin, int R, const
         acc += transpose ? w * in[o] : w * in[o] / filter_colsum<DIM>(d, i, j, k, rmin, R);
       }
   out[e] = transpose ? acc / filter_colsum<DIM>(d, ei, ej, ek, rmin, R) : acc;
+}
+
+// Workgroups of a kernel (threads per group, static LDS) resident on one CU, from
+// HIP's occupancy calculator; cached per kernel.
+inline int resident_per_cu(const void* fn, int threads) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  IPMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0));
+  n = std::max(n, 1);
+  cache[fn] = n;
+  return n;
+}
+
+// Of two tilings of one fused pass (kernels fa, fb of FBS threads on grids ga, gb,
+// tiles of aa, ab nodes with their halos), true when the second is cheaper.  Tiles
+// are dealt out in rounds of (CUs x resident groups) and a round lasts about as long
+// as one tile, so the cost is rounds x tile size: a tile count just above a multiple
+// of the resident capacity would run a nearly empty last round.
+inline bool pick_tiles(const Ctx& c, const void* fa, dim3 ga, int aa, const void* fb, dim3 gb, int ab) {
+  auto cost = [&](const void* fn, dim3 g, int area) {
+    const int64_t slots = (int64_t)c.cus * resident_per_cu(fn, FBS);
+    const int64_t tiles = (int64_t)g.x * g.y;
+    return ((tiles + slots - 1) / slots) * (int64_t)area;
+  };
+  return cost(fb, gb, ab) < cost(fa, ga, aa);
 }
 
 // SIMP penalisation: xp = x~^p, and the chain-rule factor q_e = p x~_e^(p-1) E_e of
@@ -894,21 +925,33 @@ struct OpsImpl : Ops {
     if (lev == c.L - 2 && c.coarse_from_x) {
       const OpCoarse2K<2, T> op{(const T*)c.xT, c.fine().nx, c.fine().m};
       if (c.down_from_t) {   // restriction of the finest residual done in the tile
-        k_down2d<T, OpCoarse2K<2, T>, true><<<g, FBS, 0, c.stream>>>(
-            op, d, dc, nullptr, (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
-            (const T*)c.down_from_t, (T*)c.lev[lev].r);
+        down_global<T, OpCoarse2K<2, T>, true>(c, op, lev, nullptr, df, (const T*)c.down_from_t, (T*)c.lev[lev].r,
+                                               gate);
         c.down_from_t = nullptr;
       } else {
-        k_down2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(op, d, dc, (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
-                                                                (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
-                                                                nullptr, nullptr);
+        down_global<T, OpCoarse2K<2, T>, false>(c, op, lev, (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
       }
     } else {
-      k_down2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
-                                                             (const T*)c.lev[lev].r, (T*)c.lev[lev].z,
-                                                             (T*)c.lev[lev - 1].r, c.omega_dev + lev, gate, df,
-                                                             nullptr, nullptr);
+      down_global<T, OpCoarse<2, T>, false>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev,
+                                            (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
     }
+  }
+  // k_down2d on 16x8 or 16x9 coarse-node tiles, whichever runs fewer rounds x area
+  // (see pick_tiles).
+  template <typename T, class Op, bool FROM_T>
+  void down_global(Ctx& c, const Op& op, int lev, const T* r, const Dims& df, const T* tf, T* rw, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g8((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 7) / 8), 1);
+    const dim3 g9((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 8) / 9), 1);
+    const bool nine = pick_tiles(c, (const void*)k_down2d<T, Op, FROM_T, 16, 8>, g8, 37 * 21,
+                                 (const void*)k_down2d<T, Op, FROM_T, 16, 9>, g9, 37 * 23);
+    T* z = (T*)c.lev[lev].z;
+    T* rc = (T*)c.lev[lev - 1].r;
+    if (nine)
+      k_down2d<T, Op, FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf, rw);
+    else
+      k_down2d<T, Op, FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf, rw);
   }
   // The down pass of level lev (the first coarse level) restricts the finest
   // residual itself: the plain register-blocked fused pass for K formed from the
@@ -984,13 +1027,25 @@ struct OpsImpl : Ops {
       }
     }
     if (lev == c.L - 2 && c.coarse_from_x)
-      k_up2d<T, OpCoarse2K<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, d, dc,
-                                                             (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
-                                                             (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+      up_global<T>(c, OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, lev, zc, out, gate);
     else
-      k_up2d<T, OpCoarse<2, T>><<<g, FBS, 0, c.stream>>>(OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, d, dc,
-                                                           (const T*)c.lev[lev].r, (const T*)c.lev[lev].z,
-                                                           (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+      up_global<T>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev, zc, out, gate);
+  }
+  // k_up2d on 32x16 or 32x18 fine-node tiles (see pick_tiles).
+  template <typename T, class Op>
+  void up_global(Ctx& c, const Op& op, int lev, const void* zc, void* out, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g16((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 15) / 16), 1);
+    const dim3 g18((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 17) / 18), 1);
+    const bool tall = pick_tiles(c, (const void*)k_up2d<T, Op, 32, 16>, g16, 36 * 20,
+                                 (const void*)k_up2d<T, Op, 32, 18>, g18, 36 * 22);
+    const T* r = (const T*)c.lev[lev].r;
+    const T* z2 = (const T*)c.lev[lev].z;
+    if (tall)
+      k_up2d<T, Op, 32, 18><<<g18, FBS, 0, c.stream>>>(op, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev, gate);
+    else
+      k_up2d<T, Op, 32, 16><<<g16, FBS, 0, c.stream>>>(op, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev, gate);
   }
   void fused_down(Ctx& c, int lev, const int* gate) override {
     if constexpr (DIM == 2) {

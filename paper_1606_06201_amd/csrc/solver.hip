@@ -124,6 +124,11 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
     IPMG_REQUIRE(d.nel[a] % f == 0, IPMG_E_INVALID, "element counts must be divisible by 2^(levels-1)");
   }
   c.desc = d;
+  {
+    int dev = 0;
+    IPMG_HIP(hipGetDevice(&dev));
+    IPMG_HIP(hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   c.dim = d.dim;
   c.fp32 = d.vcycle_fp32 != 0;
   c.tsz = c.fp32 ? sizeof(float) : sizeof(double);
