@@ -45,14 +45,10 @@ KERNEL_NAMES = {
     "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4, true>: p = -y + beta p, q = K p (FP64), p'q, "
                  "and the previous step's z += alpha p_old",
     "pcg_update": "k_pcg_update<float, false>: r += alpha q (FP64), FP32 copy of r, ||r||^2",
-    "sub_down": "k_down2d<float, OpCoarse2K<2,float>, true>: first coarse level, its r = P' t from the finest "
-                "residual, two Jacobi sweeps, residual and restriction in one LDS-tiled pass",
-    "sub_up": "k_up2d_staged<true, 16, 8, 256>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
-              "pass, element matrices formed from the densities in LDS",
-    "fine_down": "k_down2d_fine<float>: finest level, two Jacobi sweeps, residual and restriction in one "
-                 "LDS-tiled pass",
-    "fine_up": "k_up2d_fine<float,true>: finest level, prolongation, two Jacobi sweeps and the PCG ratio "
-               "r~'y~ in one LDS-tiled pass",
+    "sub_down": "k_down2d_x<float, true, 16, 9>: first coarse level, its r = P' t from the finest residual, two "
+                "Jacobi sweeps, residual and restriction in one LDS-tiled pass (densities staged in LDS)",
+    "sub_up": "k_up2d_x<float, 32, 18>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
+              "pass (densities staged in LDS)",
 }
 
 
@@ -83,10 +79,6 @@ def class_bytes(nel, fp32, kind):
         return 2 * w * Nc + w * m + 2 * w * Nc + 2 * w * Nc2
     if kind == "sub_up":                        # read z2, r, coarse correction, fine x; write z
         return 3 * 2 * w * Nc + 2 * w * Nc2 + w * m
-    if kind == "fine_down":                     # read r, x; write z2, coarse residual
-        return 2 * w * N + w * m + 2 * w * N + 2 * w * Nc
-    if kind == "fine_up":                       # read z2, coarse correction, r, x, FP64 r; write z
-        return 3 * 2 * w * N + 2 * w * Nc + w * m + 2 * 8 * N
     fold = os.environ.get("IPMG_NO_FOLD_SOLUTION", "0") != "1"   # z += alpha p in the direction kernel
     if kind == "dir_apply":                     # read y, p_old; write p, q (FP64); read x (FP64)
         return 2 * N * (w + 3 * 8 + (2 * 8 if fold else 0)) + 8 * m     # (+ read, write z)

@@ -298,8 +298,7 @@ int ipmg_simp_compliance(ipmg_ctx* ctx, const double* x, const double* f, double
  *   6: last post-smoothing sweep on the finest level with the fused PCG ratio
  *   7: fused pre-smoothing, residual and restriction on the first coarse level
  *   8: fused prolongation and post-smoothing on the first coarse level
- *   9: fused pre-smoothing, residual and restriction on the finest level
- *  10: fused prolongation and post-smoothing on the finest level (with the PCG ratio)
+ *   9, 10: reserved (no kernel records them)
  *  11: prolongation folded into the first post-smoothing sweep on the finest level
  *  12: the first two pre-smoothing sweeps on the finest level in one pass
  *  13: 3D finest level, element products of a V-cycle pass (before its node pass)

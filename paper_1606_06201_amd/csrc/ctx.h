@@ -51,9 +51,6 @@ struct Ops {
   virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E64 of level lev_f-1
   virtual void dense_assemble(Ctx& c, int op, double* A, int n) = 0;
   virtual void power_start(Ctx& c, int lev, int aug, void* v) = 0;
-  // Levels 0..tail_top of the V-cycle in one single-workgroup launch:
-  // lev[tail_top].r -> lev[tail_top].z.
-  virtual void tail(Ctx& c, int op, const int* gate) = 0;
   // Fused passes of level lev (see fused2d.h): false when they do not apply.
   //   down: lev.r -> z2 (into z), coarse residual (into lev-1 .r)
   //   up:   z2 (in z), coarse correction zc -> out
@@ -62,8 +59,7 @@ struct Ops {
   // (passed in Ctx::down_from_t) instead of reading a restricted one.
   virtual bool down_restricts(const Ctx& c, int lev, int op) const = 0;
   virtual void fused_down(Ctx& c, int lev, const int* gate) = 0;
-  virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate,
-                        const double* beta64 = nullptr) = 0;
+  virtual void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) = 0;
   virtual void element_sens(Ctx& c, const double* w, const double* u, double scale, double* g) = 0;
   // 3D finest level: the diagonal of the hierarchy's operator per DOF slot (V-cycle
   // precision), formed once per set-up (no-op elsewhere)
@@ -94,21 +90,14 @@ struct Ctx {
   Ops* ops = nullptr;
   std::vector<Level> lev;      // lev[L-1] finest
   size_t tsz = 4;              // sizeof(T) of the V-cycle
-  int tail_top = -1;           // highest level handled by the single-workgroup tail (-1: none)
   bool coarse_from_x = true;   // 2D K: first coarse level evaluated from the fine densities
   bool tiled2d = true;         // 2D level passes with register-blocked tiles
   int64_t tiled_min_nodes = (int64_t)1 << 18;  // ... on levels with at least this many nodes
   int nj32 = 4, nj64 = 2, nj_dir = 4;          // nodes per thread of the tiled passes
-  bool fused2d = true;         // 2D K levels with stored operators: two fused launches per level
-  // ... and on the finest level: opt-in, measured slower there than the separate
-  // register-tiled passes (its barrier-separated phases do not hide memory latency)
-  bool fused_fine = false;
-  int cus = 256;                // compute units of the device
-  bool fine_small_tiles = false;  // finest-level fused passes on 256-thread tiles
-  bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32; stored levels
-  int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size, and the first coarse level)
-  bool staged_down_from_x = false;   // the first coarse level's down pass staged as well
-  bool staged_big = false;           // first coarse level: staged passes on the large tiles
+  bool fused2d = true;         // 2D K coarse levels: two fused launches per level
+  bool fused_staged = true;    // ... with the element matrices staged in LDS (FP32 stored levels
+  int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size)
+  int cus = 256;               // compute units of the device
   bool fold_solution = true;         // PCG solution update folded into the next direction kernel
   bool fold_rn2_fin = true;          // PCG ||r||^2 finalize done by the V-cycle's first pass
   bool fold_restrict = true;         // finest residual restricted inside the first coarse down pass
@@ -218,8 +207,7 @@ enum ProfClass {
   PC_FINE_JACOBI_BETA = 6,  // finest level, last sweep with the fused PCG ratio
   PC_SUB_DOWN = 7,          // first coarse level, fused pre-smoothing + residual + restriction
   PC_SUB_UP = 8,            // first coarse level, fused prolongation + post-smoothing
-  PC_FINE_DOWN = 9,         // finest level, fused pre-smoothing + residual + restriction
-  PC_FINE_UP = 10,          // finest level, fused prolongation + post-smoothing (+ PCG ratio)
+  // 9 and 10: reserved (no kernel records them)
   PC_FINE_PJACOBI = 11,     // finest level, prolongation folded into the first post-smoothing sweep
   PC_FINE_JACOBI2 = 12,     // finest level, the first two pre-smoothing sweeps in one pass
   PC_ELEM3 = 13,            // 3D finest level, element products of a V-cycle pass

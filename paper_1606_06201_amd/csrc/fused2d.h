@@ -7,24 +7,23 @@
 // each later step needs (recomputed by neighbouring tiles), so the two launches
 // replace seven on levels where a launch costs more than the work.  Arithmetic per
 // node is that of k_level (same operator rows, diagonal and reciprocal).
-//   k_down2d / k_up2d: any operator, read from global memory (16x8 coarse-node
-//     and 32x16 fine-node tiles, 1024 threads: every phase is one pass);
+//   k_down2d / k_up2d: stored operators read from global memory (16x8 or 16x9
+//     coarse-node and 32x16 or 32x18 fine-node tiles, 1024 threads: every phase is
+//     one pass);
+//   k_down2d_x / k_up2d_x: the first coarse level formed from the densities, the
+//     four densities of every element of the tile staged in LDS first;
 //   k_down2d_staged / k_up2d_staged: the FP32 element matrices of the tile's
-//     elements placed in LDS first (copied from the stored ones, or formed from the
-//     densities on the first coarse level), so the phases wait on LDS only and, on
-//     the first coarse level, each element matrix is formed once per tile instead
-//     of once per node evaluation (8x4 and 16x8 tiles, 256 threads).
+//     elements copied into LDS first, so the phases wait on LDS only (small stored
+//     levels; 8x4 and 16x8 tiles, 512 threads).
 #pragma once
 #include "kernels.h"
 
 namespace ipmg {
 
-constexpr int FCX = 16, FCY = 8;    // coarse nodes per k_down2d tile
-constexpr int FTX = 32, FTY = 16;   // fine nodes per k_up2d tile
 constexpr int FBS = 1024;           // every phase of a tile is one pass of the workgroup
 constexpr int SCX = 8, SCY = 4;     // coarse nodes per k_down2d_staged tile
 constexpr int STX = 16, STY = 8;    // fine nodes per k_up2d_staged tile
-constexpr int SBS = 256;
+constexpr int SBS_STORED = 512;     // threads of the staged passes: every phase one pass
 
 __device__ inline bool node_free(const Dims& d, int i, int j) { return i >= 1 && i < d.nx1 && j >= 0 && j < d.ny1; }
 
@@ -107,87 +106,54 @@ __device__ inline void stage_elements(const T* __restrict__ Eg, const Dims& d, i
   }
 }
 
-// Finest level, A_e = x_e K0, with the densities of a block of elements in LDS
-// (xl[le], le as in OpCoarseLDS) and the six K0 constants of the square element.
+// First coarse level formed from the finest densities, with the four densities of
+// each element of a block held in LDS (xl[q * ne + le], le as in OpCoarseLDS; zero
+// outside the grid), so the passes read no global memory for the operator.  The
+// element matrix sum_q x_q G_q is formed inside each node evaluation, as in
+// OpCoarse2K.
 template <typename T>
-struct OpFineKLDS {
+struct OpCoarse2KLDS : OpCoarse2K<2, T> {
   const T* xl;
   int ex0, ey0, lw, ne;
   __device__ inline int local(int ei, int ej) const {
     const int le = (ej - ey0) * lw + (ei - ex0);
     return le < 0 ? 0 : (le >= ne ? ne - 1 : le);
   }
-  __device__ inline void rows(int64_t, int ei, int ej, int, int a, const T* ve, T* acc) const {
-    const T xe = xl[local(ei, ej)];
+  __device__ inline void xs_or_zero(bool, int ei, int ej, T* xq) const {
+    const int le = local(ei, ej);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int col = 0; col < 8; ++col) s += k0sq<T>(2 * a + c, col) * ve[col];
-      acc[c] += xe * s;
-    }
-  }
-  __device__ inline void diag(int64_t, int ei, int ej, int, int a, T* dg) const {
-    const T xe = xl[local(ei, ej)];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) dg[c] += xe * k0sq<T>(2 * a + c, 2 * a + c);
+    for (int q = 0; q < 4; ++q) xq[q] = xl[q * ne + le];
   }
 };
+template <typename T>
+struct preloads_x<OpCoarse2KLDS<T>> : std::true_type {};
 
-// Densities of the elements [ex0, ex0+LW) x [ey0, ey0+LH) into LDS (zero outside:
-// those read the zero pad after the densities, index d.m, so no load is branched).
+// The four finest densities of the coarse elements [ex0, ex0+LW) x [ey0, ey0+LH)
+// into LDS as OpCoarse2KLDS reads them (outside the grid: the zero pad after the
+// densities, fine m = fnx * 2 ny).  One element per thread and pass, all loads
+// issued before the first LDS store.
 template <typename T, int NT, int LW, int LH>
-__device__ inline void stage_x(const T* __restrict__ x, const Dims& d, int ex0, int ey0, T* xl) {
-  constexpr int NE = LW * LH, PER = (NE + NT - 1) / NT;
-  T v[PER];
+__device__ inline void stage_x4(const T* __restrict__ x, int fnx, const Dims& d, int ex0, int ey0, T* xl) {
+  constexpr int NE = LW * LH, PE = (NE + NT - 1) / NT;
+  T v[PE][4];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int le = threadIdx.x + u * NT;
+  for (int j = 0; j < PE; ++j) {
+    const int le = min((int)threadIdx.x + j * NT, NE - 1);
     const int ei = ex0 + le % LW, ej = ey0 + le / LW;
-    const bool in = le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-    v[u] = x[in ? (int64_t)ej * d.nx + ei : d.m];
+    const bool in = ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
+    const uint32_t b = in ? (uint32_t)(2 * ej) * (uint32_t)fnx + (uint32_t)(2 * ei) : (uint32_t)fnx * 2u * (uint32_t)d.ny;
+    v[j][0] = x[b];
+    v[j][1] = x[b + 1];
+    v[j][2] = x[b + fnx];
+    v[j][3] = x[b + fnx + 1];
   }
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int le = threadIdx.x + u * NT;
-    if (le < NE) xl[le] = v[u];
-  }
-}
-
-// Element matrices of the first coarse level formed from the finest densities
-// (A_C = sum_q x_q G_q over the four fine sub-elements, Sec. 5.1 Galerkin product
-// of the x-scaled unit element) for the elements [ex0, ex0+LW) x [ey0, ey0+LH),
-// written to LDS packed as stage_elements does (zero outside the grid).  One
-// thread per element: four density loads, then 36 entries of 4 FMAs each with the
-// G_q constants.
-template <int NT, int LW, int LH>
-__device__ inline void stage_from_x(const float* __restrict__ x, int fnx, const Dims& d, int ex0, int ey0,
-                                    float* El) {
-  constexpr int NE = LW * LH, PER = (NE + NT - 1) / NT;
-  float xs[PER][4];
+  for (int j = 0; j < PE; ++j) {
+    const int le = (int)threadIdx.x + j * NT;
+    if (le < NE) {
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int le = threadIdx.x + u * NT;
-    const int ei = ex0 + le % LW, ej = ey0 + le / LW;
-    const bool in = le < NE && ei >= 0 && ei < d.nx && ej >= 0 && ej < d.ny;
-    // outside the grid: the zero pad after the fine densities (fine m = fnx * 2 ny)
-    const int64_t b = in ? (int64_t)(2 * ej) * fnx + 2 * ei : (int64_t)fnx * 2 * d.ny;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) xs[u][q] = x[b + (q >> 1) * fnx + (q & 1)];
-  }
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int le = threadIdx.x + u * NT;
-    if (le >= NE) continue;
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-      for (int c = r; c < 8; ++c) {
-        float s = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s += xs[u][q] * g2<float>(q * 64 + r * 8 + c);
-        El[sym_index(r, c, 8) * NE + le] = s;
-      }
+      for (int q = 0; q < 4; ++q) xl[q * NE + le] = v[j][q];
+    }
   }
 }
 
@@ -373,12 +339,9 @@ __device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, in
 // Up pass of one tile of TX x TY fine nodes with corner (I0, J0).  LDS: s0 over
 // region 0 ((TX+4) x (TY+4) nodes from (I0-2, J0-2)); sr, sd, s1 over region 1
 // (one node inside).
-// dot64 (optional): accumulate dot64' out over the tile's nodes into red0 (the
-// PCG ratio of the finest level, Algorithm PCG).
 template <typename T, class Op, int TX, int TY, int NT>
 __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0,
-                               const UpLoads<T, TX, TY, NT>& pre, T* out, T omega, T* s0, T* sr, T* sd, T* s1,
-                               const double* dot64 = nullptr, double* red0 = nullptr) {
+                               const UpLoads<T, TX, TY, NT>& pre, T* out, T omega, T* s0, T* sr, T* sd, T* s1) {
   constexpr int W0 = TX + 4, H0 = TY + 4;
   constexpr int W1 = TX + 2, H1 = TY + 2;
 #pragma unroll
@@ -439,33 +402,27 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
     }
-    const int64_t qn = (int64_t)gj * d.nx1 + gi;
-    store_node<2, T>(out, qn, o);
-    if (dot64) *red0 += dot64[2 * qn] * (double)o[0] + dot64[2 * qn + 1] * (double)o[1];
+    store_node<2, T>(out, (int64_t)gj * d.nx1 + gi, o);
   }
 }
 
-// Grid: (ceil(dc.nx1 / FCX), ceil(dc.ny1 / FCY)); d is level k, dc level k-1.
-// FROM_T: r is not read but restricted from the finest residual tf (grid df) in
-// the tile (DownLoads::load_restrict) and stored into rw for the up pass.
-template <typename T, class Op, bool FROM_T = false, int CX = FCX, int CY = FCY>
+// Grid: (ceil(dc.nx1 / CX), ceil(dc.ny1 / CY)); d is level k, dc level k-1.
+template <typename T, class Op, int CX, int CY>
 __global__ __launch_bounds__(FBS) void k_down2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
                                                 T* __restrict__ z2out, T* __restrict__ rc,
-                                                const double* __restrict__ omg, const int* gate, Dims df,
-                                                const T* __restrict__ tf, T* __restrict__ rw) {
+                                                const double* __restrict__ omg, const int* gate) {
   if (gate && *gate) return;
   constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
   const Tile tl = xcd_tile();
   DownLoads<T, CX, CY, FBS> pre;
-  if constexpr (FROM_T) pre.load_restrict(d, df, (int)tl.x * CX, (int)tl.y * CY, tf, rw);
-  else pre.load(d, (int)tl.x * CX, (int)tl.y * CY, r);
+  pre.load(d, (int)tl.x * CX, (int)tl.y * CY, r);
   down_tile<T, Op, CX, CY, FBS>(op, d, dc, (int)tl.x * CX, (int)tl.y * CY, pre, z2out, rc, T(*omg), sr, sd, s1,
                                 s2, s3);
 }
 
-// Grid: (ceil(d.nx1 / FTX), ceil(d.ny1 / FTY)).
-template <typename T, class Op, int TX = FTX, int TY = FTY>
+// Grid: (ceil(d.nx1 / TX), ceil(d.ny1 / TY)).
+template <typename T, class Op, int TX, int TY>
 __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* __restrict__ r,
                                               const T* __restrict__ z2, const T* __restrict__ zc,
                                               T* __restrict__ out, const double* __restrict__ omg,
@@ -479,18 +436,71 @@ __global__ __launch_bounds__(FBS) void k_up2d(Op op, Dims d, Dims dc, const T* _
   up_tile<T, Op, TX, TY, FBS>(op, d, dc, (int)tl.x * TX, (int)tl.y * TY, pre, out, T(*omg), s0, sr, sd, s1);
 }
 
+// k_down2d / k_up2d on the first coarse level formed from the densities, with the
+// tile's densities staged in LDS first (OpCoarse2KLDS).  x: finest densities with
+// their zero pad, fnx finest elements along x.
+template <typename T, bool FROM_T, int CX, int CY>
+__global__ __launch_bounds__(FBS) void k_down2d_x(const T* __restrict__ x, int fnx, Dims d, Dims dc,
+                                                  const T* __restrict__ r, T* __restrict__ z2out, T* __restrict__ rc,
+                                                  const double* __restrict__ omg, const int* gate, Dims df,
+                                                  const T* __restrict__ tf, T* __restrict__ rw) {
+  if (gate && *gate) return;
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ T xl[4 * LW * LH];
+  __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
+  const Tile tl = xcd_tile();
+  const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
+  const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
+  DownLoads<T, CX, CY, FBS> pre;
+  if constexpr (FROM_T) pre.load_restrict(d, df, CI0, CJ0, tf, rw);
+  else pre.load(d, CI0, CJ0, r);
+  stage_x4<T, FBS, LW, LH>(x, fnx, d, ex0, ey0, xl);
+  __syncthreads();
+  OpCoarse2KLDS<T> op;
+  op.xl = xl;
+  op.ex0 = ex0;
+  op.ey0 = ey0;
+  op.lw = LW;
+  op.ne = LW * LH;
+  down_tile<T, OpCoarse2KLDS<T>, CX, CY, FBS>(op, d, dc, CI0, CJ0, pre, z2out, rc, T(*omg), sr, sd, s1, s2, s3);
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(FBS) void k_up2d_x(const T* __restrict__ x, int fnx, Dims d, Dims dc,
+                                                const T* __restrict__ r, const T* __restrict__ z2,
+                                                const T* __restrict__ zc, T* __restrict__ out,
+                                                const double* __restrict__ omg, const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  __shared__ T xl[4 * LW * LH];
+  __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
+  const Tile tl = xcd_tile();
+  const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
+  const int ex0 = I0 - 2, ey0 = J0 - 2;
+  UpLoads<T, TX, TY, FBS> pre;
+  pre.load(d, dc, I0, J0, r, z2, zc);
+  stage_x4<T, FBS, LW, LH>(x, fnx, d, ex0, ey0, xl);
+  __syncthreads();
+  OpCoarse2KLDS<T> op;
+  op.xl = xl;
+  op.ex0 = ex0;
+  op.ey0 = ey0;
+  op.lw = LW;
+  op.ne = LW * LH;
+  up_tile<T, OpCoarse2KLDS<T>, TX, TY, FBS>(op, d, dc, I0, J0, pre, out, T(*omg), s0, sr, sd, s1);
+}
+
 // Stored FP32 element matrices staged in LDS, tiles of CX x CY coarse nodes and NT
 // threads.  Grid: (ceil(dc.nx1 / CX), ceil(dc.ny1 / CY)).  Region 1 of a tile has
 // nodes (2CI0-3 .. 2CI0+2CX+1); the elements around them are
 // (2CI0-4 .. 2CI0+2CX+1) x (2CJ0-4 .. 2CJ0+2CY+1).
-// FROM_X: the level is the first coarse level formed from the densities x (fnx
-// finest elements along x) instead of stored matrices Eg.  Large tiles (more than
-// 64 KB of LDS, one workgroup per CU) form fewer halo elements twice.
-template <bool FROM_X, int CX = SCX, int CY = SCY, int NT = SBS>
-__global__ __launch_bounds__(NT) void k_down2d_staged(const float* __restrict__ Eg, const float* __restrict__ x,
-                                                      int fnx, Dims d, Dims dc, const float* __restrict__ r,
-                                                      float* __restrict__ z2out, float* __restrict__ rc,
-                                                      const double* __restrict__ omg, const int* gate) {
+template <int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) void k_down2d_staged(const float* __restrict__ Eg, Dims d, Dims dc,
+                                                      const float* __restrict__ r, float* __restrict__ z2out,
+                                                      float* __restrict__ rc, const double* __restrict__ omg,
+                                                      const int* gate) {
   if (gate && *gate) return;
   constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
   constexpr int LW = W1 + 1, LH = H1 + 1;
@@ -501,8 +511,7 @@ __global__ __launch_bounds__(NT) void k_down2d_staged(const float* __restrict__ 
   const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
   DownLoads<float, CX, CY, NT> pre;
   pre.load(d, CI0, CJ0, r);
-  if constexpr (FROM_X) stage_from_x<NT, LW, LH>(x, fnx, d, ex0, ey0, El);
-  else stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
+  stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
   __syncthreads();
   const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
   down_tile<float, OpCoarseLDS<float>, CX, CY, NT>(op, d, dc, CI0, CJ0, pre, z2out, rc, float(*omg), sr, sd, s1, s2,
@@ -512,12 +521,11 @@ __global__ __launch_bounds__(NT) void k_down2d_staged(const float* __restrict__ 
 // Tiles of TX x TY fine nodes and NT threads.  Grid: (ceil(d.nx1 / TX),
 // ceil(d.ny1 / TY)).  Region 1 has nodes (I0-1 .. I0+TX); the elements around them
 // are (I0-2 .. I0+TX) x (J0-2 .. J0+TY).
-template <bool FROM_X, int TX = STX, int TY = STY, int NT = SBS>
-__global__ __launch_bounds__(NT) void k_up2d_staged(const float* __restrict__ Eg, const float* __restrict__ x, int fnx,
-                                                    Dims d, Dims dc, const float* __restrict__ r,
-                                                    const float* __restrict__ z2, const float* __restrict__ zc,
-                                                    float* __restrict__ out, const double* __restrict__ omg,
-                                                    const int* gate) {
+template <int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_up2d_staged(const float* __restrict__ Eg, Dims d, Dims dc,
+                                                    const float* __restrict__ r, const float* __restrict__ z2,
+                                                    const float* __restrict__ zc, float* __restrict__ out,
+                                                    const double* __restrict__ omg, const int* gate) {
   if (gate && *gate) return;
   constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int LW = W1 + 1, LH = H1 + 1;
@@ -528,67 +536,10 @@ __global__ __launch_bounds__(NT) void k_up2d_staged(const float* __restrict__ Eg
   const int ex0 = I0 - 2, ey0 = J0 - 2;
   UpLoads<float, TX, TY, NT> pre;
   pre.load(d, dc, I0, J0, r, z2, zc);
-  if constexpr (FROM_X) stage_from_x<NT, LW, LH>(x, fnx, d, ex0, ey0, El);
-  else stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
+  stage_elements<float, NT, LW, LH>(Eg, d, ex0, ey0, El);
   __syncthreads();
   const OpCoarseLDS<float> op{El, ex0, ey0, LW, LW * LH};
   up_tile<float, OpCoarseLDS<float>, TX, TY, NT>(op, d, dc, I0, J0, pre, out, float(*omg), s0, sr, sd, s1);
-}
-
-// Finest level of K (densities x, V-cycle precision T), tiles of CX x CY coarse
-// nodes and NT threads.  Grid: (ceil(dc.nx1 / CX), ceil(dc.ny1 / CY)).  The
-// elements around region 1 are (2CI0-4 .. 2CI0+2CX+1) x (2CJ0-4 .. 2CJ0+2CY+1).
-template <typename T, int CX, int CY, int NT>
-__global__ __launch_bounds__(NT) void k_down2d_fine(const T* __restrict__ x, Dims d, Dims dc,
-                                                    const T* __restrict__ r, T* __restrict__ z2out,
-                                                    T* __restrict__ rc, const double* __restrict__ omg,
-                                                    const int* gate) {
-  if (gate && *gate) return;
-  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
-  constexpr int LW = W1 + 1, LH = H1 + 1;
-  __shared__ T xl[LW * LH];
-  __shared__ T sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
-  const Tile tl = xcd_tile();
-  const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
-  const int ex0 = 2 * CI0 - 4, ey0 = 2 * CJ0 - 4;
-  DownLoads<T, CX, CY, NT> pre;
-  pre.load(d, CI0, CJ0, r);
-  stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
-  __syncthreads();
-  const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
-  down_tile<T, OpFineKLDS<T>, CX, CY, NT>(op, d, dc, CI0, CJ0, pre, z2out, rc, T(*omg), sr, sd, s1, s2, s3);
-}
-
-// Tiles of TX x TY fine nodes, NT threads.  Grid: (ceil(d.nx1 / TX), ceil(d.ny1 /
-// TY)).  Elements (I0-2 .. I0+TX) x (J0-2 .. J0+TY).  BETA: block partials of
-// dot64' out (the PCG ratio r~'y~ with the FP64 residual dot64), summed by
-// k_level_fin<T, M_JACOBI_BETA>.
-template <typename T, bool BETA, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_up2d_fine(const T* __restrict__ x, Dims d, Dims dc,
-                                                   const T* __restrict__ r, const T* __restrict__ z2,
-                                                   const T* __restrict__ zc, T* __restrict__ out,
-                                                   const double* __restrict__ omg, const double* __restrict__ dot64,
-                                                   Red red, const int* gate) {
-  if (gate && *gate) return;
-  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-  constexpr int LW = W1 + 1, LH = H1 + 1;
-  __shared__ T xl[LW * LH];
-  __shared__ T s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
-  const Tile tl = xcd_tile();
-  const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
-  const int ex0 = I0 - 2, ey0 = J0 - 2;
-  UpLoads<T, TX, TY, NT> pre;
-  pre.load(d, dc, I0, J0, r, z2, zc);
-  stage_x<T, NT, LW, LH>(x, d, ex0, ey0, xl);
-  __syncthreads();
-  const OpFineKLDS<T> op{xl, ex0, ey0, LW, LW * LH};
-  double red0 = 0.0;
-  up_tile<T, OpFineKLDS<T>, TX, TY, NT>(op, d, dc, I0, J0, pre, out, T(*omg), s0, sr, sd, s1,
-                                        BETA ? dot64 : nullptr, &red0);
-  if constexpr (BETA) {
-    const double vals[1] = {red0};
-    block_partials<1, false, NT>(vals, red);
-  }
 }
 
 }  // namespace ipmg

@@ -8,7 +8,6 @@
 #include <unordered_map>
 #include "ctx.h"
 #include "kernels.h"
-#include "tail.h"
 #include "fused2d.h"
 
 namespace ipmg {
@@ -869,167 +868,110 @@ struct OpsImpl : Ops {
     if constexpr (DIM != 2) {
       return false;
     } else {
-      // The first coarse level formed from the densities is VALU-bound: fused (with
-      // its recomputed halos) it pays in FP32 only.
+      // Coarse levels only (the finest level's separate register-blocked passes are
+      // faster).  The first coarse level formed from the densities is VALU-bound:
+      // fused (with its recomputed halos) it pays in FP32 only.
       const bool from_x = lev == c.L - 2 && c.coarse_from_x;
-      const bool fine = lev == c.L - 1;
       return c.fused2d && op == IPMG_OP_K && c.desc.nu_pre == 2 && c.desc.nu_post == 2 && lev >= 1 &&
-             lev > c.tail_top && (!from_x || c.fp32) && (!fine || c.fused_fine);
+             lev < c.L - 1 && (!from_x || c.fp32);
     }
   }
+  // Down pass of a fused coarse level: the first coarse level formed from the
+  // densities (k_down2d_x, densities staged in LDS); stored levels below 2^16 nodes
+  // with their FP32 element matrices staged in LDS (k_down2d_staged); larger stored
+  // levels reading the matrices from global memory (k_down2d).
   template <typename T>
   void fused_down_t(Ctx& c, int lev, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
-    if (lev == c.L - 1) {
-      ProfScope ps(c, PC_FINE_DOWN);
-      if (c.fine_small_tiles) {
-        const dim3 g((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
-        k_down2d_fine<T, SCX, SCY, SBS><<<g, SBS, 0, c.stream>>>((const T*)c.xT, d, dc, (const T*)c.lev[lev].r,
-                                                                 (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r,
-                                                                 c.omega_dev + lev, gate);
+    const Dims& df = c.fine();
+    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
+    if (lev == c.L - 2 && c.coarse_from_x) {
+      if (c.down_from_t) {   // restriction of the finest residual done in the tile
+        down_x<T, true>(c, lev, nullptr, df, (const T*)c.down_from_t, (T*)c.lev[lev].r, gate);
+        c.down_from_t = nullptr;
       } else {
-        const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
-        k_down2d_fine<T, FCX, FCY, FBS><<<g, FBS, 0, c.stream>>>((const T*)c.xT, d, dc, (const T*)c.lev[lev].r,
-                                                                 (T*)c.lev[lev].z, (T*)c.lev[lev - 1].r,
-                                                                 c.omega_dev + lev, gate);
+        down_x<T, false>(c, lev, (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
       }
       return;
     }
-    const dim3 g((unsigned)((dc.nx1 + FCX - 1) / FCX), (unsigned)((dc.ny1 + FCY - 1) / FCY), 1);
-    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
     if constexpr (std::is_same<T, float>::value) {
-      // measured: the down pass of the first coarse level is faster unstaged (its
-      // small staged tiles form each halo element matrix again)
-      const bool from_x = lev == c.L - 2 && c.coarse_from_x;
-      if (c.fused_staged && from_x && c.staged_big) {
-        k_down2d_staged<true, FCX, FCY, FBS><<<g, FBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
-                                                                     (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
-                                                                     (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
-        return;
-      }
-      if (c.fused_staged && ((!from_x && d.nnodes < c.staged_max_nodes) || (from_x && c.staged_down_from_x))) {
+      if (c.fused_staged && d.nnodes < c.staged_max_nodes) {
         const dim3 gs((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
-        if (from_x)
-          k_down2d_staged<true><<<gs, SBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
-                                                          (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
-                                                          (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
-        else
-          k_down2d_staged<false><<<gs, SBS, 0, c.stream>>>((const float*)c.lev[lev].E, nullptr, 0, d, dc,
-                                                           (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
-                                                           (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
+        k_down2d_staged<SCX, SCY, SBS_STORED><<<gs, SBS_STORED, 0, c.stream>>>(
+            (const float*)c.lev[lev].E, d, dc, (const float*)c.lev[lev].r, (float*)c.lev[lev].z,
+            (float*)c.lev[lev - 1].r, c.omega_dev + lev, gate);
         return;
       }
     }
-    const Dims& df = c.fine();
-    if (lev == c.L - 2 && c.coarse_from_x) {
-      const OpCoarse2K<2, T> op{(const T*)c.xT, c.fine().nx, c.fine().m};
-      if (c.down_from_t) {   // restriction of the finest residual done in the tile
-        down_global<T, OpCoarse2K<2, T>, true>(c, op, lev, nullptr, df, (const T*)c.down_from_t, (T*)c.lev[lev].r,
-                                               gate);
-        c.down_from_t = nullptr;
-      } else {
-        down_global<T, OpCoarse2K<2, T>, false>(c, op, lev, (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
-      }
-    } else {
-      down_global<T, OpCoarse<2, T>, false>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev,
-                                            (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
-    }
+    down_global<T>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev, gate);
   }
   // k_down2d on 16x8 or 16x9 coarse-node tiles, whichever runs fewer rounds x area
   // (see pick_tiles).
-  template <typename T, class Op, bool FROM_T>
-  void down_global(Ctx& c, const Op& op, int lev, const T* r, const Dims& df, const T* tf, T* rw, const int* gate) {
+  template <typename T, class Op>
+  void down_global(Ctx& c, const Op& op, int lev, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g8((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 7) / 8), 1);
     const dim3 g9((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 8) / 9), 1);
-    const bool nine = pick_tiles(c, (const void*)k_down2d<T, Op, FROM_T, 16, 8>, g8, 37 * 21,
-                                 (const void*)k_down2d<T, Op, FROM_T, 16, 9>, g9, 37 * 23);
+    const bool nine = pick_tiles(c, (const void*)k_down2d<T, Op, 16, 8>, g8, 37 * 21,
+                                 (const void*)k_down2d<T, Op, 16, 9>, g9, 37 * 23);
+    const T* r = (const T*)c.lev[lev].r;
+    T* z = (T*)c.lev[lev].z;
+    T* rc = (T*)c.lev[lev - 1].r;
+    if (nine) k_down2d<T, Op, 16, 9><<<g9, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate);
+    else k_down2d<T, Op, 16, 8><<<g8, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate);
+  }
+  // k_down2d_x on 16x8 or 16x9 coarse-node tiles (see pick_tiles).
+  template <typename T, bool FROM_T>
+  void down_x(Ctx& c, int lev, const T* r, const Dims& df, const T* tf, T* rw, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g8((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 7) / 8), 1);
+    const dim3 g9((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 8) / 9), 1);
+    const bool nine = pick_tiles(c, (const void*)k_down2d_x<T, FROM_T, 16, 8>, g8, 37 * 21,
+                                 (const void*)k_down2d_x<T, FROM_T, 16, 9>, g9, 37 * 23);
+    const T* x = (const T*)c.xT;
+    const int fnx = c.fine().nx;
     T* z = (T*)c.lev[lev].z;
     T* rc = (T*)c.lev[lev - 1].r;
     if (nine)
-      k_down2d<T, Op, FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf, rw);
+      k_down2d_x<T, FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf,
+                                                             rw);
     else
-      k_down2d<T, Op, FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf, rw);
+      k_down2d_x<T, FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf,
+                                                             rw);
   }
-  // The down pass of level lev (the first coarse level) restricts the finest
-  // residual itself: the plain register-blocked fused pass for K formed from the
-  // densities, in FP32 (the other variants read the restricted residual).
+  // The down pass of level lev (the first coarse level formed from the densities,
+  // FP32) restricts the finest residual itself.
   bool down_restricts(const Ctx& c, int lev, int op) const override {
     if constexpr (DIM != 2) {
       return false;
     } else {
       return c.fold_restrict && c.fp32 && op == IPMG_OP_K && lev == c.L - 2 && c.coarse_from_x &&
-             fused_applies(c, lev, op) && !(c.fused_staged && (c.staged_big || c.staged_down_from_x));
+             fused_applies(c, lev, op);
     }
   }
+  // Up pass of a fused coarse level (the kernels as in fused_down_t).
   template <typename T>
-  void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate, const double* beta64) {
+  void fused_up_t(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
-    if (lev == c.L - 1) {
-      const int tx = c.fine_small_tiles ? STX : FTX, ty = c.fine_small_tiles ? STY : FTY;
-      const dim3 g((unsigned)((d.nx1 + tx - 1) / tx), (unsigned)((d.ny1 + ty - 1) / ty), 1);
-      IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
-      {
-        ProfScope ps(c, PC_FINE_UP);
-        const T* xr = (const T*)c.xT;
-        const T* rr = (const T*)c.lev[lev].r;
-        const T* z2 = (const T*)c.lev[lev].z;
-        const double* w = c.omega_dev + lev;
-        if (c.fine_small_tiles) {
-          if (beta64)
-            k_up2d_fine<T, true, STX, STY, SBS><<<g, SBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out, w,
-                                                                         beta64, c.red, gate);
-          else
-            k_up2d_fine<T, false, STX, STY, SBS><<<g, SBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out,
-                                                                          w, nullptr, c.red, gate);
-        } else {
-          if (beta64)
-            k_up2d_fine<T, true, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out, w,
-                                                                         beta64, c.red, gate);
-          else
-            k_up2d_fine<T, false, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(xr, d, dc, rr, z2, (const T*)zc, (T*)out,
-                                                                          w, nullptr, c.red, gate);
-        }
-      }
-      if (beta64)
-        k_level_fin<T, M_JACOBI_BETA><<<1, BS, 0, c.stream>>>((const T*)out, (const T*)c.lev[lev].r, (T*)out,
-                                                              c.omega_dev + lev, 0, 0.0, d.nslots, beta64, c.red,
-                                                              g.x * g.y, 0, -1, gate, c.take_flag_dst());
+    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
+    if (lev == c.L - 2 && c.coarse_from_x) {
+      up_x<T>(c, lev, zc, out, gate);
       return;
     }
-    const dim3 g((unsigned)((d.nx1 + FTX - 1) / FTX), (unsigned)((d.ny1 + FTY - 1) / FTY), 1);
-    ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
     if constexpr (std::is_same<T, float>::value) {
-      const bool from_x = lev == c.L - 2 && c.coarse_from_x;
-      if (c.fused_staged && from_x && c.staged_big) {
-        k_up2d_staged<true, FTX, FTY, FBS><<<g, FBS, 0, c.stream>>>(nullptr, (const float*)c.xT, c.fine().nx, d, dc,
-                                                                   (const float*)c.lev[lev].r,
-                                                                   (const float*)c.lev[lev].z, (const float*)zc,
-                                                                   (float*)out, c.omega_dev + lev, gate);
-        return;
-      }
-      if (c.fused_staged && (from_x || d.nnodes < c.staged_max_nodes)) {
+      if (c.fused_staged && d.nnodes < c.staged_max_nodes) {
         const dim3 gs((unsigned)((d.nx1 + STX - 1) / STX), (unsigned)((d.ny1 + STY - 1) / STY), 1);
-        const float* E = (const float*)c.lev[lev].E;
-        const float* x = (const float*)c.xT;
-        if (from_x)
-          k_up2d_staged<true><<<gs, SBS, 0, c.stream>>>(E, x, c.fine().nx, d, dc, (const float*)c.lev[lev].r,
-                                                        (const float*)c.lev[lev].z, (const float*)zc, (float*)out,
-                                                        c.omega_dev + lev, gate);
-        else
-          k_up2d_staged<false><<<gs, SBS, 0, c.stream>>>(E, x, c.fine().nx, d, dc, (const float*)c.lev[lev].r,
-                                                         (const float*)c.lev[lev].z, (const float*)zc, (float*)out,
-                                                         c.omega_dev + lev, gate);
+        k_up2d_staged<STX, STY, SBS_STORED><<<gs, SBS_STORED, 0, c.stream>>>(
+            (const float*)c.lev[lev].E, d, dc, (const float*)c.lev[lev].r, (const float*)c.lev[lev].z,
+            (const float*)zc, (float*)out, c.omega_dev + lev, gate);
         return;
       }
     }
-    if (lev == c.L - 2 && c.coarse_from_x)
-      up_global<T>(c, OpCoarse2K<2, T>{(const T*)c.xT, c.fine().nx, c.fine().m}, lev, zc, out, gate);
-    else
-      up_global<T>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev, zc, out, gate);
+    up_global<T>(c, OpCoarse<2, T>{(const T*)c.lev[lev].E, d.m}, lev, zc, out, gate);
   }
   // k_up2d on 32x16 or 32x18 fine-node tiles (see pick_tiles).
   template <typename T, class Op>
@@ -1047,16 +989,36 @@ struct OpsImpl : Ops {
     else
       k_up2d<T, Op, 32, 16><<<g16, FBS, 0, c.stream>>>(op, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev, gate);
   }
+  // k_up2d_x on 32x16 or 32x18 fine-node tiles (see pick_tiles).
+  template <typename T>
+  void up_x(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
+    const Dims& d = c.lev[lev].d;
+    const Dims& dc = c.lev[lev - 1].d;
+    const dim3 g16((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 15) / 16), 1);
+    const dim3 g18((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 17) / 18), 1);
+    const bool tall = pick_tiles(c, (const void*)k_up2d_x<T, 32, 16>, g16, 36 * 20,
+                                 (const void*)k_up2d_x<T, 32, 18>, g18, 36 * 22);
+    const T* x = (const T*)c.xT;
+    const int fnx = c.fine().nx;
+    const T* r = (const T*)c.lev[lev].r;
+    const T* z2 = (const T*)c.lev[lev].z;
+    if (tall)
+      k_up2d_x<T, 32, 18><<<g18, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev,
+                                                     gate);
+    else
+      k_up2d_x<T, 32, 16><<<g16, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev,
+                                                     gate);
+  }
   void fused_down(Ctx& c, int lev, const int* gate) override {
     if constexpr (DIM == 2) {
       if (c.fp32) fused_down_t<float>(c, lev, gate);
       else fused_down_t<double>(c, lev, gate);
     }
   }
-  void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate, const double* beta64) override {
+  void fused_up(Ctx& c, int lev, const void* zc, void* out, const int* gate) override {
     if constexpr (DIM == 2) {
-      if (c.fp32) fused_up_t<float>(c, lev, zc, out, gate, beta64);
-      else fused_up_t<double>(c, lev, zc, out, gate, beta64);
+      if (c.fp32) fused_up_t<float>(c, lev, zc, out, gate);
+      else fused_up_t<double>(c, lev, zc, out, gate);
     }
   }
 
@@ -1093,44 +1055,6 @@ struct OpsImpl : Ops {
       k_dense_assemble<DIM, OpCoarse<DIM, double>, double><<<g, BS, 0, c.stream>>>(
           OpCoarse<DIM, double>{c.lev[0].E64, d.m}, d, c.lev[0].bZ64, c.cZ, aug, A, n);
     }
-  }
-
-  template <typename T, class TopOp>
-  void launch_tail(Ctx& c, const TopOp& top, int top_is_fine, int op, const int* gate) {
-    TailArgs<T> a{};
-    a.nt = c.tail_top + 1;
-    int off = 0;
-    for (int k = 0; k < a.nt; ++k) {
-      TailLev<T>& L = a.lv[k];
-      L.d = c.lev[k].d;
-      L.E = (const T*)c.lev[k].E;
-      L.b = op == IPMG_OP_Z ? (const T*)c.lev[k].bZ : nullptr;
-      L.omg = c.omega_dev + k;
-      L.off = off;
-      off += 3 * (int)(L.d.nslots + 1);
-    }
-    a.rin = (const T*)c.lev[c.tail_top].r;
-    a.zout = (T*)c.lev[c.tail_top].z;
-    a.Ainv = c.dAi;
-    a.n0 = (int)c.lev[0].d.nslots + (op == IPMG_OP_Z ? 1 : 0);
-    a.c = c.cZ;
-    a.aug = op == IPMG_OP_Z;
-    a.nu1 = c.desc.nu_pre;
-    a.nu2 = c.desc.nu_post;
-    const size_t lds = sizeof(T) * (size_t)off;
-    k_tail<DIM, T, TopOp><<<1, TAIL_THREADS, lds, c.stream>>>(top, top_is_fine, a, gate);
-  }
-  template <typename T>
-  void tail_t(Ctx& c, int op, const int* gate) {
-    const bool fine = c.tail_top == c.L - 1;
-    const Dims& d = c.fine();
-    if (fine && op == IPMG_OP_K) launch_tail<T>(c, OpFineK<DIM, T>{(const T*)c.xT, d.m}, 1, op, gate);
-    else if (fine) launch_tail<T>(c, OpFineZ<DIM, T>{(const T*)c.xT, (const T*)c.hT, d.m}, 1, op, gate);
-    else launch_tail<T>(c, OpCoarse<DIM, T>{nullptr, 0}, 0, op, gate);
-  }
-  void tail(Ctx& c, int op, const int* gate) override {
-    if (c.fp32) tail_t<float>(c, op, gate);
-    else tail_t<double>(c, op, gate);
   }
 
   void power_start(Ctx& c, int lev, int aug, void* v) override {

@@ -143,17 +143,11 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   }
   const Dims& fd = c.fine();
   IPMG_REQUIRE(fd.nslots < ((int64_t)1 << 31), IPMG_E_INVALID, "grid too large");
-  // Coarse tail (single-workgroup V-cycle of the lowest levels whose three vectors
-  // fit in 64 KB of LDS): opt-in with IPMG_TAIL=1.  Measured on MI355X it does not
-  // beat separate launches when the coarsest dense inverse is large (one CU reads
-  // it), so the default keeps one launch per pass.
   if (const char* e = std::getenv("IPMG_STORED_COARSE")) c.coarse_from_x = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNTILED")) c.tiled2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNFUSED")) c.fused2d = e[0] != '1';
   if (const char* e = std::getenv("IPMG_UNSTAGED")) c.fused_staged = e[0] != '1';
   if (const char* e = std::getenv("IPMG_STAGED_MAX_NODES")) c.staged_max_nodes = std::max<int64_t>(0, std::atoll(e));
-  if (const char* e = std::getenv("IPMG_STAGED_DOWN_FROM_X")) c.staged_down_from_x = e[0] == '1';
-  if (const char* e = std::getenv("IPMG_STAGED_BIG")) c.staged_big = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_PROLONG")) c.fold_prolong = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_SOLUTION")) c.fold_solution = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_FOLD_RN2")) c.fold_rn2_fin = e[0] != '1';
@@ -162,25 +156,12 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_ELEM_APPLY3")) c.elem_apply3 = e[0] != '1';
   if (const char* e = std::getenv("IPMG_ELEM_APPLY3_MIN")) c.elem_apply3_min = std::max<int64_t>(0, std::atoll(e));
   if (const char* e = std::getenv("IPMG_NO_ELEM_FINE3")) c.elem_fine3 = e[0] != '1';
-  if (const char* e = std::getenv("IPMG_FUSED_FINE")) c.fused_fine = e[0] == '1';
-  if (const char* e = std::getenv("IPMG_FINE_SMALL_TILES")) c.fine_small_tiles = e[0] == '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);
   c.power_steps = POWER_STEPS;
   c.power_steps_z = POWER_STEPS_Z;
   if (const char* e = std::getenv("IPMG_TILED_MIN_NODES")) c.tiled_min_nodes = std::max<int64_t>(0, std::atoll(e));
-  c.tail_top = -1;
-  if (const char* e = std::getenv("IPMG_TAIL")) {
-    if (e[0] == '1') {
-      size_t lds = 0;
-      for (int k = 0; k < c.L && k < 12; ++k) {
-        lds += 3 * c.tsz * ((size_t)c.lev[k].d.nslots + 1);
-        if (lds > 64 * 1024 - 512 || c.lev[k].d.nnodes > 4096) break;
-        c.tail_top = k;
-      }
-    }
-  }
   c.ncoarse = (int)std::min<int64_t>(c.lev[0].d.nslots + 1, (int64_t)1 << 30);
 
   // reductions
@@ -394,13 +375,7 @@ static void rn2_fin_flush(Ctx& c, const int* gate) {
 static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* beta64) {
   Level& l = c.lev[k];
   const int aug = op == IPMG_OP_Z;
-  if (c.rn2_fin_blocks &&
-      (k == c.tail_top || k == 0 || c.ops->fused_applies(c, k, op) || c.desc.nu_pre < 2))
-    rn2_fin_flush(c, gate);
-  if (k == c.tail_top) {
-    c.ops->tail(c, op, gate);
-    return l.z;
-  }
+  if (c.rn2_fin_blocks && (k == 0 || c.ops->fused_applies(c, k, op) || c.desc.nu_pre < 2)) rn2_fin_flush(c, gate);
   if (k == 0) {
     const int n = l.d.nslots + aug;
     if (c.fp32) dense_apply<float, float>(c.stream, c.dAif, c.dpart, n, (const float*)l.r, (float*)l.z, gate);
@@ -410,7 +385,7 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   if (c.ops->fused_applies(c, k, op)) {
     c.ops->fused_down(c, k, gate);                                            // two sweeps, residual, P'
     void* vc = vcycle_level(c, op, k - 1, gate, nullptr);
-    c.ops->fused_up(c, k, vc, l.z2, gate, beta64);                            // P, two sweeps (+ ratio)
+    c.ops->fused_up(c, k, vc, l.z2, gate);                                    // P, two sweeps
     return l.z2;
   }
   void* cur = l.z;
@@ -514,7 +489,9 @@ static void pcg_iteration(Ctx& c, int op, int64_t n, const int* gate, int first)
   } else {
     vpcg_update_fin(c.stream, n, c.red, gate, fold);
   }
-  const bool fused_beta = c.desc.nu_post >= 1 && c.tail_top < c.L - 1;
+  // the finest level's last post-smoothing sweep forms beta (no sweep on a one-level
+  // hierarchy: the coarsest solve is the whole V-cycle)
+  const bool fused_beta = c.desc.nu_post >= 1 && c.L > 1;
   void* y = vcycle_level(c, op, c.L - 1, gate, fused_beta ? c.pr : nullptr);
   if (!fused_beta) {
     if (c.fp32) vdot_beta<float>(c.stream, c.pr, (const float*)y, n, c.red, gate);

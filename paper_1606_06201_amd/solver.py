@@ -259,7 +259,7 @@ class Solver:
     # ------------------------------------------------------------------ timing --
     KERNEL_CLASSES = {"fine_jacobi": 0, "dir_apply": 1, "fine_resid": 2, "pcg_update": 3, "sub_jacobi": 4,
                       "fine_jacobi0": 5, "fine_jacobi_beta": 6, "sub_down": 7, "sub_up": 8,
-                      "fine_down": 9, "fine_up": 10, "fine_pjacobi": 11, "fine_jacobi2": 12, "elem3": 13,
+                      "fine_pjacobi": 11, "fine_jacobi2": 12, "elem3": 13,
                       "elem3_dir": 14}
 
     def profile_begin(self, kernels, max_launches=4096):

@@ -203,11 +203,9 @@ def test_z3d_element_hv_pass_matches_gather(fp32, monkeypatch):
     assert relerr(np.concatenate([a[0][free], a[0][-1:]]), ref) < 1e-12
 
 
-@pytest.mark.parametrize("env,val,fp32", [("IPMG_TAIL", "1", False), ("IPMG_TILED_MIN_NODES", "0", False),
-                                          ("IPMG_TILED_MIN_NODES", "0", True)])
+@pytest.mark.parametrize("env,val,fp32", [("IPMG_TILED_MIN_NODES", "0", False), ("IPMG_TILED_MIN_NODES", "0", True)])
 def test_z_vcycle_alternative_paths_match_oracle(env, val, fp32, monkeypatch):
-    # Z V-cycle through the single-workgroup coarse tail, and through register-blocked
-    # 2D tiles on every level.
+    # Z V-cycle through register-blocked 2D tiles on every level.
     from paper_1606_06201_amd import Solver
     nel, levels = (32, 16), 3
     prob = _problem(nel)

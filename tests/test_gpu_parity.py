@@ -257,22 +257,19 @@ def test_element_sensitivities_match_oracle():
     assert relerr(gs, ref) < 1e-13
 
 
-@pytest.mark.parametrize("env,val", [("IPMG_TAIL", "1"), ("IPMG_STORED_COARSE", "1"),
+@pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"),
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
-                                     ("IPMG_UNSTAGED", "1"), ("IPMG_FUSED_FINE", "1"), ("IPMG_STAGED_BIG", "1"),
-                                     ("IPMG_STAGED_DOWN_FROM_X", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
+                                     ("IPMG_UNSTAGED", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
                                      ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
                                                   ((8, 4, 4), 3, False, 1e-11), ((128, 64), 4, False, 1e-11),
                                                   ((128, 64), 4, True, 2e-4)])
 def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol, monkeypatch):
-    if env == "IPMG_FUSED_FINE":
-        monkeypatch.setenv("IPMG_FINE_SMALL_TILES", "1" if fp32 else "0")
-    # Opt-in execution paths (single-workgroup coarse tail; stored first coarse level;
-    # register-blocked 2D tiles on every level; one node per thread everywhere; the
-    # staged fused passes on large tiles, for the first coarse level's down pass, or
-    # on every coarse level; prolongation as a pass of its own) must give the same
-    # V-cycle as the default path and the oracle.
+    # Opt-in execution paths (stored first coarse level; register-blocked 2D tiles on
+    # every level; one node per thread everywhere; separate passes instead of the
+    # fused coarse ones; fused passes reading global memory, or staged, on every
+    # coarse level; prolongation and restriction as passes of their own) must give
+    # the same V-cycle as the default path and the oracle.
     g, K0, x = _kproblem(nel)
     H = mg.kstiffness_hierarchy(g, x, K0, levels)
     r = np.random.default_rng(6).standard_normal(g.nslots)
@@ -280,7 +277,6 @@ def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol,
     monkeypatch.setenv(env, val)
     s = _solver(nel, levels, fp32=fp32)
     monkeypatch.delenv(env)
-    monkeypatch.delenv("IPMG_FINE_SMALL_TILES", raising=False)
     s.set_density(T(x))
     s.mg_setup()
     z = N(s.vcycle(T(r)))
