@@ -249,6 +249,39 @@ struct UpLoads {
   }
 };
 
+// Last phase of a down tile: rc = P' t on the tile's coarse nodes (t in s3, over
+// region 3) and z2 (in s2, over region 2) on the fine nodes the tile owns.
+template <typename T, int CX, int CY, int NT>
+__device__ inline void down_tile_out(const Dims& d, const Dims& dc, int CI0, int CJ0, T* z2out, T* rc, const T* s2,
+                                     const T* s3) {
+  constexpr int W1 = 2 * CX + 5, W2 = W1 - 2, W3 = W1 - 4;
+  const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
+  for (int t = threadIdx.x; t < CX * CY; t += NT) {     // rc = P' t on the tile's coarse nodes
+    const int I = CI0 + t % CX, J = CJ0 + t / CX;
+    if (I >= dc.nx1 || J >= dc.ny1) continue;
+    T acc[2] = {T(0), T(0)};
+    if (I > 0) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int li = 2 * (I - CI0) + 1 + dx, lj = 2 * (J - CJ0) + 1 + dy;   // position in region 3
+          const T w = T(w1(dx) * w1(dy));
+          acc[0] += w * s3[2 * (lj * W3 + li)];
+          acc[1] += w * s3[2 * (lj * W3 + li) + 1];
+        }
+    }
+    store_node<2, T>(rc, (int64_t)J * dc.nx1 + I, acc);
+  }
+  for (int t = threadIdx.x; t < 4 * CX * CY; t += NT) {   // z2 on the fine nodes the tile owns
+    const int gi = 2 * CI0 + t % (2 * CX), gj = 2 * CJ0 + t / (2 * CX);
+    if (gi >= d.nx1 || gj >= d.ny1) continue;
+    const int q = 2 * ((gj - oy - 1) * W2 + gi - ox - 1);
+    const T o[2] = {s2[q], s2[q + 1]};
+    store_node<2, T>(z2out, (int64_t)gj * d.nx1 + gi, o);
+  }
+}
+
 // Down pass of one tile of CX x CY coarse nodes with corner (CI0, CJ0).  LDS:
 // sr, sd, s1 over region 1 ((2CX+5) x (2CY+5) fine nodes from (2CI0-3, 2CJ0-3)),
 // s2 over region 2 (one node inside), s3 over region 3 (two nodes inside).
@@ -310,40 +343,17 @@ __device__ inline void down_tile(const Op& op, const Dims& d, const Dims& dc, in
     s3[2 * t + 1] = o[1];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < CX * CY; t += NT) {     // rc = P' t on the tile's coarse nodes
-    const int I = CI0 + t % CX, J = CJ0 + t / CX;
-    if (I >= dc.nx1 || J >= dc.ny1) continue;
-    T acc[2] = {T(0), T(0)};
-    if (I > 0) {
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int li = 2 * (I - CI0) + 1 + dx, lj = 2 * (J - CJ0) + 1 + dy;   // position in region 3
-          const T w = T(w1(dx) * w1(dy));
-          acc[0] += w * s3[2 * (lj * W3 + li)];
-          acc[1] += w * s3[2 * (lj * W3 + li) + 1];
-        }
-    }
-    store_node<2, T>(rc, (int64_t)J * dc.nx1 + I, acc);
-  }
-  for (int t = threadIdx.x; t < 4 * CX * CY; t += NT) {   // z2 on the fine nodes the tile owns
-    const int gi = 2 * CI0 + t % (2 * CX), gj = 2 * CJ0 + t / (2 * CX);
-    if (gi >= d.nx1 || gj >= d.ny1) continue;
-    const int q = 2 * ((gj - oy - 1) * W2 + gi - ox - 1);
-    const T o[2] = {s2[q], s2[q + 1]};
-    store_node<2, T>(z2out, (int64_t)gj * d.nx1 + gi, o);
-  }
+  down_tile_out<T, CX, CY, NT>(d, dc, CI0, CJ0, z2out, rc, s2, s3);
 }
 
 // Up pass of one tile of TX x TY fine nodes with corner (I0, J0).  LDS: s0 over
 // region 0 ((TX+4) x (TY+4) nodes from (I0-2, J0-2)); sr, sd, s1 over region 1
 // (one node inside).
-template <typename T, class Op, int TX, int TY, int NT>
-__device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0,
-                               const UpLoads<T, TX, TY, NT>& pre, T* out, T omega, T* s0, T* sr, T* sd, T* s1) {
+// First phase of an up tile: s0 = z2 + P zc over region 0 (zero on nodes that are
+// not free).
+template <typename T, int TX, int TY, int NT>
+__device__ inline void up_tile_prolong(const Dims& d, int I0, int J0, const UpLoads<T, TX, TY, NT>& pre, T* s0) {
   constexpr int W0 = TX + 4, H0 = TY + 4;
-  constexpr int W1 = TX + 2, H1 = TY + 2;
 #pragma unroll
   for (int u = 0; u < UpLoads<T, TX, TY, NT>::P0; ++u) {
     const int t = threadIdx.x + u * NT;
@@ -367,6 +377,14 @@ __device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int 
     s0[2 * t] = fr ? o[0] : T(0);
     s0[2 * t + 1] = fr ? o[1] : T(0);
   }
+}
+
+template <typename T, class Op, int TX, int TY, int NT>
+__device__ inline void up_tile(const Op& op, const Dims& d, const Dims& dc, int I0, int J0,
+                               const UpLoads<T, TX, TY, NT>& pre, T* out, T omega, T* s0, T* sr, T* sd, T* s1) {
+  constexpr int W0 = TX + 4;
+  constexpr int W1 = TX + 2, H1 = TY + 2;
+  up_tile_prolong<T, TX, TY, NT>(d, I0, J0, pre, s0);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < UpLoads<T, TX, TY, NT>::P1; ++u) {
@@ -490,6 +508,240 @@ __global__ __launch_bounds__(FBS) void k_up2d_x(const T* __restrict__ x, int fnx
   op.lw = LW;
   op.ne = LW * LH;
   up_tile<T, OpCoarse2KLDS<T>, TX, TY, FBS>(op, d, dc, I0, J0, pre, out, T(*omg), s0, sr, sd, s1);
+}
+
+// ------------------------------------------------------------ matrix cores --
+// The first coarse level's element products on the matrix cores.  For a group of
+// 32 elements, U = [G_0; G_1; G_2; G_3] V (32 x 8 times 8 x 32, four
+// v_mfma_f32_32x32x2f32 steps of K = 2), V the elements' vertex values as columns;
+// then y_e = sum_q x_q U_q[:, e] (the x-weighted sum of each element's four 8-row
+// blocks), and the node passes gather y_e of the four elements around each node.
+// Lane layout of the 32x32x2 product: lane l supplies A[l % 32][2s + l / 32] and
+// B[2s + l / 32][l % 32] at step s and receives D[8 (v / 4) + 4 (l / 32) + v % 4]
+// [l % 32] in result register v, so each lane holds rows 4 h .. 4 h + 3 (h = l / 32)
+// of all four blocks of its element.
+static __constant__ float cG256f[256];   // G_q[r][k] at 64 q + 8 r + k (q-major stack)
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+
+// This lane's A operands of the four K steps (row l % 32 of the stack).
+__device__ inline void gstack_operands(float (&aG)[4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) aG[s] = cG256f[(lane & 31) * 8 + 2 * s + (lane >> 5)];
+}
+
+// y_e for the NEX x NEY elements of a block: element (ex, ey) has vertex b at node
+// (ex + loc_x(b), ey + loc_y(b)) of sv (row width WV, two values per node) and the
+// four densities of staged element (ex + ELX, ey + ELY) of xl (row width LW, LH
+// rows, as OpCoarse2KLDS).  Writes ye[8 t + r], t = ey NEX + ex.  The waves of the
+// workgroup take the groups of 32 elements in turn.
+template <int NEX, int NEY, int WV, int LW, int LH, int ELX, int ELY, int NT>
+__device__ inline void elem_products_mfma(const float* sv, const float* xl, const float (&aG)[4], float* ye) {
+  constexpr int NE = NEX * NEY, NG = (NE + 31) / 32, NW = NT / 64, NEL = LW * LH;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  for (int g = (int)threadIdx.x >> 6; g < NG; g += NW) {
+    const int t0 = g * 32 + (lane & 31), t = min(t0, NE - 1);
+    const int ex = t % NEX, ey = t / NEX;
+    float b[4], xq[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) b[s] = sv[2 * ((ey + loc_y(s)) * WV + ex + loc_x(s)) + h];
+    const int le = (ey + ELY) * LW + ex + ELX;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xq[q] = xl[q * NEL + le];
+    mfma_f32x16 acc = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
+                       0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aG[s], b[s], acc, 0, 0, 0);
+    float4 y;
+    y.x = xq[0] * acc[0] + xq[1] * acc[4] + xq[2] * acc[8] + xq[3] * acc[12];
+    y.y = xq[0] * acc[1] + xq[1] * acc[5] + xq[2] * acc[9] + xq[3] * acc[13];
+    y.z = xq[0] * acc[2] + xq[1] * acc[6] + xq[2] * acc[10] + xq[3] * acc[14];
+    y.w = xq[0] * acc[3] + xq[1] * acc[7] + xq[2] * acc[11] + xq[3] * acc[15];
+    if (t0 < NE) *reinterpret_cast<float4*>(ye + 8 * t + 4 * h) = y;
+  }
+}
+
+// Row sums of node (li, lj) from the products of the four elements around it:
+// element (li - 1 + ex + OX, lj - 1 + ey + OY) of a block of row width NEX, the node
+// its vertex loc_index(1 - ex, 1 - ey).
+template <int NEX, int OX, int OY>
+__device__ inline void gather_rows(const float* ye, int li, int lj, float (&acc)[2]) {
+  acc[0] = acc[1] = 0.0f;
+#pragma unroll
+  for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+    for (int ex = 0; ex < 2; ++ex) {
+      const int t = (lj - 1 + ey + OY) * NEX + li - 1 + ex + OX;
+      const int a = loc_index(1 - ex, 1 - ey, 0);
+      const float2 v = *reinterpret_cast<const float2*>(ye + 8 * t + 2 * a);
+      acc[0] += v.x;
+      acc[1] += v.y;
+    }
+}
+
+// k_down2d_x with the operator applications of its second and third phases on the
+// matrix cores (FP32).  Regions and outputs as in down_tile.
+template <bool FROM_T, int CX, int CY>
+__global__ __launch_bounds__(FBS) void k_down2d_m(const float* __restrict__ x, int fnx, Dims d, Dims dc,
+                                                  const float* __restrict__ r, float* __restrict__ z2out,
+                                                  float* __restrict__ rc, const double* __restrict__ omg,
+                                                  const int* gate, Dims df, const float* __restrict__ tf,
+                                                  float* __restrict__ rw) {
+  if (gate && *gate) return;
+  constexpr int W1 = 2 * CX + 5, H1 = 2 * CY + 5, W2 = W1 - 2, H2 = H1 - 2, W3 = W1 - 4, H3 = H1 - 4;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  constexpr int NEX2 = W1 - 1, NEY2 = H1 - 1, NEX3 = W1 - 3, NEY3 = H1 - 3;   // element blocks of phases 2, 3
+  __shared__ float xl[4 * LW * LH];
+  __shared__ float sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
+  __shared__ __align__(16) float ye[8 * NEX2 * NEY2];
+  const Tile tl = xcd_tile();
+  const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
+  const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
+  const int ex0 = ox - 1, ey0 = oy - 1;
+  DownLoads<float, CX, CY, FBS> pre;
+  if constexpr (FROM_T) pre.load_restrict(d, df, CI0, CJ0, tf, rw);
+  else pre.load(d, CI0, CJ0, r);
+  stage_x4<float, FBS, LW, LH>(x, fnx, d, ex0, ey0, xl);
+  float aG[4];
+  gstack_operands(aG);
+  __syncthreads();
+  OpCoarse2KLDS<float> op;
+  op.xl = xl;
+  op.ex0 = ex0;
+  op.ey0 = ey0;
+  op.lw = LW;
+  op.ne = LW * LH;
+  const float omega = (float)*omg;
+  // phase 1: z1 = w D^-1 r on region 1
+#pragma unroll
+  for (int u = 0; u < DownLoads<float, CX, CY, FBS>::P1; ++u) {
+    const int t = threadIdx.x + u * FBS;
+    if (t >= W1 * H1) break;
+    const int gi = ox + t % W1, gj = oy + t / W1;
+    float rr[2] = {0.0f, 0.0f}, dg[2] = {0.0f, 0.0f}, o[2] = {0.0f, 0.0f};
+    if (node_free(d, gi, gj)) {
+      rr[0] = pre.r[u][0];
+      rr[1] = pre.r[u][1];
+      float vn[9][2], acc[2] = {0.0f, 0.0f};
+      node_apply<2, float, OpCoarse2KLDS<float>, false, true, false>(op, d, gi, gj, 0, vn, acc, dg);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) o[c] = omega * rr[c] * recip(dg[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) { sr[2 * t + c] = rr[c]; sd[2 * t + c] = dg[c]; s1[2 * t + c] = o[c]; }
+  }
+  __syncthreads();
+  // phase 2: z2 = z1 + w D^-1 (r - A z1) on region 2
+  elem_products_mfma<NEX2, NEY2, W1, LW, LH, 1, 1, FBS>(s1, xl, aG, ye);
+  __syncthreads();
+  for (int t = threadIdx.x; t < W2 * H2; t += FBS) {
+    const int li = t % W2 + 1, lj = t / W2 + 1;        // position in region 1
+    const int gi = ox + li, gj = oy + lj;
+    float o[2] = {0.0f, 0.0f};
+    if (node_free(d, gi, gj)) {
+      float acc[2];
+      gather_rows<NEX2, 0, 0>(ye, li, lj, acc);
+      const int q = 2 * (lj * W1 + li);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
+    }
+    s2[2 * t] = o[0];
+    s2[2 * t + 1] = o[1];
+  }
+  __syncthreads();
+  // phase 3: t = r - A z2 on region 3 (elements with lower-left node 1 .. W1-3 of region 1)
+  elem_products_mfma<NEX3, NEY3, W2, LW, LH, 2, 2, FBS>(s2, xl, aG, ye);
+  __syncthreads();
+  for (int t = threadIdx.x; t < W3 * H3; t += FBS) {
+    const int li = t % W3 + 2, lj = t / W3 + 2;        // position in region 1
+    const int gi = ox + li, gj = oy + lj;
+    float o[2] = {0.0f, 0.0f};
+    if (node_free(d, gi, gj)) {
+      float acc[2];
+      gather_rows<NEX3, -1, -1>(ye, li, lj, acc);
+      const int q = 2 * (lj * W1 + li);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) o[c] = sr[q + c] - acc[c];
+    }
+    s3[2 * t] = o[0];
+    s3[2 * t + 1] = o[1];
+  }
+  __syncthreads();
+  down_tile_out<float, CX, CY, FBS>(d, dc, CI0, CJ0, z2out, rc, s2, s3);
+}
+
+// k_up2d_x with the operator applications of its two sweeps on the matrix cores
+// (FP32).  Regions and output as in up_tile.
+template <int TX, int TY>
+__global__ __launch_bounds__(FBS) void k_up2d_m(const float* __restrict__ x, int fnx, Dims d, Dims dc,
+                                                const float* __restrict__ r, const float* __restrict__ z2,
+                                                const float* __restrict__ zc, float* __restrict__ out,
+                                                const double* __restrict__ omg, const int* gate) {
+  if (gate && *gate) return;
+  constexpr int W0 = TX + 4, H0 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int LW = W1 + 1, LH = H1 + 1;
+  constexpr int NEXA = W1 + 1, NEYA = H1 + 1, NEXB = W1 - 1, NEYB = H1 - 1;   // element blocks of the sweeps
+  __shared__ float xl[4 * LW * LH];
+  __shared__ float s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
+  __shared__ __align__(16) float ye[8 * NEXA * NEYA];
+  const Tile tl = xcd_tile();
+  const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
+  const int ex0 = I0 - 2, ey0 = J0 - 2;
+  UpLoads<float, TX, TY, FBS> pre;
+  pre.load(d, dc, I0, J0, r, z2, zc);
+  stage_x4<float, FBS, LW, LH>(x, fnx, d, ex0, ey0, xl);
+  float aG[4];
+  gstack_operands(aG);
+  OpCoarse2KLDS<float> op;
+  op.xl = xl;
+  op.ex0 = ex0;
+  op.ey0 = ey0;
+  op.lw = LW;
+  op.ne = LW * LH;
+  const float omega = (float)*omg;
+  up_tile_prolong<float, TX, TY, FBS>(d, I0, J0, pre, s0);
+  __syncthreads();
+  // first sweep on region 1: elements with lower-left node 0 .. W1 of region 0
+  elem_products_mfma<NEXA, NEYA, W0, LW, LH, 0, 0, FBS>(s0, xl, aG, ye);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UpLoads<float, TX, TY, FBS>::P1; ++u) {
+    const int t = threadIdx.x + u * FBS;
+    if (t >= W1 * H1) break;
+    const int li = t % W1, lj = t / W1;                 // position in region 1
+    const int gi = I0 - 1 + li, gj = J0 - 1 + lj;
+    float rr[2] = {0.0f, 0.0f}, dg[2] = {0.0f, 0.0f}, o[2] = {0.0f, 0.0f};
+    if (node_free(d, gi, gj)) {
+      rr[0] = pre.r[u][0];
+      rr[1] = pre.r[u][1];
+      float vn[9][2], acc[2];
+      node_apply<2, float, OpCoarse2KLDS<float>, false, true, false>(op, d, gi, gj, 0, vn, acc, dg);
+      gather_rows<NEXA, 1, 1>(ye, li, lj, acc);
+      const int q = 2 * ((lj + 1) * W0 + li + 1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) o[c] = s0[q + c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) { sr[2 * t + c] = rr[c]; sd[2 * t + c] = dg[c]; s1[2 * t + c] = o[c]; }
+  }
+  __syncthreads();
+  // second sweep on the tile: elements with lower-left node 0 .. TX of region 1
+  elem_products_mfma<NEXB, NEYB, W1, LW, LH, 1, 1, FBS>(s1, xl, aG, ye);
+  __syncthreads();
+  for (int t = threadIdx.x; t < TX * TY; t += FBS) {
+    const int gi = I0 + t % TX, gj = J0 + t / TX;
+    if (gi >= d.nx1 || gj >= d.ny1) continue;
+    float o[2] = {0.0f, 0.0f};
+    if (gi >= 1) {
+      const int li = gi - I0 + 1, lj = gj - J0 + 1;     // position in region 1
+      float acc[2];
+      gather_rows<NEXB, 0, 0>(ye, li, lj, acc);
+      const int q = 2 * (lj * W1 + li);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
+    }
+    store_node<2, float>(out, (int64_t)gj * d.nx1 + gi, o);
+  }
 }
 
 // Stored FP32 element matrices staged in LDS, tiles of CX x CY coarse nodes and NT

@@ -504,6 +504,12 @@ struct OpsImpl : Ops {
       for (int k = 0; k < 18; ++k) g18f[k] = (float)g18[k];
       IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG18d), g18, sizeof(double) * 18));
       IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG18f), g18f, sizeof(float) * 18));
+      float g256f[256];
+      for (int t = 0; t < 256; ++t) {
+        const int e = kSqG2d[t], k = (e > 0 ? e : -e) - 1;
+        g256f[t] = e > 0 ? g18f[k] : -g18f[k];
+      }
+      IPMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cG256f), g256f, sizeof(float) * 256));
     }
   }
 
@@ -886,16 +892,16 @@ struct OpsImpl : Ops {
     const Dims& dc = c.lev[lev - 1].d;
     const Dims& df = c.fine();
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_DOWN : -1);
-    if (lev == c.L - 2 && c.coarse_from_x) {
-      if (c.down_from_t) {   // restriction of the finest residual done in the tile
-        down_x<T, true>(c, lev, nullptr, df, (const T*)c.down_from_t, (T*)c.lev[lev].r, gate);
-        c.down_from_t = nullptr;
-      } else {
-        down_x<T, false>(c, lev, (const T*)c.lev[lev].r, df, nullptr, nullptr, gate);
+    if constexpr (std::is_same<T, float>::value) {   // (fused_applies: from x in FP32 only)
+      if (lev == c.L - 2 && c.coarse_from_x) {
+        if (c.down_from_t) {   // restriction of the finest residual done in the tile
+          down_x<true>(c, lev, nullptr, df, (const float*)c.down_from_t, (float*)c.lev[lev].r, gate);
+          c.down_from_t = nullptr;
+        } else {
+          down_x<false>(c, lev, (const float*)c.lev[lev].r, df, nullptr, nullptr, gate);
+        }
+        return;
       }
-      return;
-    }
-    if constexpr (std::is_same<T, float>::value) {
       if (c.fused_staged && d.nnodes < c.staged_max_nodes) {
         const dim3 gs((unsigned)((dc.nx1 + SCX - 1) / SCX), (unsigned)((dc.ny1 + SCY - 1) / SCY), 1);
         k_down2d_staged<SCX, SCY, SBS_STORED><<<gs, SBS_STORED, 0, c.stream>>>(
@@ -922,25 +928,33 @@ struct OpsImpl : Ops {
     if (nine) k_down2d<T, Op, 16, 9><<<g9, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate);
     else k_down2d<T, Op, 16, 8><<<g8, FBS, 0, c.stream>>>(op, d, dc, r, z, rc, c.omega_dev + lev, gate);
   }
-  // k_down2d_x on 16x8 or 16x9 coarse-node tiles (see pick_tiles).
-  template <typename T, bool FROM_T>
-  void down_x(Ctx& c, int lev, const T* r, const Dims& df, const T* tf, T* rw, const int* gate) {
+  // First coarse level formed from the densities (FP32): k_down2d_m (element
+  // products on the matrix cores) or k_down2d_x, on 16x8 or 16x9 coarse-node tiles
+  // (see pick_tiles).
+  template <bool FROM_T>
+  void down_x(Ctx& c, int lev, const float* r, const Dims& df, const float* tf, float* rw, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g8((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 7) / 8), 1);
     const dim3 g9((unsigned)((dc.nx1 + 15) / 16), (unsigned)((dc.ny1 + 8) / 9), 1);
-    const bool nine = pick_tiles(c, (const void*)k_down2d_x<T, FROM_T, 16, 8>, g8, 37 * 21,
-                                 (const void*)k_down2d_x<T, FROM_T, 16, 9>, g9, 37 * 23);
-    const T* x = (const T*)c.xT;
+    const float* x = (const float*)c.xT;
     const int fnx = c.fine().nx;
-    T* z = (T*)c.lev[lev].z;
-    T* rc = (T*)c.lev[lev - 1].r;
-    if (nine)
-      k_down2d_x<T, FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf,
-                                                             rw);
-    else
-      k_down2d_x<T, FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, c.omega_dev + lev, gate, df, tf,
-                                                             rw);
+    float* z = (float*)c.lev[lev].z;
+    float* rc = (float*)c.lev[lev - 1].r;
+    const double* w = c.omega_dev + lev;
+    if (c.mfma) {
+      if (pick_tiles(c, (const void*)k_down2d_m<FROM_T, 16, 8>, g8, 37 * 21, (const void*)k_down2d_m<FROM_T, 16, 9>,
+                     g9, 37 * 23))
+        k_down2d_m<FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, w, gate, df, tf, rw);
+      else
+        k_down2d_m<FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, w, gate, df, tf, rw);
+    } else {
+      if (pick_tiles(c, (const void*)k_down2d_x<float, FROM_T, 16, 8>, g8, 37 * 21,
+                     (const void*)k_down2d_x<float, FROM_T, 16, 9>, g9, 37 * 23))
+        k_down2d_x<float, FROM_T, 16, 9><<<g9, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, w, gate, df, tf, rw);
+      else
+        k_down2d_x<float, FROM_T, 16, 8><<<g8, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z, rc, w, gate, df, tf, rw);
+    }
   }
   // The down pass of level lev (the first coarse level formed from the densities,
   // FP32) restricts the finest residual itself.
@@ -958,11 +972,11 @@ struct OpsImpl : Ops {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     ProfScope ps(c, lev == c.L - 2 ? PC_SUB_UP : -1);
-    if (lev == c.L - 2 && c.coarse_from_x) {
-      up_x<T>(c, lev, zc, out, gate);
-      return;
-    }
     if constexpr (std::is_same<T, float>::value) {
+      if (lev == c.L - 2 && c.coarse_from_x) {
+        up_x(c, lev, zc, out, gate);
+        return;
+      }
       if (c.fused_staged && d.nnodes < c.staged_max_nodes) {
         const dim3 gs((unsigned)((d.nx1 + STX - 1) / STX), (unsigned)((d.ny1 + STY - 1) / STY), 1);
         k_up2d_staged<STX, STY, SBS_STORED><<<gs, SBS_STORED, 0, c.stream>>>(
@@ -989,25 +1003,32 @@ struct OpsImpl : Ops {
     else
       k_up2d<T, Op, 32, 16><<<g16, FBS, 0, c.stream>>>(op, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev, gate);
   }
-  // k_up2d_x on 32x16 or 32x18 fine-node tiles (see pick_tiles).
-  template <typename T>
+  // First coarse level formed from the densities (FP32): k_up2d_m or k_up2d_x, on
+  // 32x16 or 32x18 fine-node tiles (see pick_tiles).
   void up_x(Ctx& c, int lev, const void* zc, void* out, const int* gate) {
     const Dims& d = c.lev[lev].d;
     const Dims& dc = c.lev[lev - 1].d;
     const dim3 g16((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 15) / 16), 1);
     const dim3 g18((unsigned)((d.nx1 + 31) / 32), (unsigned)((d.ny1 + 17) / 18), 1);
-    const bool tall = pick_tiles(c, (const void*)k_up2d_x<T, 32, 16>, g16, 36 * 20,
-                                 (const void*)k_up2d_x<T, 32, 18>, g18, 36 * 22);
-    const T* x = (const T*)c.xT;
+    const float* x = (const float*)c.xT;
     const int fnx = c.fine().nx;
-    const T* r = (const T*)c.lev[lev].r;
-    const T* z2 = (const T*)c.lev[lev].z;
-    if (tall)
-      k_up2d_x<T, 32, 18><<<g18, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev,
-                                                     gate);
-    else
-      k_up2d_x<T, 32, 16><<<g16, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, (const T*)zc, (T*)out, c.omega_dev + lev,
-                                                     gate);
+    const float* r = (const float*)c.lev[lev].r;
+    const float* z2 = (const float*)c.lev[lev].z;
+    const float* zf = (const float*)zc;
+    float* o = (float*)out;
+    const double* w = c.omega_dev + lev;
+    if (c.mfma) {
+      if (pick_tiles(c, (const void*)k_up2d_m<32, 16>, g16, 36 * 20, (const void*)k_up2d_m<32, 18>, g18, 36 * 22))
+        k_up2d_m<32, 18><<<g18, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, zf, o, w, gate);
+      else
+        k_up2d_m<32, 16><<<g16, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, zf, o, w, gate);
+    } else {
+      if (pick_tiles(c, (const void*)k_up2d_x<float, 32, 16>, g16, 36 * 20, (const void*)k_up2d_x<float, 32, 18>, g18,
+                     36 * 22))
+        k_up2d_x<float, 32, 18><<<g18, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, zf, o, w, gate);
+      else
+        k_up2d_x<float, 32, 16><<<g16, FBS, 0, c.stream>>>(x, fnx, d, dc, r, z2, zf, o, w, gate);
+    }
   }
   void fused_down(Ctx& c, int lev, const int* gate) override {
     if constexpr (DIM == 2) {

@@ -257,10 +257,34 @@ def test_element_sensitivities_match_oracle():
     assert relerr(gs, ref) < 1e-13
 
 
+@pytest.mark.parametrize("nel,levels", [((256, 128), 4), ((96, 48), 3), ((72, 40), 3)])
+def test_first_coarse_level_matrix_cores_match_vector_units(nel, levels, monkeypatch):
+    # The first coarse level's fused passes with the element products on the matrix
+    # cores against the same passes on the vector units (FP32 V-cycle).  Each
+    # 32x32x2 step rounds like two chained FMAs in the order of the vector code, so
+    # the results agree to FP32 rounding (bit for bit on MI355X); the bound allows
+    # a reordering.  The grids give one or several tiles per direction with ragged
+    # last tiles; every element block of a tile ends in a partly filled group of 32.
+    g, K0, x = _kproblem(nel, seed=9)
+    r = np.random.default_rng(10).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    z = {}
+    for v in ("0", "1"):
+        monkeypatch.setenv("IPMG_NO_MFMA", v)
+        s = _solver(nel, levels, fp32=True)
+        s.set_density(T(x))
+        s.mg_setup()
+        z[v] = N(s.vcycle(T(r)))
+    monkeypatch.delenv("IPMG_NO_MFMA")
+    print(f"{nel}: matrix cores vs vector units bitwise equal: {np.array_equal(z['0'], z['1'])}", flush=True)
+    assert relerr(z["0"], z["1"]) < 1e-6
+
+
 @pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"),
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
                                      ("IPMG_UNSTAGED", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
-                                     ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1")])
+                                     ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1"),
+                                     ("IPMG_NO_MFMA", "1")])
 @pytest.mark.parametrize("nel,levels,fp32,tol", [((32, 16), 4, False, 1e-11), ((32, 16), 4, True, 2e-4),
                                                   ((8, 4, 4), 3, False, 1e-11), ((128, 64), 4, False, 1e-11),
                                                   ((128, 64), 4, True, 2e-4)])
@@ -268,8 +292,9 @@ def test_vcycle_alternative_paths_match_oracle(env, val, nel, levels, fp32, tol,
     # Opt-in execution paths (stored first coarse level; register-blocked 2D tiles on
     # every level; one node per thread everywhere; separate passes instead of the
     # fused coarse ones; fused passes reading global memory, or staged, on every
-    # coarse level; prolongation and restriction as passes of their own) must give
-    # the same V-cycle as the default path and the oracle.
+    # coarse level; prolongation and restriction as passes of their own; the first
+    # coarse level's element products on the vector units instead of the matrix
+    # cores) must give the same V-cycle as the default path and the oracle.
     g, K0, x = _kproblem(nel)
     H = mg.kstiffness_hierarchy(g, x, K0, levels)
     r = np.random.default_rng(6).standard_normal(g.nslots)
