@@ -108,6 +108,18 @@ class Problem:
         ue = self.elem(u)
         return np.einsum("ei,ij,ej->e", ue, self.K0, ue)
 
+    def Bmat(self, st):
+        """The matrix B of the Newton system at st (B(u) for problem (1))."""
+        return self.B(st.u)
+
+    def energy_term(self, st):
+        """u' [dK/dx_i] u per design variable, the energy part of F3 (KKT3)."""
+        return self.energies(st.u)
+
+    def z_preconditioner(self, st, parts):
+        """Matrix whose multigrid hierarchy preconditions Z (None: Z itself)."""
+        return None
+
     def residuals(self, st, matrix_free=False):
         """F1..F5 (Sec. 2).  matrix_free: K(x) u element by element instead of the
         assembled matrix (same sum; for grids too large to assemble)."""
@@ -117,7 +129,7 @@ class Problem:
         else:
             F1 = self.K(st.x) @ st.u - self.f
         F2 = float(st.x.sum() - self.V)
-        F3 = -0.5 * self.energies(st.u) - st.lam - st.phi + st.psi
+        F3 = -0.5 * self.energy_term(st) - st.lam - st.phi + st.psi
         F4 = st.phi * st.x - st.s
         F5 = st.psi * (self.xbar - st.x) - st.r
         return F1, F2, F3, F4, F5
@@ -138,7 +150,7 @@ class Problem:
         xt = self.xbar - st.x
         D = st.phi / st.x + st.psi / xt
         G3 = F3 + F4 / st.x - F5 / xt
-        B = self.B(st.u)
+        B = self.Bmat(st)
         Dinv = sp.diags(1.0 / D)
         Zuu = self.K(st.x) + B @ Dinv @ B.T
         bvec = B @ (1.0 / D)
@@ -159,7 +171,7 @@ class Problem:
         """Dense Jacobian of F with respect to (u, lambda, x, phi, psi)."""
         n, m = len(self.free), self.grid.m
         K = self.K(st.x).toarray()
-        B = self.B(st.u).toarray()
+        B = self.Bmat(st).toarray()
         N = n + 1 + 3 * m
         J = np.zeros((N, N))
         iu, il, ix, ip, iq = 0, n, n + 1, n + 1 + m, n + 1 + 2 * m
@@ -212,21 +224,23 @@ class IPLog:
         self.status = "running"
 
 
-def solve_linear(Z, rhs, params, grid, augmented, x0=None):
+def solve_linear(Z, rhs, params, grid, augmented, x0=None, Zprec=None):
     """MG-PCG (or a sparse direct solve); returns (solution, iterations, status,
-    true relative residual), status "ok", "maxit" or "breakdown"."""
+    true relative residual), status "ok", "maxit" or "breakdown".  Zprec: the
+    multigrid hierarchy is built from this matrix instead of Z (PCG still on Z)."""
     if params.solver == "direct":
         return spla.spsolve(Z.tocsc(), rhs), 0, "ok", 0.0
-    H = mg.Hierarchy(grid, Z, params.levels, augmented=augmented, omega=params.omega)
+    H = mg.Hierarchy(grid, Z if Zprec is None else Zprec, params.levels, augmented=augmented, omega=params.omega)
+    A = None if Zprec is None else Z
     res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, None,
-                         params.nu1, params.nu2)
+                         params.nu1, params.nu2, A=A)
     iters = res.iters
     if res.status == "breakdown":
         # the V-cycle was not positive definite (the estimate of rho came out too
         # low): damping estimated again, more steps and a smaller product, and the
         # solve continued from its last iterate
         H.damping(mg.RETRY_POWER_FACTOR * mg.POWER_STEPS_Z, mg.SAFE_PRODUCT_RETRY)
-        res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, res.z, params.nu1, params.nu2)
+        res = pcg_mod.mg_pcg(H, rhs, params.pcg_rtol, params.pcg_maxit, res.z, params.nu1, params.nu2, A=A)
         iters += res.iters
     return res.z, iters, res.status, res.true_relres
 
@@ -257,7 +271,8 @@ def accept_solve(status, true_relres, params):
 
 def newton_step(prob, st, params, log=None):
     Z, rhs, parts = prob.z_system(st)
-    sol, iters, status, true_rel = solve_linear(Z, rhs, params, prob.grid, True)
+    Zp = prob.z_preconditioner(st, parts) if params.solver == "mg" else None
+    sol, iters, status, true_rel = solve_linear(Z, rhs, params, prob.grid, True, Zprec=Zp)
     short = accept_solve(status, true_rel, params)
     if log is not None:
         log.short_solves += int(short)

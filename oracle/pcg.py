@@ -88,9 +88,9 @@ def pcg(apply_A, b, precond, rtol=1e-8, maxit=1000, z0=None, flexible=False):
     return PCGResult(z, iters, history[-1], true_rel, False, restarts, history, "maxit")
 
 
-def mg_pcg(H, b, rtol=1e-8, maxit=1000, z0=None, nu1=2, nu2=2, flexible=False):
-    """PCG on the finest operator of hierarchy H with one V-cycle per step
-    (the damping weights live in the hierarchy)."""
+def mg_pcg(H, b, rtol=1e-8, maxit=1000, z0=None, nu1=2, nu2=2, flexible=False, A=None):
+    """PCG on the finest operator of hierarchy H (or on the matrix A, when given)
+    with one V-cycle of H per step (the damping weights live in the hierarchy)."""
     from . import mg
-    A = H.A[-1]
+    A = H.A[-1] if A is None else A
     return pcg(lambda v: A @ v, b, lambda r: mg.vcycle(H, r, nu1, nu2), rtol, maxit, z0, flexible)

@@ -8,12 +8,31 @@ every column of W sums to one (sum x~ = sum x).  For the compliance c = f'u the
 derivative follows from K^ du/dx_i = -(dK^/dx_i) u:
   dc/dx_i = -u' [p sum_j W_ji x~_j^(p-1) K_j] u = -sum_j W_ji p x~_j^(p-1) E_j,
 E_j = u_j'K0u_j; this is the bracket of the paper's modified condition (KKT3).
+
+Interior-point method on the SIMP model (Sec. 9): the method of Sec. 2-3 with
+K(x) replaced by K^(x~) and the matrix B(u) of the Newton system (eq. (nwtr), and
+so Z of eq. (nwtr2)) replaced by
+  B^(u) = (b_1, ..., b_m),  b_i = p sum_j W_ji x~_j^(p-1) K_j u = B(u) C W e_i,
+C = diag(p x~^(p-1)), B(u) = (K_1 u, ..., K_m u) with the unit element matrices;
+F3_i = -1/2 (W'(C E))_i - lambda - phi_i + psi_i.  Reading: the paper keeps the
+Newton system of the convex problem with B^ in place of B (it calls the method
+"vanilla"), so the term of d(B^'u)/dx (second derivatives of K^) is not part of
+the Newton matrix; the Newton matrix here is exactly that system.
+Preconditioner (reading: the paper does not say how its multigrid treats the
+filtered rank-one terms, whose vectors b_i span the elements of a filter patch):
+the hierarchy is built from the element-local SPD matrix
+  Z~ = [[K^, 0], [0, 0]] + sum_j [h_j; g_j][h_j; g_j]',
+  h_j = sqrt(w~_j) K_j u,  w~_j = c_j^2 (W2 w)_j,  (W2)_ji = W_ji^2,  w = D^-1,
+  g_j = beta_j / sqrt(w~_j),  beta_j = c_j (W w)_j,
+that is the rank-one terms w_i b_i b_i' with the couplings between different
+elements of a patch dropped, and the border sum_j beta_j K_j u = B^ D^-1 e exact;
+PCG runs on the exact Z.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import fem
+from . import fem, ip
 
 
 def filter_matrix(grid, rmin, metric="manhattan"):
@@ -57,3 +76,42 @@ def compliance_and_gradient(grid, K0, f_slots, x, rmin, p, W=None):
     E = np.einsum("ei,ij,ej->e", ue, K0, ue)
     grad = -(W.T @ (p * xt ** (p - 1) * E))
     return float(f @ u), u, grad, xt
+
+
+class SimpProblem(ip.Problem):
+    """Problem (1) with the SIMP model and density filter of Sec. 9 for the
+    interior-point method (readings in the module header)."""
+
+    def __init__(self, grid, K0, f_slots, V, xbar, rmin=2.0, p=3.0, W=None):
+        super().__init__(grid, K0, f_slots, V, xbar)
+        self.rmin, self.p = float(rmin), float(p)
+        self.W = filter_matrix(grid, rmin) if W is None else W
+
+    def xt(self, x):
+        return self.W @ x
+
+    def cfac(self, x):
+        """c = p x~^(p-1), the derivative of x~^p."""
+        return self.p * self.xt(x) ** (self.p - 1.0)
+
+    def K(self, x):
+        return fem.stiffness_free(self.grid, self.xt(x) ** self.p, self.K0)
+
+    def Bmat(self, st):
+        return self.B(st.u) @ sp.diags(self.cfac(st.x)) @ self.W
+
+    def energy_term(self, st):
+        return self.W.T @ (self.cfac(st.x) * self.energies(st.u))
+
+    def z_preconditioner(self, st, parts):
+        F1, F2, F3, F4, F5, D, G3, B = parts
+        w = 1.0 / D
+        cf = self.cfac(st.x)
+        wt = cf ** 2 * (self.W.multiply(self.W) @ w)
+        beta = cf * (self.W @ w)
+        Bu = self.B(st.u)
+        Zuu = self.K(st.x) + Bu @ sp.diags(wt) @ Bu.T
+        bvec = Bu @ beta
+        corner = float(np.sum(beta ** 2 / wt))
+        return sp.bmat([[Zuu, sp.csr_matrix(bvec[:, None])],
+                        [sp.csr_matrix(bvec[None, :]), sp.csr_matrix([[corner]])]]).tocsr()
