@@ -285,6 +285,23 @@ int ipmg_filter(ipmg_ctx* ctx, double rmin, const double* in, double* out, int t
 int ipmg_simp_compliance(ipmg_ctx* ctx, const double* x, const double* f, double rmin, double p, double rtol,
                          int maxit, double* u, double* grad, ipmg_pcg_info* info);
 
+/* Interior-point method on the SIMP model with the density filter (Sec. 9): the
+ * method of Sec. 2-3 for min f'u with K^(x~) u = f, K^ = sum_e x~_e^p K_e, x~ = W x (the
+ * filter of ipmg_filter, radius rmin, Manhattan distance), and B(u) of the Newton
+ * system replaced by B^(u) = B(u) diag(p x~^(p-1)) W.  The Newton matrix
+ * Z^ = [[K^ + B^ D^-1 B^', B^ D^-1 e], [e'D^-1 B^', e'D^-1 e]] is applied element by
+ * element (its rank-one terms span the elements of a filter patch) inside PCG, which
+ * a V-cycle of the element-local matrix with the couplings between the elements of
+ * a patch dropped preconditions (border exact, corner chosen so that the matrix is
+ * SPD).  init: the starting point of ip_init with K^ (x = V/m, phi = psi = 1,
+ * lambda = s = r = 1, u = K^(x)^-1 f by MG-PCG).  step: one Newton step as
+ * ipmg_ip_step (same parameters, state, acceptance rule, measures and return
+ * codes).  rmin in (0, 5], pexp >= 1 (p, 3 in the paper), else IPMG_E_INVALID. */
+int ipmg_simp_ip_init(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, double rmin, double pexp,
+                      ipmg_ip_state* st, ipmg_pcg_info* info);
+int ipmg_simp_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, double rmin, double pexp,
+                      ipmg_ip_state* st, ipmg_ip_info* info);
+
 /* Kernel timing for roofline measurements.  Between begin and end, the launch of
  * the main kernel of every selected class (bit k of class_mask selects class k) is
  * bracketed by a pair of HIP events on the context's stream; the one-block

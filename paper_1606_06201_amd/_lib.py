@@ -79,6 +79,10 @@ SIGNATURES = {
                                   C.c_void_p]),
     "ipmg_ip_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.POINTER(IPState),
                                C.POINTER(IPInfo)]),
+    "ipmg_simp_ip_init": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.c_double, C.c_double,
+                                    C.POINTER(IPState), C.POINTER(PCGInfo)]),
+    "ipmg_simp_ip_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(IPParams), C.c_double, C.c_double,
+                                    C.POINTER(IPState), C.POINTER(IPInfo)]),
     "ipmg_profile_begin": (C.c_int, [C.c_void_p, C.c_uint, C.c_int]),
     "ipmg_profile_end": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
 }

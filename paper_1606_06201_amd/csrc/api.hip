@@ -317,4 +317,24 @@ int ipmg_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, ipmg
   return guard(ctx, [&](Ctx& c) { return ipmg::ip_step(c, f, *prm, *st, info); });
 }
 
+static bool simp_args_ok(double rmin, double pexp) {
+  return rmin > 0.0 && rmin <= 5.0 && pexp >= 1.0 && std::isfinite(pexp);
+}
+
+int ipmg_simp_ip_init(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, double rmin, double pexp,
+                      ipmg_ip_state* st, ipmg_pcg_info* info) {
+  if (!f || !simp_args_ok(rmin, pexp)) return IPMG_E_INVALID;
+  const int v = check_ip(prm, st);
+  if (v != IPMG_OK) return v;
+  return guard(ctx, [&](Ctx& c) { return ipmg::simp_ip_init(c, f, *prm, rmin, pexp, *st, info); });
+}
+
+int ipmg_simp_ip_step(ipmg_ctx* ctx, const double* f, const ipmg_ip_params* prm, double rmin, double pexp,
+                      ipmg_ip_state* st, ipmg_ip_info* info) {
+  if (!f || !simp_args_ok(rmin, pexp)) return IPMG_E_INVALID;
+  const int v = check_ip(prm, st);
+  if (v != IPMG_OK) return v;
+  return guard(ctx, [&](Ctx& c) { return ipmg::simp_ip_step(c, f, *prm, rmin, pexp, *st, info); });
+}
+
 }  // extern "C"

@@ -64,9 +64,26 @@ struct Ops {
   // 3D finest level: the diagonal of the hierarchy's operator per DOF slot (V-cycle
   // precision), formed once per set-up (no-op elsewhere)
   virtual void fine_diag(Ctx& c, int op) = 0;
-  // SIMP model (Sec. 9): out = W in or W' in (density filter), and x~^p / p x~^(p-1) E
-  virtual void filter(Ctx& c, double rmin, const double* in, double* out, int transpose) = 0;
+  // SIMP model (Sec. 9): the density filter (mode 0: out = W in, 1: W' in, 2: W2 in
+  // with (W2)_ji = W_ji^2), and x~^p / p x~^(p-1) E
+  virtual void filter(Ctx& c, double rmin, const double* in, double* out, int mode) = 0;
   virtual void simp_pow(Ctx& c, const double* xt, double p, double* xp, double* q) = 0;
+  // Interior-point method on the SIMP model (Sec. 9), see the kernels in ops_impl.h:
+  //   elem: g_e = K0 u_e, E_e = u_e'g_e;  design: F3 from the filtered energy term t,
+  //   G3, w = 1/D (ipG3, ipW) and the sums of ip_elements;  coef: border/rhs
+  //   coefficients, the lumped rank-one factors h64/hT and their corner
+  //   (scal[S_TMP7]);  nodes: F1, border bZ64, right-hand side;  gather: y_u +=
+  //   sum coef_e g_e + b v_lambda;  recover: d_x, d_phi, d_psi, step length.
+  virtual void simp_elem(Ctx& c, const double* u, double* g, double* E) = 0;
+  virtual void simp_design(Ctx& c, const double* t, const double* x, const double* phi, const double* psi,
+                           double lam, double s, double r, double xbar) = 0;
+  virtual void simp_coef(Ctx& c, const double* cf, const double* Ww, const double* WGw, const double* W2w,
+                         const double* g, double* bcoef, double* rcoef) = 0;
+  virtual void simp_nodes(Ctx& c, const double* Ku, const double* f, const double* u, const double* g,
+                          const double* bcoef, const double* rcoef, double* rhs) = 0;
+  virtual void simp_gather(Ctx& c, const double* g, const double* coef, const double* v, double* y) = 0;
+  virtual void simp_recover(Ctx& c, const double* btdu, const double* du, const double* x, const double* phi,
+                            const double* psi, double s, double r, double xbar, double frac, int all_blocks) = 0;
   // t_e = x_e (u_e'K0u_e)^q of the OC update (Sec. 4)
   virtual void oc_energy(Ctx& c, const double* u, const double* x, double q, double* t) = 0;
   // Interior point kernels (FP64).
@@ -178,6 +195,12 @@ struct Ctx {
   // SIMP model: filtered densities and the penalised ones (m each)
   double* simp_xt = nullptr;
   double* simp_xp = nullptr;
+  // SIMP interior point (Sec. 9): c = p x~^(p-1), g_e = K0 u_e (ND x m), E, work
+  // vectors on the design variables, border/rhs coefficients, PCG vectors (n_slots+1)
+  double *simp_cf = nullptr, *simp_g = nullptr, *simp_E = nullptr, *simp_a = nullptr, *simp_t = nullptr;
+  double *simp_b1 = nullptr, *simp_b2 = nullptr, *simp_b3 = nullptr, *simp_bcoef = nullptr, *simp_rcoef = nullptr;
+  double *simp_r = nullptr, *simp_y = nullptr, *simp_p = nullptr, *simp_q = nullptr;
+  double simp_corner = 0.0;    // corner of the exact Newton matrix, sum w
 
   // OC update: t_e = x_e E_e^q (m) and the trial multipliers of a bisection pass
   double* oc_t = nullptr;
@@ -262,6 +285,14 @@ void ip_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, const ipmg_ip_
 int ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, ipmg_ip_state& st, ipmg_ip_info* info);
 void oc_update(Ctx& c, const double* u, const double* x, double V, double xbar, double q, double lam_hi,
                double tau, const double* blend, double* x_new, ipmg_oc_info* info);
+// Interior-point method on the SIMP model (Sec. 9): initial state (as ip_init with
+// K^ in place of K) and one Newton step (as ip_step: the exact Newton matrix Z^
+// applied matrix-free, PCG preconditioned by the V-cycle of the element-local
+// approximation).
+int simp_ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, double rmin, double pexp, ipmg_ip_state& st,
+                 ipmg_pcg_info* info);
+int simp_ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, double rmin, double pexp, ipmg_ip_state& st,
+                 ipmg_ip_info* info);
 int simp_compliance(Ctx& c, const double* x, const double* f, double rmin, double p, double rtol, int maxit,
                     double* u, double* grad, ipmg_pcg_info* info);
 

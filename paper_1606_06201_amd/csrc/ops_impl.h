@@ -163,9 +163,10 @@ __device__ inline double filter_colsum(const Dims& d, int ei, int ej, int ek, do
   return s;
 }
 
+// mode 0: out = W in; 1: out = W' in; 2: out = W2 in with (W2)_ji = W_ji^2.
 template <int DIM>
 __global__ __launch_bounds__(BS) void k_filter(Dims d, double rmin, int R, const double* __restrict__ in,
-                                               double* __restrict__ out, int transpose) {
+                                               double* __restrict__ out, int mode) {
   const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (e >= d.m) return;
   int ei, ej, ek;
@@ -179,9 +180,14 @@ __global__ __launch_bounds__(BS) void k_filter(Dims d, double rmin, int R, const
         const double w = rmin - (double)(abs(dx) + abs(dy) + abs(dz));
         if (!(w > 0.0)) continue;
         const int64_t o = ((int64_t)(DIM == 3 ? k : 0) * d.ny + j) * d.nx + i;
-        acc += transpose ? w * in[o] : w * in[o] / filter_colsum<DIM>(d, i, j, k, rmin, R);
+        if (mode == 1) {
+          acc += w * in[o];
+        } else {
+          const double wc = w / filter_colsum<DIM>(d, i, j, k, rmin, R);
+          acc += mode == 2 ? wc * wc * in[o] : wc * in[o];
+        }
       }
-  out[e] = transpose ? acc / filter_colsum<DIM>(d, ei, ej, ek, rmin, R) : acc;
+  out[e] = mode == 1 ? acc / filter_colsum<DIM>(d, ei, ej, ek, rmin, R) : acc;
 }
 
 // Workgroups of a kernel (threads per group, static LDS) resident on one CU, from
@@ -431,6 +437,219 @@ __global__ __launch_bounds__(BS) void k_ip_update(Dims d, double* __restrict__ u
       psi[t] += a * dpsi[t];
     }
   }
+}
+
+// ------------------------------------------------------ SIMP interior point --
+// The interior-point method on the SIMP model (Sec. 9): K^ = sum x~^p K_e with the
+// filtered densities x~ = W x, and B^(u) = B(u) C W in place of B(u) in the Newton
+// system, C = diag(c), c = p x~^(p-1), B(u) = (K_1 u, ..., K_m u) with the unit
+// element matrices.  The exact Newton matrix Z^ is applied matrix-free; the
+// multigrid hierarchy is built from an element-local SPD approximation (the
+// couplings between the elements of a filter patch dropped).
+
+// g_e = K0 u_e (entry r at r m + e) and E_e = u_e'g_e.
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_simp_elem(Dims d, const double* __restrict__ u, double* __restrict__ g,
+                                                  double* __restrict__ E) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (e >= d.m) return;
+  int ei, ej, ek;
+  elem_coords<DIM>(d, e, ei, ej, ek);
+  double ue[ND];
+  gather_elem<DIM>(u, d, ei, ej, ek, ue);
+  double en = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < ND; ++rr) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) t += cK0d[rr * ND + c] * ue[c];
+    g[rr * d.m + e] = t;
+    en += ue[rr] * t;
+  }
+  E[e] = en;
+}
+
+// Per design variable, with t = W'(c o E) (the filtered energy term of the modified
+// KKT3): F3 = -t/2 - lambda - phi + psi, F4, F5, D, G3, w = 1/D, and the sums of
+// k_ip_elements (finalized by k_ip_elements_fin into scal[S_TMP0..6]).
+static __global__ __launch_bounds__(BS) void k_simp_design(int64_t m, const double* __restrict__ t,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ psi, double lam, double s,
+                                                           double r, double xbar, double* __restrict__ G3o,
+                                                           double* __restrict__ Wo, Red red) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (e < m) {
+    const double xe = x[e], ph = phi[e], ps = psi[e], xt = xbar - xe;
+    if (!(xe > 0.0) || !(xt > 0.0) || !isfinite(xe) || !isfinite(ph) || !isfinite(ps) || !isfinite(t[e]))
+      red.flags[F_BAD] = 1;
+    const double F3 = -0.5 * t[e] - lam - ph + ps;
+    const double F4 = ph * xe - s;
+    const double F5 = ps * xt - r;
+    const double D = ph / xe + ps / xt;
+    const double G3 = F3 + F4 / xe - F5 / xt;
+    const double w = 1.0 / D;
+    G3o[e] = G3;
+    Wo[e] = w;
+    acc[0] = w; acc[1] = G3 * w; acc[2] = xe; acc[3] = G3 * G3;
+    acc[4] = ph * ph; acc[5] = ps * ps; acc[6] = ph * xe + ps * xt;
+  }
+  block_partials<7>(acc, red);
+}
+
+// Per element: bcoef = c (W w), rcoef = c (W (G3 w)) (coefficients of K0 u_e in the
+// border B^ D^-1 e and in B^ D^-1 G3), the lumped rank-one weight wt = c^2 (W2 w)
+// ((W2)_ji = W_ji^2), the preconditioner's factor h_e = sqrt(wt) g_e (h64, and the
+// V-cycle copy hT), and the partials of its corner sum bcoef^2 / wt.
+template <int DIM, typename T>
+__global__ __launch_bounds__(BS) void k_simp_coef(Dims d, const double* __restrict__ cf,
+                                                  const double* __restrict__ Ww, const double* __restrict__ WGw,
+                                                  const double* __restrict__ W2w, const double* __restrict__ g,
+                                                  double* __restrict__ bcoef, double* __restrict__ rcoef,
+                                                  double* __restrict__ h64, T* __restrict__ hT, Red red) {
+  constexpr int ND = Geo<DIM>::ND;
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (e < d.m) {
+    const double c = cf[e], bc = c * Ww[e], wt = c * c * W2w[e], sw = sqrt(wt);
+    bcoef[e] = bc;
+    rcoef[e] = c * WGw[e];
+#pragma unroll
+    for (int rr = 0; rr < ND; ++rr) {
+      const double hv = sw * g[rr * d.m + e];
+      h64[rr * d.m + e] = hv;
+      if (hT) hT[rr * d.m + e] = T(hv);
+    }
+    acc[0] = bc * bc / wt;
+    if (!(wt > 0.0) || !isfinite(wt)) red.flags[F_BAD] = 1;
+  }
+  block_partials<1>(acc, red);
+}
+
+static __global__ __launch_bounds__(BS) void k_simp_coef_fin(Red red, unsigned nblocks) {
+  double tot[1];
+  sum_partials<1>(red, nblocks, tot);
+  if (threadIdx.x == 0) red.scal[S_TMP7] = tot[0];
+}
+
+// Per node: F1 = K^ u - f, the border b = sum_e bcoef_e g_e (= B^ D^-1 e) and
+// rhs_u = -F1 + sum_e rcoef_e g_e (= -F1 + B^ D^-1 G3); sums as k_ip_nodes
+// (finalized by k_ip_nodes_fin).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_simp_nodes(Dims d, const double* __restrict__ Ku,
+                                                   const double* __restrict__ f, const double* __restrict__ u,
+                                                   const double* __restrict__ g, const double* __restrict__ bcoef,
+                                                   const double* __restrict__ rcoef, double* __restrict__ rhs,
+                                                   double* __restrict__ bZ, Red red) {
+  constexpr int NN = Geo<DIM>::NN;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
+  double acc[3] = {0, 0, 0};
+  if (i < d.nx1 && j < d.ny1) {
+    const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+    double bb[DIM], tt[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { bb[c] = 0.0; tt[c] = 0.0; }
+    if (i > 0) {
+#pragma unroll
+      for (int qq = 0; qq < NN; ++qq) {
+        const int ex = qq & 1, ey = (qq >> 1) & 1, ez = (qq >> 2) & 1;
+        const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+        if (ei < 0 || ei >= d.nx || ej < 0 || ej >= d.ny || (DIM == 3 && (ek < 0 || ek >= d.nz))) continue;
+        const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
+        const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const double gv = g[(a * DIM + c) * d.m + e];
+          bb[c] += bcoef[e] * gv;
+          tt[c] += rcoef[e] * gv;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t sl = q * DIM + c;
+      const double fc = i > 0 ? f[sl] : 0.0;
+      const double F1 = i > 0 ? Ku[sl] - fc : 0.0;
+      rhs[sl] = i > 0 ? -F1 + tt[c] : 0.0;
+      bZ[sl] = bb[c];
+      acc[0] += F1 * F1;
+      acc[1] += fc * fc;
+      acc[2] += fc * (i > 0 ? u[sl] : 0.0);
+    }
+  }
+  block_partials<3>(acc, red);
+}
+
+// y_u += sum_e coef_e g_e + b v_lambda on the free slots: the rank-one and border
+// part of Z^ v (coef = c o W (w o W'(c o s)), s_e = g_e . v_e).
+template <int DIM>
+__global__ __launch_bounds__(BS) void k_simp_gather(Dims d, const double* __restrict__ g,
+                                                    const double* __restrict__ coef, const double* __restrict__ bZ,
+                                                    const double* __restrict__ v, double* __restrict__ y) {
+  constexpr int NN = Geo<DIM>::NN;
+  const Tile tl = xcd_tile();
+  const int i = tl.x * 64 + (threadIdx.x & 63);
+  const int j = tl.y * (BS / 64) + (threadIdx.x >> 6);
+  const int k = tl.z;
+  if (i < 1 || i >= d.nx1 || j >= d.ny1) return;
+  const int64_t q = ((int64_t)k * d.ny1 + j) * d.nx1 + i;
+  double tt[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) tt[c] = 0.0;
+#pragma unroll
+  for (int qq = 0; qq < NN; ++qq) {
+    const int ex = qq & 1, ey = (qq >> 1) & 1, ez = (qq >> 2) & 1;
+    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    if (ei < 0 || ei >= d.nx || ej < 0 || ej >= d.ny || (DIM == 3 && (ek < 0 || ek >= d.nz))) continue;
+    const int64_t e = ((int64_t)(DIM == 3 ? ek : 0) * d.ny + ej) * d.nx + ei;
+    const int a = loc_index(1 - ex, 1 - ey, DIM == 3 ? 1 - ez : 0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) tt[c] += coef[e] * g[(a * DIM + c) * d.m + e];
+  }
+  const double vl = v[d.nslots];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t sl = q * DIM + c;
+    y[sl] += tt[c] + bZ[sl] * vl;
+  }
+}
+
+// Recovery of the SIMP direction: d_x = w (B^'d_u + d_lambda - G3) with btdu =
+// B^'d_u = W'(c o (g . d_u)), d_phi, d_psi and the step-length minima (finalized by
+// k_ip_recover_fin).
+static __global__ __launch_bounds__(BS) void k_simp_recover(int64_t m, int64_t nslots,
+                                                            const double* __restrict__ btdu,
+                                                            const double* __restrict__ du,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ phi,
+                                                            const double* __restrict__ psi,
+                                                            const double* __restrict__ G3,
+                                                            const double* __restrict__ W, double s, double r,
+                                                            double xbar, double* __restrict__ dx,
+                                                            double* __restrict__ dphi, double* __restrict__ dpsi,
+                                                            Red red) {
+  const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double mins[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  if (e < m) {
+    const double dl = du[nslots];
+    const double xe = x[e], ph = phi[e], ps = psi[e], xt = xbar - xe;
+    const double ddx = W[e] * (btdu[e] + dl - G3[e]);
+    const double F4 = ph * xe - s, F5 = ps * xt - r;
+    const double ddphi = (-F4 - ph * ddx) / xe;
+    const double ddpsi = (-F5 + ps * ddx) / xt;
+    dx[e] = ddx; dphi[e] = ddphi; dpsi[e] = ddpsi;
+    if (!isfinite(ddx) || !isfinite(ddphi) || !isfinite(ddpsi) || !isfinite(dl)) red.flags[F_BAD] = 1;
+    if (ddx < 0.0) mins[0] = -xe / ddx;
+    if (ddx > 0.0) mins[1] = xt / ddx;
+    if (ddphi < 0.0) mins[2] = -ph / ddphi;
+    if (ddpsi < 0.0) mins[3] = -ps / ddpsi;
+  }
+  block_partials<4, true>(mins, red);
 }
 
 // ------------------------------------------------------------------- dispatch --
@@ -1084,10 +1303,10 @@ struct OpsImpl : Ops {
     else k_power_start<DIM, double><<<lin_grid(d.nslots + 1), BS, 0, c.stream>>>(d, aug, (double*)v);
   }
 
-  void filter(Ctx& c, double rmin, const double* in, double* out, int transpose) override {
+  void filter(Ctx& c, double rmin, const double* in, double* out, int mode) override {
     const Dims& d = c.fine();
     const int R = (int)std::ceil(rmin) - 1;
-    k_filter<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, rmin, R, in, out, transpose);
+    k_filter<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, rmin, R, in, out, mode);
   }
   void simp_pow(Ctx& c, const double* xt, double p, double* xp, double* q) override {
     k_simp_pow<<<lin_grid(c.fine().m), BS, 0, c.stream>>>(c.fine().m, xt, p, xp, q);
@@ -1133,6 +1352,47 @@ struct OpsImpl : Ops {
     const int64_t n = d.nslots > d.m ? d.nslots : d.m;
     const unsigned g = lin_grid(n) < 2048 ? lin_grid(n) : 2048;
     k_ip_update<DIM><<<g, BS, 0, c.stream>>>(d, u, du, x, phi, psi, c.ipDx, c.ipDphi, c.ipDpsi, c.red);
+  }
+
+  void simp_elem(Ctx& c, const double* u, double* g, double* E) override {
+    const Dims& d = c.fine();
+    k_simp_elem<DIM><<<lin_grid(d.m), BS, 0, c.stream>>>(d, u, g, E);
+  }
+  void simp_design(Ctx& c, const double* t, const double* x, const double* phi, const double* psi, double lam,
+                   double s, double r, double xbar) override {
+    const Dims& d = c.fine();
+    IPMG_REQUIRE(lin_grid(d.m) <= (unsigned)MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+    k_simp_design<<<lin_grid(d.m), BS, 0, c.stream>>>(d.m, t, x, phi, psi, lam, s, r, xbar, c.ipG3, c.ipW, c.red);
+    k_ip_elements_fin<<<1, BS, 0, c.stream>>>(c.red, lin_grid(d.m));
+  }
+  void simp_coef(Ctx& c, const double* cf, const double* Ww, const double* WGw, const double* W2w, const double* g,
+                 double* bcoef, double* rcoef) override {
+    const Dims& d = c.fine();
+    if (c.fp32)
+      k_simp_coef<DIM, float><<<lin_grid(d.m), BS, 0, c.stream>>>(d, cf, Ww, WGw, W2w, g, bcoef, rcoef, c.h64,
+                                                                  (float*)c.hT, c.red);
+    else
+      k_simp_coef<DIM, double><<<lin_grid(d.m), BS, 0, c.stream>>>(d, cf, Ww, WGw, W2w, g, bcoef, rcoef, c.h64,
+                                                                   nullptr, c.red);
+    k_simp_coef_fin<<<1, BS, 0, c.stream>>>(c.red, lin_grid(d.m));
+  }
+  void simp_nodes(Ctx& c, const double* Ku, const double* f, const double* u, const double* g, const double* bcoef,
+                  const double* rcoef, double* rhs) override {
+    const Dims& d = c.fine();
+    const dim3 gr = node_grid(d);
+    k_simp_nodes<DIM><<<gr, BS, 0, c.stream>>>(d, Ku, f, u, g, bcoef, rcoef, rhs, c.bZ64, c.red);
+    k_ip_nodes_fin<<<1, BS, 0, c.stream>>>(c.red, gr.x * gr.y * gr.z, c.ipV, rhs, d.nslots);
+  }
+  void simp_gather(Ctx& c, const double* g, const double* coef, const double* v, double* y) override {
+    const Dims& d = c.fine();
+    k_simp_gather<DIM><<<node_grid(d), BS, 0, c.stream>>>(d, g, coef, c.bZ64, v, y);
+  }
+  void simp_recover(Ctx& c, const double* btdu, const double* du, const double* x, const double* phi,
+                    const double* psi, double s, double r, double xbar, double frac, int all_blocks) override {
+    const Dims& d = c.fine();
+    k_simp_recover<<<lin_grid(d.m), BS, 0, c.stream>>>(d.m, d.nslots, btdu, du, x, phi, psi, c.ipG3, c.ipW, s, r,
+                                                       xbar, c.ipDx, c.ipDphi, c.ipDpsi, c.red);
+    k_ip_recover_fin<<<1, BS, 0, c.stream>>>(c.red, lin_grid(d.m), frac, all_blocks);
   }
 };
 

@@ -265,6 +265,9 @@ void ctx_free(Ctx& c) {
   dfree(c.ipG3); dfree(c.ipW); dfree(c.ipSW); dfree(c.ipDx); dfree(c.ipDphi); dfree(c.ipDpsi);
   dfree(c.ipRhs); dfree(c.ipD); dfree(c.ipKu);
   dfree(c.oc_t); dfree(c.oc_cand); dfree(c.ye); dfree(c.simp_xt); dfree(c.simp_xp);
+  for (double** b : {&c.simp_cf, &c.simp_g, &c.simp_E, &c.simp_a, &c.simp_t, &c.simp_b1, &c.simp_b2, &c.simp_b3,
+                     &c.simp_bcoef, &c.simp_rcoef, &c.simp_r, &c.simp_y, &c.simp_p, &c.simp_q})
+    dfree(*b);
   if (c.fine_ye != (void*)c.fine_ye64) dfree(c.fine_ye);
   c.fine_ye = nullptr;
   dfree(c.fine_ye64); dfree(c.fine_dg);
@@ -722,6 +725,236 @@ int simp_compliance(Ctx& c, const double* x, const double* f, double rmin, doubl
   vscale(c.stream, grad, -1.0, d.m);
   IPMG_HIP(hipGetLastError());
   sync(c);
+  return IPMG_OK;
+}
+
+// ------------------------------------------------------- SIMP interior point --
+static void ensure_simp_buffers(Ctx& c) {
+  if (c.simp_cf) return;
+  const Dims& d = c.fine();
+  const size_t m = (size_t)d.m, n1 = (size_t)d.nslots + 1;
+  if (!c.simp_xt) dalloc(c.simp_xt, sizeof(double) * m);
+  if (!c.simp_xp) dalloc(c.simp_xp, sizeof(double) * m);
+  for (double** b : {&c.simp_cf, &c.simp_E, &c.simp_a, &c.simp_t, &c.simp_b1, &c.simp_b2, &c.simp_b3, &c.simp_bcoef,
+                     &c.simp_rcoef})
+    dalloc(*b, sizeof(double) * m);
+  dalloc(c.simp_g, sizeof(double) * (size_t)c.nd * m);
+  for (double** b : {&c.simp_r, &c.simp_y, &c.simp_p, &c.simp_q}) dalloc(*b, sizeof(double) * n1);
+}
+
+// x~ = W x, K^ = sum x~^p K_e (set as the densities), c = p x~^(p-1).
+static void simp_densities(Ctx& c, const double* x, double rmin, double pexp) {
+  const Dims& d = c.fine();
+  c.ops->filter(c, rmin, x, c.simp_xt, 0);
+  c.ops->simp_pow(c, c.simp_xt, pexp, c.simp_xp, nullptr);
+  vfill(c.stream, c.simp_cf, 1.0, d.m);
+  c.ops->simp_pow(c, c.simp_xt, pexp, nullptr, c.simp_cf);
+  IPMG_HIP(hipGetLastError());
+  set_density(c, c.simp_xp);
+}
+
+// The SIMP Newton system at st (Sec. 9 with Sec. 2): residuals, G3 and w (ipG3,
+// ipW), right-hand side (ipRhs), the exact border b = B^ D^-1 e (bZ64) and corner
+// sum w (simp_corner), and the preconditioner's element-local rank-one factors
+// (h64/hT) and corner (cZ).  Measures in hscal as ip_prepare.
+static void simp_prepare(Ctx& c, const double* f, const ipmg_ip_params& p, double rmin, double pexp,
+                         const ipmg_ip_state& st) {
+  ensure_z_buffers(c);
+  ensure_simp_buffers(c);
+  const Dims& d = c.fine();
+  c.ipV = p.V;
+  simp_densities(c, st.x, rmin, pexp);
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  c.ops->simp_elem(c, st.u, c.simp_g, c.simp_E);
+  vmul(c.stream, c.simp_cf, c.simp_E, c.simp_a, d.m);
+  c.ops->filter(c, rmin, c.simp_a, c.simp_t, 1);                         // W'(c o E)
+  c.ops->simp_design(c, c.simp_t, st.x, st.phi, st.psi, st.lam, st.s, st.r, p.xbar);
+  c.ops->filter(c, rmin, c.ipW, c.simp_b1, 0);                           // W w
+  vmul(c.stream, c.ipG3, c.ipW, c.simp_a, d.m);
+  c.ops->filter(c, rmin, c.simp_a, c.simp_b2, 0);                        // W (G3 o w)
+  c.ops->filter(c, rmin, c.ipW, c.simp_b3, 2);                           // W2 w
+  c.ops->simp_coef(c, c.simp_cf, c.simp_b1, c.simp_b2, c.simp_b3, c.simp_g, c.simp_bcoef, c.simp_rcoef);
+  c.ops->fine_apply64(c, IPMG_OP_K, st.u, c.ipKu, nullptr);
+  c.ops->simp_nodes(c, c.ipKu, f, st.u, c.simp_g, c.simp_bcoef, c.simp_rcoef, c.ipRhs);
+  IPMG_HIP(hipGetLastError());
+  read_scalars(c);
+  IPMG_REQUIRE(!c.hflags[F_BAD], IPMG_E_DOMAIN, "interior-point iterate left the interior or is not finite");
+  c.simp_corner = c.hscal[S_TMP0];
+  c.cZ = c.hscal[S_TMP7];
+  c.have_z = true;
+  c.hier_op = -1;
+}
+
+// y = Z^ v (n_slots + 1): K^ v_u + B^ D^-1 B^' v_u + b v_lambda, b' v_u + (sum w) v_lambda,
+// with B^' v_u = W'(c o s), s_e = v_e'K0u_e, and B^ t = sum_e c_e (W t)_e K0 u_e.
+static void simp_apply(Ctx& c, double rmin, const double* u, const double* v, double* y) {
+  const Dims& d = c.fine();
+  c.ops->fine_apply64(c, IPMG_OP_K, v, y, nullptr);
+  c.ops->element_sens(c, v, u, 1.0, c.simp_a);
+  vmul(c.stream, c.simp_cf, c.simp_a, c.simp_a, d.m);
+  c.ops->filter(c, rmin, c.simp_a, c.simp_b1, 1);
+  vmul(c.stream, c.simp_b1, c.ipW, c.simp_b1, d.m);
+  c.ops->filter(c, rmin, c.simp_b1, c.simp_a, 0);
+  vmul(c.stream, c.simp_cf, c.simp_a, c.simp_a, d.m);
+  c.ops->simp_gather(c, c.simp_g, c.simp_a, v, y);
+  vdot(c.stream, c.bZ64, v, d.nslots, c.red, S_TMP4, nullptr);
+  vlam_row(c.stream, y, v, c.red, S_TMP4, c.simp_corner, d.nslots);
+  IPMG_HIP(hipGetLastError());
+}
+
+// Algorithm PCG (the recurrence, stopping test and true-residual restart of pcg)
+// on Z^ with the V-cycle of the prepared hierarchy, from z (from_z) or from 0.
+static int simp_pcg(Ctx& c, double rmin, const double* u, const double* b, double* z, double rtol, int maxit,
+                    bool from_z, ipmg_pcg_info* info) {
+  const Dims& d = c.fine();
+  const int64_t n1 = d.nslots + 1;
+  auto t0 = std::chrono::steady_clock::now();
+  auto dot = [&](const double* a, const double* bb) {
+    vdot(c.stream, a, bb, n1, c.red, S_TMP5, nullptr);
+    double v = 0.0;
+    IPMG_HIP(hipMemcpyAsync(&v, c.red.scal + S_TMP5, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+    return v;
+  };
+  double *r = c.simp_r, *y = c.simp_y, *pp = c.simp_p, *q = c.simp_q;
+  ipmg_pcg_info inf{};
+  const double bnorm = std::sqrt(dot(b, b));
+  auto finish = [&](int status, int iters, double rel) {
+    simp_apply(c, rmin, u, z, q);
+    vlincomb(c.stream, q, 1.0, q, -1.0, b, n1);
+    inf.iters = iters;
+    inf.status = status;
+    inf.relres = rel;
+    inf.true_relres = bnorm > 0.0 ? std::sqrt(dot(q, q)) / bnorm : 0.0;
+    inf.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
+  };
+  if (!from_z) IPMG_HIP(hipMemsetAsync(z, 0, sizeof(double) * n1, c.stream));
+  if (bnorm == 0.0) return finish(IPMG_OK, 0, 0.0);
+  simp_apply(c, rmin, u, z, r);
+  vlincomb(c.stream, r, 1.0, r, -1.0, b, n1);                 // r = A z - b
+  double rel = std::sqrt(dot(r, r)) / bnorm;
+  if (rel <= rtol) return finish(IPMG_OK, 0, rel);
+  vcycle64(c, IPMG_OP_Z, r, y);
+  vlincomb(c.stream, pp, -1.0, y, 0.0, y, n1);
+  double rho = dot(r, y);
+  if (!(rho > 0.0)) return finish(IPMG_E_BREAKDOWN, 0, rel);
+  int iters = 0;
+  while (iters < maxit) {
+    simp_apply(c, rmin, u, pp, q);
+    const double pq = dot(pp, q);
+    if (!(pq > 0.0)) return finish(IPMG_E_BREAKDOWN, iters, rel);
+    const double alpha = rho / pq;
+    vlincomb(c.stream, z, 1.0, z, alpha, pp, n1);
+    vlincomb(c.stream, r, 1.0, r, alpha, q, n1);
+    ++iters;
+    rel = std::sqrt(dot(r, r)) / bnorm;
+    if (rel <= rtol) {
+      simp_apply(c, rmin, u, z, q);
+      vlincomb(c.stream, q, 1.0, q, -1.0, b, n1);
+      if (std::sqrt(dot(q, q)) / bnorm <= rtol) return finish(IPMG_OK, iters, rel);
+      ++inf.restarts;
+      IPMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n1, hipMemcpyDeviceToDevice, c.stream));
+      vcycle64(c, IPMG_OP_Z, r, y);
+      vlincomb(c.stream, pp, -1.0, y, 0.0, y, n1);
+      rho = dot(r, y);
+      continue;
+    }
+    vcycle64(c, IPMG_OP_Z, r, y);
+    const double rho_new = dot(r, y);
+    if (!(rho_new > 0.0)) return finish(IPMG_E_BREAKDOWN, iters, rel);
+    vlincomb(c.stream, pp, -1.0, y, rho_new / rho, pp, n1);
+    rho = rho_new;
+  }
+  return finish(IPMG_E_NOT_CONVERGED, iters, rel);
+}
+
+int simp_ip_init(Ctx& c, const double* f, const ipmg_ip_params& p, double rmin, double pexp, ipmg_ip_state& st,
+                 ipmg_pcg_info* info) {
+  const Dims& d = c.fine();
+  IPMG_REQUIRE(p.xbar > 0.0 && p.V > 0.0 && p.V < p.xbar * (double)d.m, IPMG_E_DOMAIN,
+               "need 0 < V < m * xbar");
+  ensure_simp_buffers(c);
+  vfill(c.stream, st.x, p.V / (double)d.m, d.m);
+  vfill(c.stream, st.phi, 1.0, d.m);
+  vfill(c.stream, st.psi, 1.0, d.m);
+  IPMG_HIP(hipMemsetAsync(st.u, 0, sizeof(double) * d.nslots, c.stream));
+  st.lam = 1.0;
+  st.s = 1.0;
+  st.r = 1.0;
+  simp_densities(c, st.x, rmin, pexp);
+  return pcg(c, IPMG_OP_K, f, st.u, p.pcg_rtol, p.pcg_maxit, info);
+}
+
+int simp_ip_step(Ctx& c, const double* f, const ipmg_ip_params& p, double rmin, double pexp, ipmg_ip_state& st,
+                 ipmg_ip_info* info) {
+  const Dims& d = c.fine();
+  ipmg_ip_info inf{};
+  simp_prepare(c, f, p, rmin, pexp, st);
+  double setup_ms = 0.0;
+  mg_setup(c, IPMG_OP_Z, &setup_ms);
+  ipmg_pcg_info pin{};
+  int ps = simp_pcg(c, rmin, st.u, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, false, &pin);
+  if (ps == IPMG_E_BREAKDOWN) {   // as ip_step: damping estimated again, continued from the last iterate
+    const int first = pin.iters;
+    const double first_ms = pin.solve_ms;
+    for (int k = 1; k < c.L; ++k)
+      jacobi_damping(c, k, IPMG_OP_Z, RETRY_POWER_FACTOR * c.power_steps_z, SAFE_PRODUCT_RETRY);
+    IPMG_HIP(hipGetLastError());
+    ps = simp_pcg(c, rmin, st.u, c.ipRhs, c.ipD, p.pcg_rtol, p.pcg_maxit, true, &pin);
+    pin.iters += first;
+    pin.solve_ms += first_ms;
+    inf.pcg_retries = 1;
+  }
+  inf.pcg_iters = pin.iters;
+  inf.pcg_status = ps;
+  inf.pcg_true_relres = pin.true_relres;
+  inf.setup_ms = setup_ms;
+  inf.solve_ms = pin.solve_ms;
+  if (ps != IPMG_OK && !(ps == IPMG_E_NOT_CONVERGED && pin.true_relres <= p.accept_rtol)) {
+    if (info) *info = inf;
+    return ps;
+  }
+  // d_x = w (B^'d_u + d_lambda - G3), B^'d_u = W'(c o s), s_e = d_u,e'K0u_e
+  c.ops->element_sens(c, c.ipD, st.u, 1.0, c.simp_a);
+  vmul(c.stream, c.simp_cf, c.simp_a, c.simp_a, d.m);
+  c.ops->filter(c, rmin, c.simp_a, c.simp_t, 1);
+  IPMG_HIP(hipMemsetAsync(c.red.flags + F_BAD, 0, sizeof(int), c.stream));
+  c.ops->simp_recover(c, c.simp_t, c.ipD, st.x, st.phi, st.psi, st.s, st.r, p.xbar, p.frac, p.step_all_blocks);
+  double dlam = 0.0;
+  IPMG_HIP(hipMemcpyAsync(&dlam, c.ipD + d.nslots, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  read_scalars(c);
+  const double alpha = c.hscal[S_ALPHA];
+  inf.alpha = alpha;
+  if (!(alpha >= 1e-14) || !std::isfinite(dlam) || c.hflags[F_BAD]) {
+    if (info) *info = inf;
+    return IPMG_E_STALLED;
+  }
+  c.ops->ip_update(c, st.u, c.ipD, st.x, st.phi, st.psi);
+  st.lam += alpha * dlam;
+  simp_prepare(c, f, p, rmin, pexp, st);   // measures at the new iterate
+  const double* S = c.hscal;
+  const double nF1 = std::sqrt(S[S_MIN0]), nf = std::sqrt(S[S_MIN1]);
+  const double nG3 = std::sqrt(S[S_TMP3]), nphi = std::sqrt(S[S_TMP4]), npsi = std::sqrt(S[S_TMP5]);
+  inf.nwt = nF1 / nf + nG3 / (nphi + npsi);
+  inf.compliance = S[S_MIN2];
+  inf.gap = S[S_TMP6] / S[S_MIN2];
+  inf.volume_res = S[S_TMP2] - p.V;
+  if (!std::isfinite(inf.nwt) || !std::isfinite(inf.gap)) {
+    if (info) *info = inf;
+    return IPMG_E_DOMAIN;
+  }
+  const bool newton_ok = inf.nwt <= p.tau_nwt;
+  if (p.stop_rule == 0 && newton_ok && inf.gap <= p.kkt_tol) {
+    inf.converged = 1;
+  } else if (newton_ok) {
+    st.s *= p.sigma;
+    st.r *= p.sigma;
+    inf.barrier_updated = 1;
+    if (p.stop_rule == 1 && std::fmax(st.s, st.r) <= p.tau_ip) inf.converged = 1;
+  }
+  if (info) *info = inf;
   return IPMG_OK;
 }
 

@@ -32,6 +32,11 @@ template <typename T>
 void vnormalize(hipStream_t st, T* x, int64_t n, const Red& red, int sidx);
 void vfill(hipStream_t st, double* dst, double value, int64_t n);
 void vscale(hipStream_t st, double* v, double a, int64_t n);   // v *= a
+void vmul(hipStream_t st, const double* a, const double* b, double* out, int64_t n);   // out = a o b
+void vlincomb(hipStream_t st, double* out, double a, const double* x, double b, const double* y,
+              int64_t n);   // out = a x + b y (out may alias x or y)
+void vlam_row(hipStream_t st, double* y, const double* v, const Red& red, int sidx, double c,
+              int64_t n);   // y[n] = scal[sidx] + c v[n]
 void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red);
 void vset_omega(hipStream_t st, const Red& red, double* w, double* rho, int s_vav, int s_vdv, double omega,
                 double product);

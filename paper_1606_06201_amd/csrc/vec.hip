@@ -326,8 +326,31 @@ namespace {
 __global__ __launch_bounds__(BS) void k_scale(double* __restrict__ v, double a, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) v[t] *= a;
 }
+__global__ __launch_bounds__(BS) void k_mul(const double* __restrict__ a, const double* __restrict__ b,
+                                            double* __restrict__ out, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) out[t] = a[t] * b[t];
+}
+__global__ __launch_bounds__(BS) void k_lincomb(double* __restrict__ out, double a, const double* __restrict__ x,
+                                                double b, const double* __restrict__ y, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS)
+    out[t] = a * x[t] + b * y[t];
+}
+// y[n] = scal[sidx] + c v[n]: the lambda row of an augmented operator, b'v_u in scal.
+__global__ void k_lam_row(double* __restrict__ y, const double* __restrict__ v, Red red, int sidx, double c,
+                          int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) y[n] = red.scal[sidx] + c * v[n];
+}
 }  // namespace
 void vscale(hipStream_t st, double* v, double a, int64_t n) { k_scale<<<vgrid(n), BS, 0, st>>>(v, a, n); }
+void vmul(hipStream_t st, const double* a, const double* b, double* out, int64_t n) {
+  k_mul<<<vgrid(n), BS, 0, st>>>(a, b, out, n);
+}
+void vlincomb(hipStream_t st, double* out, double a, const double* x, double b, const double* y, int64_t n) {
+  k_lincomb<<<vgrid(n), BS, 0, st>>>(out, a, x, b, y, n);
+}
+void vlam_row(hipStream_t st, double* y, const double* v, const Red& red, int sidx, double c, int64_t n) {
+  k_lam_row<<<1, 64, 0, st>>>(y, v, red, sidx, c, n);
+}
 void vcopy_positive(hipStream_t st, const double* src, double* dst, int64_t n, const Red& red) {
   k_copy_positive<<<vgrid(n), BS, 0, st>>>(src, dst, n, red);
 }

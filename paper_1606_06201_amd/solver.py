@@ -323,12 +323,18 @@ class Solver:
     def _state_back(s, st):
         st["lam"], st["s"], st["r"] = s.lam, s.s, s.r
 
-    def ip_init(self, f, params, state=None):
+    def ip_init(self, f, params, state=None, simp=None):
+        """Starting point of the interior-point method; simp=(rmin, p): the SIMP model
+        with the density filter (Sec. 9)."""
         st = self.new_ip_state() if state is None else state
         s = self._state_struct(st)
         info = L.PCGInfo()
-        self._call(self.lib.ipmg_ip_init, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
-                   C.byref(info))
+        if simp is None:
+            self._call(self.lib.ipmg_ip_init, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
+                       C.byref(info))
+        else:
+            self._call(self.lib.ipmg_simp_ip_init, self._ptr(f, self.n_slots, "f"), C.byref(params),
+                       float(simp[0]), float(simp[1]), C.byref(s), C.byref(info))
         self._state_back(s, st)
         return st, dict(iters=info.iters, true_relres=info.true_relres)
 
@@ -339,11 +345,17 @@ class Solver:
                    self._ptr(rhs, self.n_slots + 1, "rhs"))
         return rhs
 
-    def ip_step(self, f, params, st):
+    def ip_step(self, f, params, st, simp=None):
+        """One Newton step; simp=(rmin, p): on the SIMP model (Sec. 9)."""
         s = self._state_struct(st)
         info = L.IPInfo()
-        rc = self._call(self.lib.ipmg_ip_step, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
-                        C.byref(info), allow=(L.E_STALLED, L.E_BREAKDOWN, L.E_NOT_CONVERGED))
+        allow = (L.E_STALLED, L.E_BREAKDOWN, L.E_NOT_CONVERGED)
+        if simp is None:
+            rc = self._call(self.lib.ipmg_ip_step, self._ptr(f, self.n_slots, "f"), C.byref(params), C.byref(s),
+                            C.byref(info), allow=allow)
+        else:
+            rc = self._call(self.lib.ipmg_simp_ip_step, self._ptr(f, self.n_slots, "f"), C.byref(params),
+                            float(simp[0]), float(simp[1]), C.byref(s), C.byref(info), allow=allow)
         self._state_back(s, st)
         return dict(alpha=info.alpha, nwt=info.nwt, gap=info.gap, volume_res=info.volume_res,
                     compliance=info.compliance, pcg_iters=info.pcg_iters, pcg_status=info.pcg_status,
@@ -351,19 +363,20 @@ class Solver:
                     barrier_updated=info.barrier_updated,
                     converged=info.converged, setup_ms=info.setup_ms, solve_ms=info.solve_ms, rc=rc)
 
-    def ip_run(self, f, params, callback=None, cg_tol_factor=1.0):
+    def ip_run(self, f, params, callback=None, cg_tol_factor=1.0, simp=None):
         """Interior-point loop (Sec. 3.1): init, then Newton steps until the stop rule.
         log["short_solves"] counts Newton systems whose solve stopped at pcg_maxit and
         was taken as an inexact direction (true residual within accept_rtol); a solve
         that broke down or stopped above that bound ends the run ("solve_failed").
         cg_tol_factor < 1: the "CG tol decreasing" variant of Sec. 8.1, the PCG
-        tolerance multiplied by this factor after every barrier update (0.5 there)."""
+        tolerance multiplied by this factor after every barrier update (0.5 there).
+        simp=(rmin, p): the SIMP model with the density filter (Sec. 9)."""
         params = L.IPParams.from_buffer_copy(params)
-        st, init = self.ip_init(f, params)
+        st, init = self.ip_init(f, params, simp=simp)
         log = dict(newton=0, barrier_updates=0, pcg_iters=[init["iters"]], steps=[], status="max_newton",
                    short_solves=0, retries=0)
         while log["newton"] < params.max_newton:
-            inf = self.ip_step(f, params, st)
+            inf = self.ip_step(f, params, st, simp=simp)
             if inf["rc"] in (L.E_BREAKDOWN, L.E_NOT_CONVERGED):
                 log["steps"].append(inf)
                 log["status"] = "solve_failed"
