@@ -1852,48 +1852,150 @@ __global__ __launch_bounds__(BS) void k_prolong(Dims f, Dims c, T* __restrict__ 
 // W_e interpolates the 2^dim coarse corner values of C to the nodes of fine
 // element e (each fine node interpolates only from the corners of the coarse
 // element containing it, so the sum equals the Galerkin product P' A P).
-// One thread per (coarse element, coarse local row R); writes the packed
-// entries (R, col >= R).  Accumulation in FP64, stored as T.
-template <int DIM, typename T, class Op>
-__global__ __launch_bounds__(BS) void k_galerkin(Op op, Dims f, Dims c, T* __restrict__ Ec) {
+// One wave per (64 coarse elements, coarse local row R = (A, comp)): the lane is
+// the coarse element, R is the same on every lane, so the interpolation weights
+// that select the fine rows are uniform and the zero ones are skipped without
+// divergence.  For each fine sub-element q of C:
+//   t = sum_a W_q[a][A] A_q[(a, comp), :]                (row combination, per Op)
+//   row[(B, cb)] += sum_b W_q[b][B] t[(b, cb)]           (weights known at compile time)
+// and the packed entries (R, col >= R) are stored, lane-contiguous.  Accumulation
+// in FP64, stored as T.  Four waves per block; blocks of one group of coarse
+// elements are dealt to one XCD (its L2 holds the group's fine element data).
+
+// 1D hat value of the coarse corner at offset L (0, 1) at fine position p (0, 1, 2).
+__host__ __device__ constexpr double hat2(int p, int L) { return p == 2 * L ? 1.0 : (p == 1 ? 0.5 : 0.0); }
+template <int DIM>
+__host__ __device__ constexpr double sub_weight(int q, int a, int B) {
+  return hat2((q & 1) + loc_x(a), loc_x(B)) * hat2(((q >> 1) & 1) + loc_y(a), loc_y(B)) *
+         (DIM == 3 ? hat2(((q >> 2) & 1) + loc_z(a), loc_z(B)) : 1.0);
+}
+
+// Weight of coarse corner A at local node a of sub-element q (wave-uniform).
+template <int DIM>
+__device__ inline double row_weight(int q, int a, int A) {
+  return hat2((q & 1) + loc_x(a), loc_x(A)) * hat2(((q >> 1) & 1) + loc_y(a), loc_y(A)) *
+         (DIM == 3 ? hat2(((q >> 2) & 1) + loc_z(a), loc_z(A)) : 1.0);
+}
+
+// t[col] = sum_a W_q[a][A] A_e[(a, comp), col], from the element matrix entries
+// (one fine row at a time, its 24 or 8 loads in flight together).
+template <int DIM, class Op>
+__device__ inline void galerkin_rows(const Op& op, int64_t e, int q, int A, int comp, double* t) {
   constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
-  const int64_t tid = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (tid >= c.m * ND) return;
-  const int R = (int)(tid % ND);
-  const int64_t C = tid / ND;
+#pragma unroll
+  for (int col = 0; col < ND; ++col) t[col] = 0.0;
+#pragma unroll 1
+  for (int a = 0; a < NN; ++a) {
+    const double wa = row_weight<DIM>(q, a, A);
+    if (wa == 0.0) continue;
+    double v[ND];
+#pragma unroll
+    for (int col = 0; col < ND; ++col) v[col] = op.entry(e, a * DIM + comp, col);
+#pragma unroll
+    for (int col = 0; col < ND; ++col) t[col] = fma(wa, v[col], t[col]);
+  }
+}
+// A_e = x_e K0: t = x_e (sum_a W_q[a][A] K0[(a, comp), :]).
+template <int DIM>
+__device__ inline void galerkin_rows(const OpFineK<DIM, double>& op, int64_t e, int q, int A, int comp,
+                                     double* t) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  const double xe = op.x[e];
+  double w[NN];
+#pragma unroll
+  for (int a = 0; a < NN; ++a) w[a] = row_weight<DIM>(q, a, A);
+#pragma unroll
+  for (int col = 0; col < ND; ++col) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < NN; ++a) s = fma(w[a], k0<double>((a * DIM + comp) * ND + col), s);
+    t[col] = xe * s;
+  }
+}
+// A_e = x_e K0 + h_e h_e': t = x_e (sum_a W_q[a][A] K0[(a, comp), :]) + (sum_a W_q[a][A] h_(a, comp)) h_e.
+template <int DIM>
+__device__ inline void galerkin_rows(const OpFineZ<DIM, double>& op, int64_t e, int q, int A, int comp,
+                                     double* t) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  const double xe = op.x[e];
+  double w[NN], hv[ND];
+#pragma unroll
+  for (int col = 0; col < ND; ++col) hv[col] = op.h[col * op.m + e];
+  double hw = 0.0;
+#pragma unroll
+  for (int a = 0; a < NN; ++a) {
+    w[a] = row_weight<DIM>(q, a, A);
+    hw = fma(w[a], op.h[(a * DIM + comp) * op.m + e], hw);
+  }
+#pragma unroll
+  for (int col = 0; col < ND; ++col) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < NN; ++a) s = fma(w[a], k0<double>((a * DIM + comp) * ND + col), s);
+    t[col] = fma(xe, s, hw * hv[col]);
+  }
+}
+
+// row[(B, cb)] += sum_b W_Q[b][B] t[(b, cb)], the weights constant after unrolling.
+template <int DIM, int Q>
+__device__ inline void galerkin_scatter(const double* t, double* row) {
+  constexpr int NN = Geo<DIM>::NN;
+#pragma unroll
+  for (int bb = 0; bb < NN; ++bb)
+#pragma unroll
+    for (int B = 0; B < NN; ++B) {
+      const double wb = sub_weight<DIM>(Q, bb, B);
+      if (wb == 0.0) continue;
+#pragma unroll
+      for (int cb = 0; cb < DIM; ++cb) row[B * DIM + cb] = fma(wb, t[bb * DIM + cb], row[B * DIM + cb]);
+    }
+}
+template <int DIM>
+__device__ inline void galerkin_scatter_q(int q, const double* t, double* row) {
+  switch (q) {
+    case 0: galerkin_scatter<DIM, 0>(t, row); break;
+    case 1: galerkin_scatter<DIM, 1>(t, row); break;
+    case 2: galerkin_scatter<DIM, 2>(t, row); break;
+    case 3: galerkin_scatter<DIM, 3>(t, row); break;
+    default:
+      if constexpr (DIM == 3) {
+        switch (q) {
+          case 4: galerkin_scatter<DIM, 4>(t, row); break;
+          case 5: galerkin_scatter<DIM, 5>(t, row); break;
+          case 6: galerkin_scatter<DIM, 6>(t, row); break;
+          default: galerkin_scatter<DIM, 7>(t, row); break;
+        }
+      }
+  }
+}
+
+constexpr int GAL_WAVES = 4;
+template <int DIM, typename T, class Op>
+__global__ __launch_bounds__(64 * GAL_WAVES) void k_galerkin(Op op, Dims f, Dims c, T* __restrict__ Ec) {
+  constexpr int NN = Geo<DIM>::NN, ND = Geo<DIM>::ND;
+  constexpr int RB = ND / GAL_WAVES;                // blocks per group of 64 coarse elements
+  static_assert(ND % GAL_WAVES == 0, "rows split evenly over the waves");
+  const unsigned b = xcd_tile().x;
+  // the row is the same on every lane of the wave: kept in scalar registers
+  const int R = __builtin_amdgcn_readfirstlane((int)(b % RB) * GAL_WAVES + (int)(threadIdx.x >> 6));
+  const int64_t C = (int64_t)(b / RB) * 64 + (threadIdx.x & 63);
+  if (C >= c.m) return;
   const int CI = (int)(C % c.nx), CJ = (int)((C / c.nx) % c.ny), CK = DIM == 3 ? (int)(C / ((int64_t)c.nx * c.ny)) : 0;
   const int A = R / DIM, comp = R % DIM;
   double row[ND];
 #pragma unroll
   for (int col = 0; col < ND; ++col) row[col] = 0.0;
-  for (int qe = 0; qe < NN; ++qe) {                 // fine sub-element offset in C
-    const int qx = qe & 1, qy = (qe >> 1) & 1, qz = (qe >> 2) & 1;
+#pragma unroll 1
+  for (int q = 0; q < NN; ++q) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = (q >> 2) & 1;
     const int64_t e = ((int64_t)(2 * CK + qz) * f.ny + (2 * CJ + qy)) * f.nx + (2 * CI + qx);
-    // weight of coarse corner B at fine local node a: product of 1D hat values
-    double W[NN][NN];
-#pragma unroll
-    for (int a = 0; a < NN; ++a)
-#pragma unroll
-      for (int B = 0; B < NN; ++B) {
-        const int px = qx + loc_x(a), py = qy + loc_y(a), pz = qz + loc_z(a);   // 0..2
-        const double wx = 1.0 - fabs(0.5 * px - loc_x(B));
-        const double wy = 1.0 - fabs(0.5 * py - loc_y(B));
-        const double wz = DIM == 3 ? 1.0 - fabs(0.5 * pz - loc_z(B)) : 1.0;
-        W[a][B] = wx * wy * wz;
-      }
-    for (int a = 0; a < NN; ++a) {
-      const double wa = W[a][A];
-      if (wa == 0.0) continue;
-      for (int b = 0; b < NN; ++b) {
-        for (int cb = 0; cb < DIM; ++cb) {
-          const double t = wa * op.entry(e, a * DIM + comp, b * DIM + cb);
-#pragma unroll
-          for (int B = 0; B < NN; ++B) row[B * DIM + cb] += t * W[b][B];
-        }
-      }
-    }
+    double t[ND];
+    galerkin_rows<DIM>(op, e, q, A, comp, t);
+    galerkin_scatter_q<DIM>(q, t, row);
   }
-  for (int col = R; col < ND; ++col) Ec[(int64_t)sym_index(R, col, ND) * c.m + C] = T(row[col]);
+#pragma unroll
+  for (int col = 0; col < ND; ++col)
+    if (col >= R) Ec[(int64_t)sym_index(R, col, ND) * c.m + C] = T(row[col]);
 }
 
 // G_q = W_q' K0 W_q for the four sub-elements q of a coarse 2D element (one

@@ -1265,7 +1265,8 @@ struct OpsImpl : Ops {
   template <class Op>
   void launch_galerkin(Ctx& c, const Op& op, const Dims& f, const Dims& cd, double* Ec) {
     constexpr int ND = Geo<DIM>::ND;
-    k_galerkin<DIM, double, Op><<<lin_grid(cd.m * ND), BS, 0, c.stream>>>(op, f, cd, Ec);
+    const unsigned groups = (unsigned)((cd.m + 63) / 64);
+    k_galerkin<DIM, double, Op><<<groups * (ND / GAL_WAVES), 64 * GAL_WAVES, 0, c.stream>>>(op, f, cd, Ec);
   }
   // E64 of level lev_f-1 from level lev_f, accumulated and stored in FP64.
   void galerkin(Ctx& c, int lev_f, int op) override {
