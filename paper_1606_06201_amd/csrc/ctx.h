@@ -116,6 +116,7 @@ struct Ctx {
   int64_t staged_max_nodes = (int64_t)1 << 16;  // below this size)
   int cus = 256;               // compute units of the device
   bool mfma = true;            // first coarse level's fused passes on the matrix cores (FP32)
+  bool lane_share = true;      // finest-level 2D passes of K on lane-shared tiles (neighbour columns by DPP)
   bool fold_solution = true;         // PCG solution update folded into the next direction kernel
   bool fold_rn2_fin = true;          // PCG ||r||^2 finalize done by the V-cycle's first pass
   bool fold_restrict = true;         // finest residual restricted inside the first coarse down pass

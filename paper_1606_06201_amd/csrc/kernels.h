@@ -1110,6 +1110,44 @@ __global__ __launch_bounds__(BS) void k_level_fin(const T* __restrict__ v, const
   if (hflags) flags_to_host(red, hflags);
 }
 
+// Lane-shared register tiles.  The 64 lanes of a wave hold 64 consecutive node
+// columns; lane l forms its own column's values once and reads column i-1 from lane
+// l-1 and column i+1 from lane l+1 (wave-wide DPP shifts, no memory traffic).  The
+// first and last lanes of a tile have no neighbour on one side: they keep their own
+// value there and serve only as halo columns for lanes 1 and 62 (62 output columns
+// per tile).  Every lane of the wave must be active at a shift.
+__device__ inline float lane_from_left(float v) {     // value of lane l-1 (wave_shr:1)
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x138, 0xf, 0xf, false));
+}
+__device__ inline float lane_from_right(float v) {    // value of lane l+1 (wave_shl:1)
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));
+}
+__device__ inline double lane_from_left(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(b.x, b.x, 0x138, 0xf, 0xf, false),
+                                              __builtin_amdgcn_update_dpp(b.y, b.y, 0x138, 0xf, 0xf, false)));
+}
+__device__ inline double lane_from_right(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(b.x, b.x, 0x130, 0xf, 0xf, false),
+                                              __builtin_amdgcn_update_dpp(b.y, b.y, 0x130, 0xf, 0xf, false)));
+}
+constexpr int LS_COLS = 62;    // output columns of a lane-shared tile
+
+// Columns i-1 and i+1 of the neighbourhood from the neighbouring lanes.
+template <typename T, int NJ>
+__device__ inline void share_columns(T (&w)[NJ + 2][3][2]) {
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      w[rr][0][c] = lane_from_left(w[rr][1][c]);
+      w[rr][2][c] = lane_from_right(w[rr][1][c]);
+    }
+}
+
 // Row sums (A v) and diagonals of the NJ nodes (i, j0..j0+NJ-1) of one thread of
 // the tiled 2D pass.  w holds v on the nodes (i-1..i+1, j0-1..j0+NJ), zero outside
 // the grid and on clamped nodes: w[rr][cc] is node (i-1+cc, j0-1+rr).  The thread's
@@ -1164,6 +1202,22 @@ struct TileApply<T, OpFineK<2, T>, ROWS, NJ> {
         const int64_t e = (int64_t)ej * d.nx + ei;
         xe[er][ec] = op.x[(!EDGE || elem_in(d, ei, ej)) ? e : op.m];
       }
+  }
+  // Lane-shared tiles: the thread loads element column i-1 only and takes column i
+  // from the lane to its right (on the tile's last lane, a halo lane whose result is
+  // not used, that value is its own).
+  template <bool EDGE>
+  __device__ static inline void run_ls(const OpFineK<2, T>& op, const Dims& d, int i, int j0,
+                                       const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+    T xe[NJ + 1][2];
+#pragma unroll
+    for (int er = 0; er <= NJ; ++er) {
+      const int ei = i - 1, ej = j0 - 1 + er;
+      xe[er][0] = op.x[(!EDGE || elem_in(d, ei, ej)) ? (int64_t)ej * d.nx + ei : op.m];
+    }
+#pragma unroll
+    for (int er = 0; er <= NJ; ++er) xe[er][1] = lane_from_right(xe[er][0]);
+    run_x(xe, w, acc, dg);
   }
   __device__ static inline void run_x(const T (&xe)[NJ + 1][2], const T (&w)[NJ + 2][3][2], T (&acc)[NJ][2],
                                       T (&dg)[NJ][2]) {
@@ -1379,6 +1433,122 @@ __device__ inline void jacobi2_tile(const OpFineK<2, T>& op, const Dims& d, int 
   TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe, w, acc, dg);
 }
 
+// Lane-shared forms of load_tile, load_tile_prolong and jacobi2_tile: the thread
+// forms column i of the neighbourhood (the same values, in the same order, as the
+// per-thread forms) and takes columns i-1 and i+1 from its neighbouring lanes.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void load_col(const T* __restrict__ v, const Dims& d, int i, int j0, T (&w)[NJ + 2][3][2]) {
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr) {
+    const int jj = j0 - 1 + rr;
+    if (!EDGE) {
+      const unsigned o = 2u * ((unsigned)jj * (unsigned)d.nx1 + (unsigned)i);
+      w[rr][1][0] = v[o];
+      w[rr][1][1] = v[o + 1];
+    } else {
+      const bool ok = i >= 1 && i < d.nx1 && jj >= 0 && jj < d.ny1;
+      const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 +
+                               (unsigned)min(max(i, 0), d.nx1 - 1));
+      const T a = v[o], b = v[o + 1];
+      w[rr][1][0] = ok ? a : T(0);
+      w[rr][1][1] = ok ? b : T(0);
+    }
+  }
+  share_columns<T, NJ>(w);
+}
+
+template <typename T, int NJ, bool EDGE>
+__device__ inline void load_col_prolong(const T* __restrict__ z2, const T* __restrict__ zc, const Dims& d,
+                                        const Dims& dc, int i, int j0, T (&w)[NJ + 2][3][2]) {
+  static_assert(NJ % 2 == 0, "the folded prolongation needs an even node count per thread");
+  constexpr int CR = NJ / 2 + 2;
+  const int jb = (j0 >> 1) - 1;
+  const bool odd = (i & 1) != 0;                 // odd column: two coarse columns, weight 1/2
+  const int I0 = min(max(i >> 1, 0), dc.nx1 - 1), I1 = min(max((i + 1) >> 1, 0), dc.nx1 - 1);
+  T cv[CR][2][2];
+#pragma unroll
+  for (int cr = 0; cr < CR; ++cr) {
+    const int J = min(max(jb + cr, 0), dc.ny1 - 1);
+    load_node<2, T>(zc, (int64_t)J * dc.nx1 + I0, cv[cr][0]);
+    load_node<2, T>(zc, (int64_t)J * dc.nx1 + I1, cv[cr][1]);
+  }
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr) {
+    const int jj = j0 - 1 + rr;
+    const int nj = (rr & 1) == 0 ? 2 : 1;
+    const int J0 = (rr + 1) >> 1;
+    const bool ok = !EDGE || (i >= 1 && i < d.nx1 && jj >= 0 && jj < d.ny1);
+    const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 + (unsigned)(ok ? i : 0));
+    T acc[2] = {z2[o], z2[o + 1]};
+    const int ni = odd ? 2 : 1;
+    const T wgt = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool use = e < ni && b < nj;
+        const int Jr = J0 + (b < nj ? b : 0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[c] += use ? wgt * cv[Jr][e][c] : T(0);
+      }
+    w[rr][1][0] = ok ? acc[0] : T(0);
+    w[rr][1][1] = ok ? acc[1] : T(0);
+  }
+  share_columns<T, NJ>(w);
+}
+
+// EDGE false: the caller has checked that the elements (i-1..i, j0-2..j0+NJ) of every
+// lane lie inside the grid.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void jacobi2_col(const OpFineK<2, T>& op, const Dims& d, int i, int j0, const T* __restrict__ r,
+                                   T omega, T (&w)[NJ + 2][3][2], T (&acc)[NJ][2], T (&dg)[NJ][2]) {
+  // elements (i-1+ec, j0-2+er), the zero pad outside the grid
+  T xb[NJ + 3][2];
+#pragma unroll
+  for (int er = 0; er < NJ + 3; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) {
+      const int ei = i - 1 + ec, ej = j0 - 2 + er;
+      xb[er][ec] = op.x[(!EDGE || elem_in(d, ei, ej)) ? (int64_t)ej * d.nx + ei : op.m];
+    }
+#pragma unroll
+  for (int rr = 0; rr < NJ + 2; ++rr) {
+    const int jj = j0 - 1 + rr;
+    const bool ok = !EDGE || (i >= 1 && i < d.nx1 && jj >= 0 && jj < d.ny1);
+    T rv[2];
+    if (!EDGE) {
+      const unsigned o = 2u * ((unsigned)jj * (unsigned)d.nx1 + (unsigned)i);
+      rv[0] = r[o];
+      rv[1] = r[o + 1];
+    } else {
+      const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 +
+                               (unsigned)min(max(i, 0), d.nx1 - 1));
+      const T a = r[o], b = r[o + 1];
+      rv[0] = ok ? a : T(0);
+      rv[1] = ok ? b : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T dd = T(0);
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+          const int a = loc_index(1 - ex, 1 - ey, 0);
+          dd += xb[rr + ey][ex] * k0sq<T>(2 * a + c, 2 * a + c);
+        }
+      w[rr][1][c] = ok ? omega * rv[c] * recip(dd) : T(0);
+    }
+  }
+  share_columns<T, NJ>(w);
+  T xe[NJ + 1][2];
+#pragma unroll
+  for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) xe[er][ec] = xb[er + 1][ec];
+  TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe, w, acc, dg);
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
 // along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
 // whose nodes are all at least one node away from every boundary (and off the
@@ -1391,7 +1561,9 @@ __device__ inline void jacobi2_tile(const OpFineK<2, T>& op, const Dims& d, int 
 // zero iterate in one pass; the first sweep's z1 = omega D^-1 r is formed on the
 // thread's neighbourhood from r and the densities of the (NJ+3) x 4 elements around
 // it (same arithmetic and order as the M_JACOBI0 pass), so z1 is never stored.
-template <typename T, class Op, int MODE, int NJ>
+// LS (finest level of K): lane-shared tiles of LS_COLS output columns, lanes 0 and
+// 63 the halo columns (see lane_from_left); the same values in the same order.
+template <typename T, class Op, int MODE, int NJ, bool LS = false>
 __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restrict__ v,
                                                 const T* __restrict__ r, T* __restrict__ out,
                                                 const double* __restrict__ omg, Aug<T> aug, Red red,
@@ -1400,14 +1572,20 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
                                                 int fin_zpend) {
   if (gate && *gate) return;
   const T omega = omg ? T(*omg) : T(0);
+  static_assert(!LS || std::is_same<Op, OpFineK<2, T>>::value, "lane-shared tiles: finest level of K");
   const Tile tl = xcd_tile();
   constexpr int RJ = (BS / 64) * NJ;               // node rows per tile
-  const int ti0 = tl.x * 64, tj0 = tl.y * RJ;
-  const int i = ti0 + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int ti0 = LS ? (int)tl.x * LS_COLS - 1 : (int)tl.x * 64, tj0 = tl.y * RJ;
+  const int i = ti0 + lane;
   const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
   const T vl = (aug.b && MODE != M_JACOBI0) ? v[aug.n] : T(0);
   double bdot = 0.0, red0 = 0.0, red1 = 0.0;
-  const bool interior = ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1;
+  // interior: every load of the tile is inside the grid and off the clamped column
+  // (lane-shared M_JACOBI2: also the ring of elements around the neighbourhood)
+  const bool interior = LS ? (MODE == M_JACOBI2 ? (ti0 >= 1 && ti0 + 65 <= d.nx1 && tj0 >= 2 && tj0 + RJ + 2 <= d.ny1)
+                                                : (ti0 >= 1 && ti0 + 64 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1))
+                           : (ti0 >= 2 && ti0 + 65 <= d.nx1 && tj0 >= 1 && tj0 + RJ + 1 <= d.ny1);
   constexpr bool ROWS = MODE != M_JACOBI0;
   // The thread's entries of r, of the FP64 dot vector and of the border are loaded
   // first, without branches (index clamped into the grid), so they are in flight
@@ -1416,7 +1594,7 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   double dpre[NJ][2];
 #pragma unroll
   for (int n = 0; n < NJ; ++n) {
-    const int j = min(j0 + n, d.ny1 - 1), ic = min(i, d.nx1 - 1);
+    const int j = min(j0 + n, d.ny1 - 1), ic = min(max(i, 0), d.nx1 - 1);
     const int64_t q = (int64_t)j * d.nx1 + ic;
     if constexpr (mode_reads_r<MODE>()) load_node<2, T>(r, q, rpre[n]);
     if constexpr (MODE == M_JACOBI_BETA) {
@@ -1430,8 +1608,23 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
   T acc[NJ][2], dg[NJ][2];
   if constexpr (MODE == M_JACOBI2) {
     static_assert(std::is_same<Op, OpFineK<2, T>>::value, "two fused sweeps from zero: finest level only");
-    if (interior) jacobi2_tile<T, NJ, false>(op, d, i, j0, r, omega, w, acc, dg);
-    else jacobi2_tile<T, NJ, true>(op, d, i, j0, r, omega, w, acc, dg);
+    if constexpr (LS) {
+      if (interior) jacobi2_col<T, NJ, false>(op, d, i, j0, r, omega, w, acc, dg);
+      else jacobi2_col<T, NJ, true>(op, d, i, j0, r, omega, w, acc, dg);
+    } else {
+      if (interior) jacobi2_tile<T, NJ, false>(op, d, i, j0, r, omega, w, acc, dg);
+      else jacobi2_tile<T, NJ, true>(op, d, i, j0, r, omega, w, acc, dg);
+    }
+  } else if constexpr (LS) {
+    if (interior) {
+      if constexpr (MODE == M_PJACOBI) load_col_prolong<T, NJ, false>(v, zc, d, dc, i, j0, w);
+      else if constexpr (ROWS) load_col<T, NJ, false>(v, d, i, j0, w);
+      TileApply<T, Op, ROWS, NJ>::template run_ls<false>(op, d, i, j0, w, acc, dg);
+    } else {
+      if constexpr (MODE == M_PJACOBI) load_col_prolong<T, NJ, true>(v, zc, d, dc, i, j0, w);
+      else if constexpr (ROWS) load_col<T, NJ, true>(v, d, i, j0, w);
+      TileApply<T, Op, ROWS, NJ>::template run_ls<true>(op, d, i, j0, w, acc, dg);
+    }
   } else if (interior) {
     if constexpr (MODE == M_PJACOBI) load_tile_prolong<T, NJ, false>(v, zc, d, dc, i, j0, w);
     else if constexpr (ROWS) load_tile<T, NJ, false>(v, d, i, j0, w);
@@ -1444,6 +1637,7 @@ __global__ __launch_bounds__(BS) void k_level2d(Op op, Dims d, const T* __restri
 #pragma unroll
   for (int n = 0; n < NJ; ++n) {
     const int j = j0 + n;
+    if (LS && (lane == 0 || lane > LS_COLS)) continue;     // halo lanes
     if (!interior && (i >= d.nx1 || j >= d.ny1)) continue;
     const int64_t q = (int64_t)j * d.nx1 + i;
     if (!interior && i == 0) {

@@ -732,21 +732,37 @@ struct OpsImpl : Ops {
     }
   }
 
-  // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes.
+  // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes; on the finest level
+  // of K lane-shared tiles of LS_COLS x 4*NJ output nodes (c.lane_share), except for
+  // the last post-sweep: it is bound by its memory traffic, and tiles that start on
+  // 64-node boundaries read fewer cache lines.
   template <typename T, class Op, int NJ>
   void launch_l2d(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out, const double* omg,
                   Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64, bool fin,
                   const T* zc = nullptr, const Dims* dcp = nullptr) {
+    if constexpr (std::is_same<Op, OpFineK<2, T>>::value) {
+      if (c.lane_share && mode != M_JACOBI_BETA) {
+        launch_l2d_t<T, Op, NJ, true>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin, zc, dcp);
+        return;
+      }
+    }
+    launch_l2d_t<T, Op, NJ, false>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin, zc, dcp);
+  }
+  template <typename T, class Op, int NJ, bool LS>
+  void launch_l2d_t(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out,
+                    const double* omg, Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64,
+                    bool fin, const T* zc, const Dims* dcp) {
     const Dims dc = dcp ? *dcp : d;
-    const dim3 g2((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
+    const int cols = LS ? LS_COLS : 64;
+    const dim3 g2((unsigned)((d.nx1 + cols - 1) / cols), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
     const unsigned nb2 = g2.x * g2.y;
     IPMG_REQUIRE((int64_t)nb2 <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
 #define IPMG_L2D_CASE(M)                                                                                     \
   case M:                                                                                                    \
     {                                                                                                        \
       ProfScope ps_(c, c.prof_tag);                                                                          \
-      k_level2d<T, Op, M, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc, dc, \
-                                                       0u, 0);                                               \
+      k_level2d<T, Op, M, NJ, LS><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc, \
+                                                           dc, 0u, 0);                                       \
     }                                                                                                        \
     if (fin)                                                                                                 \
       k_level_fin<T, M><<<1, BS, 0, c.stream>>>(v, r, out, omg, aug.b != nullptr, aug.c, aug.n, dot64, c.red, nb2, \
@@ -765,16 +781,17 @@ struct OpsImpl : Ops {
     if constexpr (std::is_same<Op, OpFineK<2, T>>::value) {
       if (mode == M_JACOBI2) {
         ProfScope ps_(c, c.prof_tag);
-        k_level2d<T, Op, M_JACOBI2, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
-                                                                 dc, c.rn2_fin_blocks, c.rn2_fin_zpend ? 1 : 0);
+        k_level2d<T, Op, M_JACOBI2, NJ, LS><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate,
+                                                                     zc, dc, c.rn2_fin_blocks,
+                                                                     c.rn2_fin_zpend ? 1 : 0);
         c.rn2_fin_blocks = 0;
       }
     }
     if constexpr (NJ % 2 == 0) {
       if (mode == M_PJACOBI) {
         ProfScope ps_(c, c.prof_tag);
-        k_level2d<T, Op, M_PJACOBI, NJ><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate, zc,
-                                                                 dc, 0u, 0);
+        k_level2d<T, Op, M_PJACOBI, NJ, LS><<<g2, BS, 0, c.stream>>>(op, d, v, r, out, omg, aug, c.red, dot64, gate,
+                                                                     zc, dc, 0u, 0);
       }
     }
   }

@@ -157,6 +157,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_ELEM_APPLY3_MIN")) c.elem_apply3_min = std::max<int64_t>(0, std::atoll(e));
   if (const char* e = std::getenv("IPMG_NO_ELEM_FINE3")) c.elem_fine3 = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_MFMA")) c.mfma = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_LANE_SHARE")) c.lane_share = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);

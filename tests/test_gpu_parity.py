@@ -280,7 +280,48 @@ def test_first_coarse_level_matrix_cores_match_vector_units(nel, levels, monkeyp
     assert relerr(z["0"], z["1"]) < 1e-6
 
 
-@pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"),
+@pytest.mark.parametrize("nel,levels", [((256, 128), 4), ((248, 124), 3), ((124, 60), 3), ((60, 30), 2), ((8, 4), 2)])
+@pytest.mark.parametrize("fp32", [True, False])
+def test_finest_level_lane_shared_tiles_match_per_thread_tiles(nel, levels, fp32, monkeypatch):
+    # The finest level's register-blocked passes on lane-shared tiles (each lane
+    # forms one column of the neighbourhood and takes the other two from its
+    # neighbouring lanes; 62 output columns per tile) against the per-thread tiles.
+    # Column counts 257, 249, 125, 61 and 9 leave 9, 1, 1, 61 and 9 columns in the
+    # last tile.  Tiles are forced on every level size.
+    #  - Prolongation as a pass of its own: every finest-level pass forms the same
+    #    values in the same order, so the V-cycles agree bit for bit.
+    #  - FP64, prolongation folded into the first post-sweep: the lane-shared pass
+    #    sums z2 + P zc as the prolongation pass does, bit for bit.  (The per-thread
+    #    folded pass differs from it by rounding.)
+    #  - Default paths: equal to rounding, the same PCG iteration count.
+    monkeypatch.setenv("IPMG_TILED_MIN_NODES", "0")
+    g, K0, x = _kproblem(nel, seed=12)
+    r = np.random.default_rng(13).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    f = fem.load_vector(g, tip_load(nel))
+    z, its = {}, {}
+    for ls in ("0", "1"):
+        for fold in ("0", "1"):
+            monkeypatch.setenv("IPMG_NO_LANE_SHARE", ls)
+            monkeypatch.setenv("IPMG_NO_FOLD_PROLONG", fold)
+            s = _solver(nel, levels, fp32=fp32)
+            s.set_density(T(x))
+            s.mg_setup()
+            z[ls, fold] = N(s.vcycle(T(r)))
+            _, info = s.pcg(T(f), rtol=1e-8)
+            assert info["true_relres"] <= 1e-8
+            its[ls, fold] = info["iters"]
+    for k in ("IPMG_NO_LANE_SHARE", "IPMG_NO_FOLD_PROLONG", "IPMG_TILED_MIN_NODES"):
+        monkeypatch.delenv(k)
+    assert np.array_equal(z["0", "1"], z["1", "1"])
+    assert its["0", "1"] == its["1", "1"]
+    if not fp32:
+        assert np.array_equal(z["0", "0"], z["1", "1"])
+    assert relerr(z["0", "0"], z["1", "0"]) < (1e-6 if fp32 else 1e-14)
+    assert abs(its["0", "0"] - its["1", "0"]) <= 1
+
+
+@pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"), ("IPMG_NO_LANE_SHARE", "1"),
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
                                      ("IPMG_UNSTAGED", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
                                      ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1"),
