@@ -732,16 +732,18 @@ struct OpsImpl : Ops {
     }
   }
 
-  // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes; on the finest level
-  // of K lane-shared tiles of LS_COLS x 4*NJ output nodes (c.lane_share), except for
-  // the last post-sweep: it is bound by its memory traffic, and tiles that start on
-  // 64-node boundaries read fewer cache lines.
+  // 2D level pass on register-blocked tiles of 64 x 4*NJ nodes.  On the finest level
+  // of K, the two passes that form their neighbourhood from other vectors (the two
+  // sweeps from zero, the folded prolongation) run on lane-shared tiles of LS_COLS x
+  // 4*NJ output nodes (c.lane_share); the passes that only load it are bound by
+  // their traffic and read fewer cache lines on tiles that start on 64-node
+  // boundaries.
   template <typename T, class Op, int NJ>
   void launch_l2d(Ctx& c, const Dims& d, const Op& op, int mode, const T* v, const T* r, T* out, const double* omg,
                   Aug<T> aug, int sidx, int sidx_in, const int* gate, const double* dot64, bool fin,
                   const T* zc = nullptr, const Dims* dcp = nullptr) {
     if constexpr (std::is_same<Op, OpFineK<2, T>>::value) {
-      if (c.lane_share && mode != M_JACOBI_BETA) {
+      if (c.lane_share && (mode == M_JACOBI2 || mode == M_PJACOBI)) {
         launch_l2d_t<T, Op, NJ, true>(c, d, op, mode, v, r, out, omg, aug, sidx, sidx_in, gate, dot64, fin, zc, dcp);
         return;
       }
