@@ -124,7 +124,7 @@ def cpu_baseline(nel, levels, x, f, iters=40):
     import numpy as np
     from oracle import fem, mg, pcg
     g = fem.Grid(nel)
-    K0 = fem.element_stiffness(2)
+    K0 = fem.element_stiffness(len(nel))
     t0 = time.perf_counter()
     A = fem.stiffness_free(g, x, K0)
     H = mg.Hierarchy(g, A, levels)
@@ -138,7 +138,7 @@ def cpu_baseline(nel, levels, x, f, iters=40):
         "unit": "DOF-iters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{res.iters} FP64 MG-PCG iterations of the same {nel[0]}x{nel[1]} solve after the "
+        "sample": (f"{res.iters} FP64 MG-PCG iterations of the same {'x'.join(map(str, nel))} solve after the "
                    f"oracle's assembly + Galerkin setup ({t1 - t0:.1f} s, excluded); scipy sparse "
                    f"kernels run on one host core"),
         "setup_s": t1 - t0,
@@ -173,12 +173,13 @@ def golden_errors(workload, u_mixed, fp64_u=None):
     return out
 
 
-def bench_3d_section(dev, steps=8):
+def bench_3d_section(dev, steps=8, cpu=True):
     """3D trilinear cantilever 128x64x64 (1.6M DOFs), FP32 V-cycle: the interior-point
     start (K solve) and `steps` Newton steps (augmented system Z), with the dominant
     3D kernels timed by HIP events and priced against the FP64 / FP32 ALU peaks
     (the 3D element products are arithmetic-bound: 1152 flops per element for
-    x_e K0 v_e against at most 200 bytes of traffic)."""
+    x_e K0 v_e against at most 200 bytes of traffic), and (cpu) the oracle's FP64
+    MG-PCG on the interior-point start system of the same grid as its baseline."""
     import numpy as np
     import torch
     from paper_1606_06201_amd import Solver, inputs
@@ -236,7 +237,11 @@ def bench_3d_section(dev, steps=8):
             "dof_iters_per_s": s.n_free * iters / (t1 - t0), "kernels": kern,
             "roofline": ({"bound": "alu", "kernel": dom, "achieved": kern[dom]["TFLOP_per_s"],
                           "peak": kern[dom]["peak_TFLOP_per_s"], "unit": "TFLOP/s", "frac": kern[dom]["frac"]}
-                         if dom else None)}
+                         if dom else None),
+            # the oracle's FP64 MG-PCG on the interior-point start system K(x0) u = f
+            # (x0 = V/m everywhere), 5 iterations after its setup
+            "cpu_baseline": (cpu_baseline(nel, levels, np.full(m, 0.3), f.detach().cpu().numpy(), iters=5)
+                             if cpu else None)}
 
 
 # The paper's counts, quoted as context (Intel i5 CPU, MATLAB; its smoother is not
@@ -530,7 +535,7 @@ def main():
     ip3d = None
     if not args.no_3d and args.workload == "thr2048x1024":
         print("[bench] 3D interior-point section", file=sys.stderr, flush=True)
-        ip3d = bench_3d_section(dev)
+        ip3d = bench_3d_section(dev, cpu=not args.no_cpu_baseline)
 
     inf = inf_mixed[-1]
     out = {
