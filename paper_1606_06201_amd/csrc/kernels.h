@@ -1549,6 +1549,142 @@ __device__ inline void jacobi2_col(const OpFineK<2, T>& op, const Dims& d, int i
   TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe, w, acc, dg);
 }
 
+// The two pre-smoothing sweeps from zero and the residual of their result, in one
+// lane-shared pass (finest level of K): z1 = omega D^-1 r on the lane's column over
+// NJ+4 rows, z2 = z1 + omega D^-1 (r - A z1) over NJ+2 rows, t = r - A z2 on its NJ
+// rows, with columns i-1 and i+1 of z1 and of z2 read from the neighbouring lanes.
+// Every value is formed as in the separate passes (z2 as M_JACOBI2 stores it, zero on
+// nodes outside the grid and on clamped ones, as M_RESID reads it back), so z2 and
+// t equal theirs bit for bit.  Lanes 0, 1, 62 and 63 are halo columns (z2 on lanes
+// 0 and 63 lacks a neighbour); LS2_COLS output columns per tile.
+// EDGE false: every load of every lane lies inside the grid, off the clamped column.
+constexpr int LS2_COLS = 60;
+template <typename T, int NJ, bool EDGE>
+__device__ inline void jacobi2_resid_col(const OpFineK<2, T>& op, const Dims& d, int i, int j0,
+                                         const T* __restrict__ r, T omega, T (&z2o)[NJ][2], T (&acc)[NJ][2],
+                                         T (&ro)[NJ][2]) {
+  constexpr int R1 = NJ + 4, R2 = NJ + 2;
+  // elements (i-1+ec, j0-3+er), the zero pad outside the grid
+  T xb[NJ + 5][2];
+#pragma unroll
+  for (int er = 0; er < NJ + 5; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) {
+      const int ei = i - 1 + ec, ej = j0 - 3 + er;
+      xb[er][ec] = op.x[(!EDGE || elem_in(d, ei, ej)) ? (int64_t)ej * d.nx + ei : op.m];
+    }
+  // r on rows j0-2 .. j0+NJ+1 of the lane's column (zero outside the grid, clamped)
+  T rv[R1][2];
+  bool ok[R1];
+#pragma unroll
+  for (int rr = 0; rr < R1; ++rr) {
+    const int jj = j0 - 2 + rr;
+    ok[rr] = !EDGE || (i >= 1 && i < d.nx1 && jj >= 0 && jj < d.ny1);
+    const unsigned o = EDGE ? 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 +
+                                    (unsigned)min(max(i, 0), d.nx1 - 1))
+                            : 2u * ((unsigned)jj * (unsigned)d.nx1 + (unsigned)i);
+    const T a = r[o], b = r[o + 1];
+    rv[rr][0] = ok[rr] ? a : T(0);
+    rv[rr][1] = ok[rr] ? b : T(0);
+  }
+  // z1 on the R1 rows (diagonal summed as in jacobi2_tile)
+  T w1[R1][3][2];
+#pragma unroll
+  for (int rr = 0; rr < R1; ++rr)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T dd = T(0);
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+          const int a = loc_index(1 - ex, 1 - ey, 0);
+          dd += xb[rr + ey][ex] * k0sq<T>(2 * a + c, 2 * a + c);
+        }
+      w1[rr][1][c] = ok[rr] ? omega * rv[rr][c] * recip(dd) : T(0);
+    }
+  share_columns<T, NJ + 2>(w1);
+  // A z1 and D on rows j0-1 .. j0+NJ, then z2 there
+  T a1[R2][2], d1[R2][2];
+  {
+    T xe[R2 + 1][2];
+#pragma unroll
+    for (int er = 0; er <= R2; ++er)
+#pragma unroll
+      for (int ec = 0; ec < 2; ++ec) xe[er][ec] = xb[er + 1][ec];
+    TileApply<T, OpFineK<2, T>, true, R2>::run_x(xe, w1, a1, d1);
+  }
+  T w2[R2][3][2];
+#pragma unroll
+  for (int n = 0; n < R2; ++n)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T o = w1[n + 1][1][c] + omega * (rv[n + 1][c] - a1[n][c]) * recip(d1[n][c]);
+      w2[n][1][c] = ok[n + 1] ? o : T(0);
+    }
+  share_columns<T, NJ>(w2);
+  // A z2 on the lane's NJ rows
+  T xe2[NJ + 1][2], dg[NJ][2];
+#pragma unroll
+  for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) xe2[er][ec] = xb[er + 2][ec];
+  TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe2, w2, acc, dg);
+#pragma unroll
+  for (int n = 0; n < NJ; ++n)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      z2o[n][c] = w2[n + 1][1][c];
+      ro[n][c] = rv[n + 2][c];
+    }
+}
+
+// Pass of jacobi2_resid_col: z2 into z2out, t = r - A z2 into tout.  fin_blocks != 0:
+// the first block also finalizes the preceding residual update's ||r||^2 (as the
+// M_JACOBI2 pass does).
+template <typename T, int NJ>
+__global__ __launch_bounds__(BS) void k_jacobi2r2d(OpFineK<2, T> op, Dims d, const T* __restrict__ r,
+                                                   T* __restrict__ z2out, T* __restrict__ tout,
+                                                   const double* __restrict__ omg, Red red, const int* gate,
+                                                   unsigned fin_blocks, int fin_zpend) {
+  if (gate && *gate) return;
+  const T omega = T(*omg);
+  const Tile tl = xcd_tile();
+  constexpr int RJ = (BS / 64) * NJ;
+  const int lane = threadIdx.x & 63;
+  const int ti0 = (int)tl.x * LS2_COLS - 2, tj0 = tl.y * RJ;
+  const int i = ti0 + lane;
+  const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
+  const bool interior = ti0 >= 1 && ti0 + 65 <= d.nx1 && tj0 >= 3 && tj0 + RJ + 3 <= d.ny1;
+  T z2[NJ][2], acc[NJ][2], rr[NJ][2];
+  if (interior) jacobi2_resid_col<T, NJ, false>(op, d, i, j0, r, omega, z2, acc, rr);
+  else jacobi2_resid_col<T, NJ, true>(op, d, i, j0, r, omega, z2, acc, rr);
+  if (lane >= 2 && lane < 2 + LS2_COLS) {
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      const int j = j0 + n;
+      if (!interior && (i >= d.nx1 || j >= d.ny1)) continue;
+      const int64_t q = (int64_t)j * d.nx1 + i;
+      T t[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) t[c] = rr[n][c] - acc[n][c];
+      if (!interior && i == 0) {
+        const T z[2] = {T(0), T(0)};
+        store_node<2, T>(z2out, q, z);
+        store_node<2, T>(tout, q, z);
+        continue;
+      }
+      store_node<2, T>(z2out, q, z2[n]);
+      store_node<2, T>(tout, q, t);
+    }
+  }
+  if (fin_blocks && block_id() == 0) {
+    double tot[1];
+    sum_partials<1>(red, fin_blocks, tot);
+    if (threadIdx.x == 0) rn2_finish(tot[0], red, fin_zpend != 0);
+  }
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
 // along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
 // whose nodes are all at least one node away from every boundary (and off the

@@ -826,6 +826,36 @@ struct OpsImpl : Ops {
     else launch_l2d<T, OpFineK<2, T>, 4>(c, d, op, M_JACOBI2, nullptr, r, out, omg, aug, 0, -1, gate, nullptr, false);
     return true;
   }
+  template <typename T, int NJ>
+  void launch_jacobi2r(Ctx& c, const Dims& d, const T* r, T* out, T* t, const double* omg, const int* gate) {
+    constexpr int RJ = 4 * NJ;
+    const dim3 g((unsigned)((d.nx1 + LS2_COLS - 1) / LS2_COLS), (unsigned)((d.ny1 + RJ - 1) / RJ), 1);
+    const OpFineK<2, T> op{(const T*)c.xT, d.m};
+    ProfScope ps(c, c.prof_tag);
+    k_jacobi2r2d<T, NJ><<<g, BS, 0, c.stream>>>(op, d, r, out, t, omg, c.red, gate, c.rn2_fin_blocks,
+                                                c.rn2_fin_zpend ? 1 : 0);
+    c.rn2_fin_blocks = 0;
+  }
+  bool jacobi2_resid(Ctx& c, int lev, int op, const void* r, void* out, void* t, const double* omg,
+                     const int* gate) override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      if (op != IPMG_OP_K || !c.fold_prolong || !c.lane_share || !c.fuse_resid || lev != c.L - 1) return false;
+      const Dims& d = c.lev[lev].d;
+      if (!c.tiled2d || d.nnodes < c.tiled_min_nodes) return false;
+      const int nj = c.fp32 ? c.nj32 : c.nj64;
+      if (nj != 2 && nj != 4) return false;
+      if (c.fp32) {
+        if (nj == 4) launch_jacobi2r<float, 4>(c, d, (const float*)r, (float*)out, (float*)t, omg, gate);
+        else launch_jacobi2r<float, 2>(c, d, (const float*)r, (float*)out, (float*)t, omg, gate);
+      } else {
+        if (nj == 4) launch_jacobi2r<double, 4>(c, d, (const double*)r, (double*)out, (double*)t, omg, gate);
+        else launch_jacobi2r<double, 2>(c, d, (const double*)r, (double*)out, (double*)t, omg, gate);
+      }
+      return true;
+    }
+  }
   bool jacobi2(Ctx& c, int lev, int op, const void* r, void* out, const double* omg, const int* gate) override {
     if constexpr (DIM != 2) {
       return false;

@@ -158,6 +158,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_ELEM_FINE3")) c.elem_fine3 = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_MFMA")) c.mfma = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_LANE_SHARE")) c.lane_share = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_JACOBI2_RESID")) c.fuse_resid = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);
@@ -399,9 +400,14 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   const bool fine = k == c.L - 1;
   const int jac = fine ? PC_FINE_JACOBI : (k == c.L - 2 ? PC_SUB_JACOBI : -1);
   int pre = 0;
+  bool resid_done = false;
   if (c.desc.nu_pre >= 2) {                   // the first two sweeps in one pass (z1 not stored)
     ProfTag pt(c, fine ? PC_FINE_JACOBI2 : -1);
-    if (c.ops->jacobi2(c, k, op, l.r, nxt, w, gate)) {
+    if (c.desc.nu_pre == 2 && c.ops->jacobi2_resid(c, k, op, l.r, nxt, l.t, w, gate)) {
+      std::swap(cur, nxt);                    // ... and the residual of their result
+      pre = 2;
+      resid_done = true;
+    } else if (c.ops->jacobi2(c, k, op, l.r, nxt, w, gate)) {
       std::swap(cur, nxt);
       pre = 2;
     }
@@ -417,7 +423,7 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
     c.ops->level(c, k, op, M_JACOBI, cur, l.r, nxt, w, 0, -1, gate);
     std::swap(cur, nxt);
   }
-  {
+  if (!resid_done) {
     ProfTag pt(c, fine ? PC_FINE_RESID : -1);
     c.ops->level(c, k, op, M_RESID, cur, l.r, l.t, nullptr, 0, -1, gate);     // restricted residual
   }

@@ -321,7 +321,43 @@ def test_finest_level_lane_shared_tiles_match_per_thread_tiles(nel, levels, fp32
     assert abs(its["0", "0"] - its["1", "0"]) <= 1
 
 
+@pytest.mark.parametrize("nel,levels", [((256, 128), 4), ((248, 124), 3), ((124, 60), 3), ((60, 30), 2), ((8, 4), 2)])
+@pytest.mark.parametrize("fp32", [True, False])
+def test_finest_level_sweeps_and_residual_in_one_pass_match_separate_passes(nel, levels, fp32, monkeypatch):
+    # The two pre-smoothing sweeps from zero and the residual of their result in one
+    # lane-shared pass (60 output columns per tile; column counts 257, 249, 125, 61
+    # and 9 leave 17, 9, 5, 1 and 9 columns in the last tile) against the two
+    # separate passes: z2 and the residual are formed by the same formulas in the same
+    # order, so in FP64 the V-cycles agree bit for bit; in FP32 the compiler fuses a
+    # multiply and an add differently in the two kernels, so they agree to a few ulps.
+    # PCG takes the same iterations (FP64) or within one (FP32).
+    monkeypatch.setenv("IPMG_TILED_MIN_NODES", "0")
+    g, K0, x = _kproblem(nel, seed=14)
+    r = np.random.default_rng(15).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    f = fem.load_vector(g, tip_load(nel))
+    z, its = {}, {}
+    for v in ("0", "1"):
+        monkeypatch.setenv("IPMG_NO_JACOBI2_RESID", v)
+        s = _solver(nel, levels, fp32=fp32)
+        s.set_density(T(x))
+        s.mg_setup()
+        z[v] = N(s.vcycle(T(r)))
+        _, info = s.pcg(T(f), rtol=1e-8)
+        assert info["true_relres"] <= 1e-8
+        its[v] = info["iters"]
+    monkeypatch.delenv("IPMG_NO_JACOBI2_RESID")
+    monkeypatch.delenv("IPMG_TILED_MIN_NODES")
+    if fp32:
+        assert relerr(z["0"], z["1"]) < 1e-6
+        assert abs(its["0"] - its["1"]) <= 1
+    else:
+        assert np.array_equal(z["0"], z["1"])
+        assert its["0"] == its["1"]
+
+
 @pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"), ("IPMG_NO_LANE_SHARE", "1"),
+                                     ("IPMG_NO_JACOBI2_RESID", "1"),
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
                                      ("IPMG_UNSTAGED", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
                                      ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1"),
