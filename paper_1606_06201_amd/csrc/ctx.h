@@ -50,6 +50,11 @@ struct Ops {
   // As jacobi2, and t = r - A out in the same pass; false when that pass does not apply.
   virtual bool jacobi2_resid(Ctx& c, int lev, int op, const void* r, void* out, void* t, const double* omg,
                              const int* gate) = 0;
+  // out = z2 + P zc followed by two damped-Jacobi sweeps, in one pass (dot64: the
+  // last sweep also accumulates the PCG ratio's partial sums, as M_JACOBI_BETA, and
+  // its finalize follows); false when that pass does not apply.
+  virtual bool prolong_jacobi2(Ctx& c, int lev, int op, const void* z2, const void* zc, const void* r, void* out,
+                               const double* omg, const int* gate, const double* dot64) = 0;
   virtual void restrict64(Ctx& c, int lev_f, const double* rf, double* rc) = 0;    // border vectors
   virtual void galerkin(Ctx& c, int lev_f, int op) = 0;              // E64 of level lev_f-1
   virtual void dense_assemble(Ctx& c, int op, double* A, int n) = 0;
@@ -121,6 +126,7 @@ struct Ctx {
   bool mfma = true;            // first coarse level's fused passes on the matrix cores (FP32)
   bool lane_share = true;      // finest-level 2D passes of K on lane-shared tiles (neighbour columns by DPP)
   bool fuse_resid = true;      // ... and the residual formed in the pass of the two sweeps from zero
+  bool fuse_post = true;       // ... and the prolongation and both post-sweeps in one pass
   bool fold_solution = true;         // PCG solution update folded into the next direction kernel
   bool fold_rn2_fin = true;          // PCG ||r||^2 finalize done by the V-cycle's first pass
   bool fold_restrict = true;         // finest residual restricted inside the first coarse down pass

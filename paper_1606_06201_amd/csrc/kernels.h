@@ -1685,6 +1685,157 @@ __global__ __launch_bounds__(BS) void k_jacobi2r2d(OpFineK<2, T> op, Dims d, con
   }
 }
 
+// The solution update z2 + P zc and the two post-smoothing sweeps in one lane-shared
+// pass (finest level of K): v = z2 + P zc on NJ+4 rows of the lane's column (summed
+// as load_col_prolong does), z3 = v + omega D^-1 (r - A v) on NJ+2 rows, and
+// z4 = z3 + omega D^-1 (r - A z3) on its NJ rows, the neighbouring columns of v and
+// of z3 read from the neighbouring lanes; zero on nodes outside the grid and on
+// clamped ones, as the separate passes store and read them.  BETA: the last sweep's
+// partial sum r~'z4 for the PCG ratio (dot64 = r~ in FP64), as M_JACOBI_BETA.
+// LS2_COLS output columns per tile, lanes 0, 1, 62 and 63 halo columns.
+template <typename T, int NJ, bool EDGE>
+__device__ inline void pjacobi2_col(const OpFineK<2, T>& op, const Dims& d, const Dims& dc, int i, int j0,
+                                    const T* __restrict__ z2, const T* __restrict__ zc, const T* __restrict__ r,
+                                    T omega, T (&z4)[NJ][2]) {
+  static_assert(NJ % 2 == 0, "the folded prolongation needs an even node count per thread");
+  constexpr int R1 = NJ + 4, R2 = NJ + 2, CR = NJ / 2 + 3;
+  T xb[NJ + 5][2];                                    // elements (i-1+ec, j0-3+er)
+#pragma unroll
+  for (int er = 0; er < NJ + 5; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) {
+      const int ei = i - 1 + ec, ej = j0 - 3 + er;
+      xb[er][ec] = op.x[(!EDGE || elem_in(d, ei, ej)) ? (int64_t)ej * d.nx + ei : op.m];
+    }
+  // coarse rows j0/2-1 .. j0/2+NJ/2+1, columns i>>1 and (i+1)>>1
+  const int jb = (j0 >> 1) - 1;
+  const bool odd = (i & 1) != 0;
+  const int I0 = min(max(i >> 1, 0), dc.nx1 - 1), I1 = min(max((i + 1) >> 1, 0), dc.nx1 - 1);
+  T cv[CR][2][2];
+#pragma unroll
+  for (int cr = 0; cr < CR; ++cr) {
+    const int J = min(max(jb + cr, 0), dc.ny1 - 1);
+    load_node<2, T>(zc, (int64_t)J * dc.nx1 + I0, cv[cr][0]);
+    load_node<2, T>(zc, (int64_t)J * dc.nx1 + I1, cv[cr][1]);
+  }
+  // r on rows j0-1 .. j0+NJ (clamped index; results on other nodes are masked)
+  T rv[R2][2];
+#pragma unroll
+  for (int n = 0; n < R2; ++n) {
+    const int jj = min(max(j0 - 1 + n, 0), d.ny1 - 1), ic = min(max(i, 0), d.nx1 - 1);
+    load_node<2, T>(r, (int64_t)jj * d.nx1 + ic, rv[n]);
+  }
+  // v = z2 + P zc on rows j0-2 .. j0+NJ+1 (row j0-2+rr is odd when rr is odd)
+  T w1[R1][3][2];
+  bool ok[R1];
+#pragma unroll
+  for (int rr = 0; rr < R1; ++rr) {
+    const int jj = j0 - 2 + rr;
+    const int nj = (rr & 1) ? 2 : 1;
+    const int J0 = rr >> 1;
+    ok[rr] = !EDGE || (i >= 1 && i < d.nx1 && jj >= 0 && jj < d.ny1);
+    const unsigned o = 2u * ((unsigned)min(max(jj, 0), d.ny1 - 1) * (unsigned)d.nx1 + (unsigned)(ok[rr] ? i : 0));
+    T acc[2] = {z2[o], z2[o + 1]};
+    const int ni = odd ? 2 : 1;
+    const T wgt = T((ni == 2 ? 0.5f : 1.0f) * (nj == 2 ? 0.5f : 1.0f));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool use = e < ni && b < nj;
+        const int Jr = J0 + (b < nj ? b : 0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[c] += use ? wgt * cv[Jr][e][c] : T(0);
+      }
+    w1[rr][1][0] = ok[rr] ? acc[0] : T(0);
+    w1[rr][1][1] = ok[rr] ? acc[1] : T(0);
+  }
+  share_columns<T, NJ + 2>(w1);
+  // z3 on rows j0-1 .. j0+NJ
+  T a1[R2][2], d1[R2][2];
+  {
+    T xe[R2 + 1][2];
+#pragma unroll
+    for (int er = 0; er <= R2; ++er)
+#pragma unroll
+      for (int ec = 0; ec < 2; ++ec) xe[er][ec] = xb[er + 1][ec];
+    TileApply<T, OpFineK<2, T>, true, R2>::run_x(xe, w1, a1, d1);
+  }
+  T w2[R2][3][2];
+#pragma unroll
+  for (int n = 0; n < R2; ++n)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T o = w1[n + 1][1][c] + omega * (rv[n][c] - a1[n][c]) * recip(d1[n][c]);
+      w2[n][1][c] = ok[n + 1] ? o : T(0);
+    }
+  share_columns<T, NJ>(w2);
+  // z4 on the lane's rows
+  T xe2[NJ + 1][2], acc[NJ][2], dg[NJ][2];
+#pragma unroll
+  for (int er = 0; er <= NJ; ++er)
+#pragma unroll
+    for (int ec = 0; ec < 2; ++ec) xe2[er][ec] = xb[er + 2][ec];
+  TileApply<T, OpFineK<2, T>, true, NJ>::run_x(xe2, w2, acc, dg);
+#pragma unroll
+  for (int n = 0; n < NJ; ++n)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      z4[n][c] = w2[n + 1][1][c] + omega * (rv[n + 1][c] - acc[n][c]) * recip(dg[n][c]);
+}
+
+template <typename T, int NJ, bool BETA>
+__global__ __launch_bounds__(BS) void k_pjacobi2d(OpFineK<2, T> op, Dims d, Dims dc, const T* __restrict__ z2,
+                                                  const T* __restrict__ zc, const T* __restrict__ r,
+                                                  T* __restrict__ out, const double* __restrict__ omg,
+                                                  const double* __restrict__ dot64, Red red, const int* gate) {
+  if (gate && *gate) return;
+  const T omega = T(*omg);
+  const Tile tl = xcd_tile();
+  constexpr int RJ = (BS / 64) * NJ;
+  const int lane = threadIdx.x & 63;
+  const int ti0 = (int)tl.x * LS2_COLS - 2, tj0 = tl.y * RJ;
+  const int i = ti0 + lane;
+  const int j0 = tj0 + (threadIdx.x >> 6) * NJ;
+  const bool interior = ti0 >= 1 && ti0 + 65 <= d.nx1 && tj0 >= 3 && tj0 + RJ + 3 <= d.ny1;
+  double dpre[NJ][2];
+  if constexpr (BETA) {
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      const int j = min(j0 + n, d.ny1 - 1), ic = min(max(i, 0), d.nx1 - 1);
+      const double2 t = *reinterpret_cast<const double2*>(dot64 + 2 * ((int64_t)j * d.nx1 + ic));
+      dpre[n][0] = t.x;
+      dpre[n][1] = t.y;
+    }
+  }
+  T z4[NJ][2];
+  if (interior) pjacobi2_col<T, NJ, false>(op, d, dc, i, j0, z2, zc, r, omega, z4);
+  else pjacobi2_col<T, NJ, true>(op, d, dc, i, j0, z2, zc, r, omega, z4);
+  double red0 = 0.0;
+  if (lane >= 2 && lane < 2 + LS2_COLS) {
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      const int j = j0 + n;
+      if (!interior && (i >= d.nx1 || j >= d.ny1)) continue;
+      const int64_t q = (int64_t)j * d.nx1 + i;
+      if (!interior && i == 0) {
+        const T z[2] = {T(0), T(0)};
+        store_node<2, T>(out, q, z);
+        continue;
+      }
+      if constexpr (BETA) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) red0 += dpre[n][c] * (double)z4[n][c];
+      }
+      store_node<2, T>(out, q, z4[n]);
+    }
+  }
+  if constexpr (BETA) {
+    const double vals[3] = {red0, 0.0, 0.0};
+    block_partials<3>(vals, red);
+  }
+}
+
 // 2D level pass with register blocking: each thread owns NJ consecutive nodes
 // along y of one column and loads the (NJ+2) x 3 window of neighbours once.  Tiles
 // whose nodes are all at least one node away from every boundary (and off the

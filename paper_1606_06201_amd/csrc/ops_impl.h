@@ -856,6 +856,43 @@ struct OpsImpl : Ops {
       return true;
     }
   }
+  template <typename T, int NJ>
+  void launch_pjacobi2(Ctx& c, const Dims& d, const Dims& dc, const T* z2, const T* zc, const T* r, T* out,
+                       const double* omg, const int* gate, const double* dot64) {
+    constexpr int RJ = 4 * NJ;
+    const dim3 g((unsigned)((d.nx1 + LS2_COLS - 1) / LS2_COLS), (unsigned)((d.ny1 + RJ - 1) / RJ), 1);
+    const unsigned nb = g.x * g.y;
+    IPMG_REQUIRE((int64_t)nb <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
+    const OpFineK<2, T> op{(const T*)c.xT, d.m};
+    {
+      ProfScope ps(c, c.prof_tag);
+      if (dot64) k_pjacobi2d<T, NJ, true><<<g, BS, 0, c.stream>>>(op, d, dc, z2, zc, r, out, omg, dot64, c.red, gate);
+      else k_pjacobi2d<T, NJ, false><<<g, BS, 0, c.stream>>>(op, d, dc, z2, zc, r, out, omg, dot64, c.red, gate);
+    }
+    if (dot64)
+      k_level_fin<T, M_JACOBI_BETA><<<1, BS, 0, c.stream>>>(z2, r, out, omg, 0, c.cZ, d.nslots, dot64, c.red, nb, 0,
+                                                           -1, gate, c.take_flag_dst());
+  }
+  bool prolong_jacobi2(Ctx& c, int lev, int op, const void* z2, const void* zc, const void* r, void* out,
+                       const double* omg, const int* gate, const double* dot64) override {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      if (op != IPMG_OP_K || !c.fold_prolong || !c.lane_share || !c.fuse_post || lev != c.L - 1) return false;
+      const Dims& d = c.lev[lev].d;
+      const Dims& dc = c.lev[lev - 1].d;
+      if (!c.tiled2d || d.nnodes < c.tiled_min_nodes) return false;
+      const int nj = c.fp32 ? c.nj32 : c.nj64;
+      if (nj != 2 && nj != 4) return false;
+      using F = float;
+      using D = double;
+      if (c.fp32 && nj == 4) launch_pjacobi2<F, 4>(c, d, dc, (const F*)z2, (const F*)zc, (const F*)r, (F*)out, omg, gate, dot64);
+      else if (c.fp32) launch_pjacobi2<F, 2>(c, d, dc, (const F*)z2, (const F*)zc, (const F*)r, (F*)out, omg, gate, dot64);
+      else if (nj == 4) launch_pjacobi2<D, 4>(c, d, dc, (const D*)z2, (const D*)zc, (const D*)r, (D*)out, omg, gate, dot64);
+      else launch_pjacobi2<D, 2>(c, d, dc, (const D*)z2, (const D*)zc, (const D*)r, (D*)out, omg, gate, dot64);
+      return true;
+    }
+  }
   bool jacobi2(Ctx& c, int lev, int op, const void* r, void* out, const double* omg, const int* gate) override {
     if constexpr (DIM != 2) {
       return false;

@@ -159,6 +159,7 @@ void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st) {
   if (const char* e = std::getenv("IPMG_NO_MFMA")) c.mfma = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_LANE_SHARE")) c.lane_share = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NO_JACOBI2_RESID")) c.fuse_resid = e[0] != '1';
+  if (const char* e = std::getenv("IPMG_NO_PJACOBI2")) c.fuse_post = e[0] != '1';
   if (const char* e = std::getenv("IPMG_NJ32")) c.nj32 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ64")) c.nj64 = std::atoi(e);
   if (const char* e = std::getenv("IPMG_NJ_DIR")) c.nj_dir = std::atoi(e);
@@ -434,7 +435,10 @@ static void* vcycle_level(Ctx& c, int op, int k, const int* gate, const double* 
   int s0 = 0;
   if (c.desc.nu_post >= 2) {                  // solution update folded into the first post-sweep
     ProfTag pt(c, fine ? PC_FINE_PJACOBI : jac);
-    if (c.ops->prolong_jacobi(c, k, op, cur, vc, l.r, nxt, w, gate)) {
+    if (c.desc.nu_post == 2 && c.ops->prolong_jacobi2(c, k, op, cur, vc, l.r, nxt, w, gate, beta64)) {
+      std::swap(cur, nxt);                    // ... and into both post-sweeps
+      s0 = 2;
+    } else if (c.ops->prolong_jacobi(c, k, op, cur, vc, l.r, nxt, w, gate)) {
       std::swap(cur, nxt);
       s0 = 1;
     }

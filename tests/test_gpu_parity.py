@@ -356,8 +356,42 @@ def test_finest_level_sweeps_and_residual_in_one_pass_match_separate_passes(nel,
         assert its["0"] == its["1"]
 
 
+@pytest.mark.parametrize("nel,levels", [((256, 128), 4), ((248, 124), 3), ((124, 60), 3), ((60, 30), 2), ((8, 4), 2)])
+@pytest.mark.parametrize("fp32", [True, False])
+def test_finest_level_prolongation_and_post_sweeps_in_one_pass_match_separate_passes(nel, levels, fp32,
+                                                                                      monkeypatch):
+    # z2 + P zc and both post-smoothing sweeps in one lane-shared pass against the
+    # folded-prolongation sweep and the last sweep as separate passes.  Same formulas
+    # and order: the FP64 V-cycles agree bit for bit, the FP32 ones to a few ulps.  In
+    # PCG the last sweep's partial sums for the ratio are grouped by the new tiles, so
+    # the iterates agree to rounding and the iteration counts within one.
+    monkeypatch.setenv("IPMG_TILED_MIN_NODES", "0")
+    g, K0, x = _kproblem(nel, seed=16)
+    r = np.random.default_rng(17).standard_normal(g.nslots)
+    r[g.clamped_mask()] = 0
+    f = fem.load_vector(g, tip_load(nel))
+    z, its, u = {}, {}, {}
+    for v in ("0", "1"):
+        monkeypatch.setenv("IPMG_NO_PJACOBI2", v)
+        s = _solver(nel, levels, fp32=fp32)
+        s.set_density(T(x))
+        s.mg_setup()
+        z[v] = N(s.vcycle(T(r)))
+        uu, info = s.pcg(T(f), rtol=1e-8)
+        assert info["true_relres"] <= 1e-8
+        its[v], u[v] = info["iters"], N(uu)
+    monkeypatch.delenv("IPMG_NO_PJACOBI2")
+    monkeypatch.delenv("IPMG_TILED_MIN_NODES")
+    if fp32:
+        assert relerr(z["0"], z["1"]) < 1e-6
+    else:
+        assert np.array_equal(z["0"], z["1"])
+    assert abs(its["0"] - its["1"]) <= 1
+    assert relerr(u["0"], u["1"]) < 1e-7
+
+
 @pytest.mark.parametrize("env,val", [("IPMG_STORED_COARSE", "1"), ("IPMG_NO_LANE_SHARE", "1"),
-                                     ("IPMG_NO_JACOBI2_RESID", "1"),
+                                     ("IPMG_NO_JACOBI2_RESID", "1"), ("IPMG_NO_PJACOBI2", "1"),
                                      ("IPMG_TILED_MIN_NODES", "0"), ("IPMG_UNTILED", "1"), ("IPMG_UNFUSED", "1"),
                                      ("IPMG_UNSTAGED", "1"), ("IPMG_STAGED_MAX_NODES", "1048576"),
                                      ("IPMG_NO_FOLD_PROLONG", "1"), ("IPMG_NO_FOLD_RESTRICT", "1"),
