@@ -34,10 +34,10 @@ KERNEL_SOURCES = ["paper_1606_06201_amd/csrc/kernels.h", "paper_1606_06201_amd/c
 KERNEL_NAMES = {
     "fine_jacobi": "k_level2d<float, OpFineK<2,float>, M_JACOBI, 4>: finest-level damped-Jacobi sweep",
     "fine_jacobi0": "k_level2d<float, OpFineK<2,float>, M_JACOBI0, 4>: first sweep from a zero iterate",
-    "fine_pjacobi": "k_level2d<float, OpFineK<2,float>, M_PJACOBI, 4>: first post-sweep from z2 + P zc "
-                    "(prolongation folded in)",
-    "fine_jacobi2": "k_level2d<float, OpFineK<2,float>, M_JACOBI2, 4>: the first two pre-sweeps from zero in one "
-                    "pass",
+    "fine_pjacobi": "k_pjacobi2d<float, 4, true>: solution update z2 + P zc and both post-sweeps in one "
+                    "lane-shared pass, with the PCG ratio's partial sums",
+    "fine_jacobi2": "k_jacobi2r2d<float, 4>: the two pre-sweeps from zero and the residual of their result in "
+                    "one lane-shared pass",
     "fine_jacobi_beta": "k_level2d<float, OpFineK<2,float>, M_JACOBI_BETA, 4>: last sweep + fused PCG ratio",
     "fine_resid": "k_level2d<float, OpFineK<2,float>, M_RESID, 4>: finest-level residual",
     "sub_jacobi": "k_level2d<float, OpCoarse2K<2,float>, M_JACOBI, 4>: first coarse level Jacobi sweep, "
@@ -45,10 +45,11 @@ KERNEL_NAMES = {
     "dir_apply": "k_dir_apply2d<float, OpFineK<2,double>, 4, true>: p = -y + beta p, q = K p (FP64), p'q, "
                  "and the previous step's z += alpha p_old",
     "pcg_update": "k_pcg_update<float, false>: r += alpha q (FP64), FP32 copy of r, ||r||^2",
-    "sub_down": "k_down2d_x<float, true, 16, 9>: first coarse level, its r = P' t from the finest residual, two "
-                "Jacobi sweeps, residual and restriction in one LDS-tiled pass (densities staged in LDS)",
-    "sub_up": "k_up2d_x<float, 32, 18>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled "
-              "pass (densities staged in LDS)",
+    "sub_down": "k_down2d_m<true, 16, 9>: first coarse level, its r = P' t from the finest residual, two "
+                "Jacobi sweeps, residual and restriction in one LDS-tiled pass (densities staged in LDS, element "
+                "products on the matrix cores)",
+    "sub_up": "k_up2d_m<32, 18>: first coarse level, prolongation and two Jacobi sweeps in one LDS-tiled pass "
+              "(densities staged in LDS, element products on the matrix cores)",
 }
 
 
@@ -64,10 +65,12 @@ def class_bytes(nel, fp32, kind):
         return 3 * 2 * w * N + w * m
     if kind == "fine_jacobi0":                  # read r; write z; read x
         return 2 * 2 * w * N + w * m
+    pj2 = os.environ.get("IPMG_NO_PJACOBI2", "0") != "1"
     if kind == "fine_pjacobi":                  # read z2, r, coarse correction; write z; read x
-        return 3 * 2 * w * N + w * m + 2 * w * Nc
-    if kind == "fine_jacobi2":                  # read r, x; write z2 (z1 never stored)
-        return 2 * 2 * w * N + w * m
+        return 3 * 2 * w * N + w * m + 2 * w * Nc + (2 * 8 * N if pj2 else 0)  # (+ FP64 r for the ratio)
+    if kind == "fine_jacobi2":                  # read r, x; write z2 (z1 never stored) and the residual t
+        j2r = os.environ.get("IPMG_NO_JACOBI2_RESID", "0") != "1"
+        return (3 if j2r else 2) * 2 * w * N + w * m
     if kind == "fine_jacobi_beta":              # fine_jacobi + read FP64 r for the ratio
         return 3 * 2 * w * N + w * m + 2 * 8 * N
     if kind == "sub_jacobi":                    # read z, r; write z'; read the fine x (4 per coarse element)
