@@ -99,7 +99,7 @@ constexpr int BS = 256;           // threads per block for level and vector kern
 constexpr int MAX_PARTIALS = 1 << 16;
 
 struct Red {
-  double* partials;   // MAX_PARTIALS * 4 doubles
+  double* partials;   // MAX_PARTIALS * 8 doubles (eight value slots)
   unsigned* counter;  // C_COUNT
   double* scal;       // S_COUNT
   int* flags;         // F_COUNT
