@@ -14,9 +14,10 @@
 // working matrix W keeps every tile transposed (tile (I, J) holds A_IJ', then
 // L_Ik' in the panel column, and X_kk' on the diagonal once factored), so every
 // 64 x 64 x 64 tile product reads both operands from LDS with the summed index
-// first: four outputs by four per thread, two 16-byte reads per operand per
-// step, FP64 vector FMAs (the FP64 vector and matrix-core rates of gfx950 are the
-// same).  The padded order keeps every tile full.
+// first and runs on the FP64 matrix cores (16 outputs per thread; the matrix-core
+// and vector FP64 rates of gfx950 are the same, but the vector form needs 64 bytes
+// of LDS per 16 FMAs and is bound by LDS bandwidth at about half of that rate).
+// The padded order keeps every tile full.
 #include "dense.h"
 
 namespace ipmg {
@@ -42,35 +43,46 @@ __device__ inline void stage(const double* __restrict__ g, Tile& s) {
   for (int u = 0; u < DT * DT / 2 / DTT; ++u) s2[threadIdx.x + u * DTT] = g2[threadIdx.x + u * DTT];
 }
 
-// acc[i][j] += sum_m SA[m][4ty + i] SB[m][4tx + j], (ty, tx) = (thread / 16, thread % 16).
+// A thread's 16 outputs of a 64 x 64 tile product, in the layout of the FP64
+// matrix-core product v_mfma_f64_16x16x4f64 (checked with a probe of the builtin):
+// wave w owns rows 16w..16w+15; accumulator (i, j) of lane l is row
+// 16w + l/16 + 4i, column 16j + l%16.
+__device__ inline int acc_row(int i) { return 16 * (int)(threadIdx.x >> 6) + (int)((threadIdx.x & 63) >> 4) + 4 * i; }
+__device__ inline int acc_col(int j) { return 16 * j + (int)(threadIdx.x & 15); }
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// acc(row, col) += sum_m SA[m][row] SB[m][col] on the matrix cores: per step of
+// four m, lane l supplies A[r][k] = SA[m0 + l/16][16w + l%16] and, for each column
+// block j, B[k][c] = SB[m0 + l/16][16j + l%16]; four 16x16x4 products per step.
+// The operands come from LDS once per product (one 8-byte read per operand), so
+// the products run at the matrix cores' rate instead of the LDS bandwidth's.
 __device__ inline void tile_mac(const Tile& SA, const Tile& SB, double (&acc)[4][4]) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, kr = l >> 4, lc = l & 15;
+  d4 c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) c[j] = d4{acc[0][j], acc[1][j], acc[2][j], acc[3][j]};
 #pragma unroll 4
-  for (int m = 0; m < DT; ++m) {
-    const double2 a0 = *reinterpret_cast<const double2*>(&SA[m][4 * ty]);
-    const double2 a1 = *reinterpret_cast<const double2*>(&SA[m][4 * ty + 2]);
-    const double2 b0 = *reinterpret_cast<const double2*>(&SB[m][4 * tx]);
-    const double2 b1 = *reinterpret_cast<const double2*>(&SB[m][4 * tx + 2]);
-    const double a[4] = {a0.x, a0.y, a1.x, a1.y}, b[4] = {b0.x, b0.y, b1.x, b1.y};
+  for (int m0 = 0; m0 < DT; m0 += 4) {
+    const double a = SA[m0 + kr][16 * w + lc];
+    double b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) b[j] = SB[m0 + kr][16 * j + lc];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    for (int j = 0; j < 4; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], c[j], 0, 0, 0);
   }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i][j] = c[j][i];
 }
 
-// acc (the thread's 4 x 4 outputs) from a global tile, or zero.
+// acc (the thread's outputs) from a global tile, or zero.
 __device__ inline void acc_load(const double* __restrict__ g, double (&acc)[4][4]) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const double2* p = reinterpret_cast<const double2*>(g + (4 * ty + i) * DT + 4 * tx);
-    const double2 v0 = p[0], v1 = p[1];
-    acc[i][0] = v0.x;
-    acc[i][1] = v0.y;
-    acc[i][2] = v1.x;
-    acc[i][3] = v1.y;
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = g[acc_row(i) * DT + acc_col(j)];
 }
 
 __device__ inline void acc_zero(double (&acc)[4][4]) {
@@ -83,16 +95,10 @@ __device__ inline void acc_zero(double (&acc)[4][4]) {
 // g = base - acc (SUB) or g = acc; base is the tile's old content (acc_load).
 template <bool SUB>
 __device__ inline void acc_store(double* __restrict__ g, const double (&acc)[4][4], const double (&base)[4][4]) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double2* p = reinterpret_cast<double2*>(g + (4 * ty + i) * DT + 4 * tx);
-    double v[4];
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = SUB ? base[i][j] - acc[i][j] : acc[i][j];
-    p[0] = make_double2(v[0], v[1]);
-    p[1] = make_double2(v[2], v[3]);
-  }
+    for (int j = 0; j < 4; ++j) g[acc_row(i) * DT + acc_col(j)] = SUB ? base[i][j] - acc[i][j] : acc[i][j];
 }
 
 // Zero every tile; identity on the padded diagonal (rows >= n) when pad is set.
@@ -276,11 +282,10 @@ __global__ __launch_bounds__(DTT) void k_dense_update(double* __restrict__ W, do
   __syncthreads();                                  // SA, SB no longer read
   DiagRows* Lc = reinterpret_cast<DiagRows*>(smemA);
   DiagRows* Xc = reinterpret_cast<DiagRows*>(smemB);
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Lc[4 * ty + i][4 * tx + j] = old[i][j] - acc[i][j];
+    for (int j = 0; j < 4; ++j) Lc[acc_row(i)][acc_col(j)] = old[i][j] - acc[i][j];
   __syncthreads();
   diag_factor(Lc, Xc, W, X, k + 1, red);
 }
@@ -304,11 +309,10 @@ __global__ __launch_bounds__(DTT) void k_dense_product(const double* __restrict_
   }
   acc_store<false>(Ai + dense_tile_off(I, J), acc, acc);
   if (Af) {
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      *reinterpret_cast<float4*>(Af + dense_tile_off(I, J) + (4 * ty + i) * DT + 4 * tx) =
-          make_float4((float)acc[i][0], (float)acc[i][1], (float)acc[i][2], (float)acc[i][3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Af[dense_tile_off(I, J) + acc_row(i) * DT + acc_col(j)] = (float)acc[i][j];
   }
 }
 
