@@ -530,14 +530,22 @@ __device__ inline void gstack_operands(float (&aG)[4]) {
   for (int s = 0; s < 4; ++s) aG[s] = cG256f[(lane & 31) * 8 + 2 * s + (lane >> 5)];
 }
 
+// Element products in LDS as four vertex planes: plane a holds rows 2a and 2a + 1
+// of every element's product as a float pair at 2 t (t the element's index in its
+// block), so a node's gather and a half-wave's store both touch consecutive pairs.
+// The plane pitch is a multiple of 32 floats plus 16, which puts the planes the two
+// half-waves store to on different banks.
+__host__ __device__ constexpr int ye_pitch(int ne) { return ((2 * ne + 31) / 32) * 32 + 16; }
+
 // y_e for the NEX x NEY elements of a block: element (ex, ey) has vertex b at node
 // (ex + loc_x(b), ey + loc_y(b)) of sv (row width WV, two values per node) and the
 // four densities of staged element (ex + ELX, ey + ELY) of xl (row width LW, LH
-// rows, as OpCoarse2KLDS).  Writes ye[8 t + r], t = ey NEX + ex.  The waves of the
-// workgroup take the groups of 32 elements in turn.
+// rows, as OpCoarse2KLDS).  Writes the vertex planes of ye (pitch ye_pitch(NE)),
+// t = ey NEX + ex.  The waves of the workgroup take the groups of 32 elements in
+// turn.
 template <int NEX, int NEY, int WV, int LW, int LH, int ELX, int ELY, int NT>
 __device__ inline void elem_products_mfma(const float* sv, const float* xl, const float (&aG)[4], float* ye) {
-  constexpr int NE = NEX * NEY, NG = (NE + 31) / 32, NW = NT / 64, NEL = LW * LH;
+  constexpr int NE = NEX * NEY, NG = (NE + 31) / 32, NW = NT / 64, NEL = LW * LH, YP = ye_pitch(NE);
   const int lane = threadIdx.x & 63, h = lane >> 5;
   for (int g = (int)threadIdx.x >> 6; g < NG; g += NW) {
     const int t0 = g * 32 + (lane & 31), t = min(t0, NE - 1);
@@ -552,20 +560,24 @@ __device__ inline void elem_products_mfma(const float* sv, const float* xl, cons
                        0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aG[s], b[s], acc, 0, 0, 0);
-    float4 y;
-    y.x = xq[0] * acc[0] + xq[1] * acc[4] + xq[2] * acc[8] + xq[3] * acc[12];
-    y.y = xq[0] * acc[1] + xq[1] * acc[5] + xq[2] * acc[9] + xq[3] * acc[13];
-    y.z = xq[0] * acc[2] + xq[1] * acc[6] + xq[2] * acc[10] + xq[3] * acc[14];
-    y.w = xq[0] * acc[3] + xq[1] * acc[7] + xq[2] * acc[11] + xq[3] * acc[15];
-    if (t0 < NE) *reinterpret_cast<float4*>(ye + 8 * t + 4 * h) = y;
+    float2 y0, y1;                                   // rows 4h, 4h+1 (vertex 2h) and 4h+2, 4h+3
+    y0.x = xq[0] * acc[0] + xq[1] * acc[4] + xq[2] * acc[8] + xq[3] * acc[12];
+    y0.y = xq[0] * acc[1] + xq[1] * acc[5] + xq[2] * acc[9] + xq[3] * acc[13];
+    y1.x = xq[0] * acc[2] + xq[1] * acc[6] + xq[2] * acc[10] + xq[3] * acc[14];
+    y1.y = xq[0] * acc[3] + xq[1] * acc[7] + xq[2] * acc[11] + xq[3] * acc[15];
+    if (t0 < NE) {
+      *reinterpret_cast<float2*>(ye + 2 * h * YP + 2 * t) = y0;
+      *reinterpret_cast<float2*>(ye + (2 * h + 1) * YP + 2 * t) = y1;
+    }
   }
 }
 
 // Row sums of node (li, lj) from the products of the four elements around it:
-// element (li - 1 + ex + OX, lj - 1 + ey + OY) of a block of row width NEX, the node
-// its vertex loc_index(1 - ex, 1 - ey).
-template <int NEX, int OX, int OY>
+// element (li - 1 + ex + OX, lj - 1 + ey + OY) of a block of NEX x NEY elements, the
+// node its vertex loc_index(1 - ex, 1 - ey).
+template <int NEX, int NEY, int OX, int OY>
 __device__ inline void gather_rows(const float* ye, int li, int lj, float (&acc)[2]) {
+  constexpr int YP = ye_pitch(NEX * NEY);
   acc[0] = acc[1] = 0.0f;
 #pragma unroll
   for (int ey = 0; ey < 2; ++ey)
@@ -573,7 +585,7 @@ __device__ inline void gather_rows(const float* ye, int li, int lj, float (&acc)
     for (int ex = 0; ex < 2; ++ex) {
       const int t = (lj - 1 + ey + OY) * NEX + li - 1 + ex + OX;
       const int a = loc_index(1 - ex, 1 - ey, 0);
-      const float2 v = *reinterpret_cast<const float2*>(ye + 8 * t + 2 * a);
+      const float2 v = *reinterpret_cast<const float2*>(ye + a * YP + 2 * t);
       acc[0] += v.x;
       acc[1] += v.y;
     }
@@ -593,7 +605,7 @@ __global__ __launch_bounds__(FBS) void k_down2d_m(const float* __restrict__ x, i
   constexpr int NEX2 = W1 - 1, NEY2 = H1 - 1, NEX3 = W1 - 3, NEY3 = H1 - 3;   // element blocks of phases 2, 3
   __shared__ float xl[4 * LW * LH];
   __shared__ float sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2], s2[H2 * W2 * 2], s3[H3 * W3 * 2];
-  __shared__ __align__(16) float ye[8 * NEX2 * NEY2];
+  __shared__ __align__(16) float ye[4 * ye_pitch(NEX2 * NEY2)];
   const Tile tl = xcd_tile();
   const int CI0 = (int)tl.x * CX, CJ0 = (int)tl.y * CY;
   const int ox = 2 * CI0 - 3, oy = 2 * CJ0 - 3;
@@ -640,7 +652,7 @@ __global__ __launch_bounds__(FBS) void k_down2d_m(const float* __restrict__ x, i
     float o[2] = {0.0f, 0.0f};
     if (node_free(d, gi, gj)) {
       float acc[2];
-      gather_rows<NEX2, 0, 0>(ye, li, lj, acc);
+      gather_rows<NEX2, NEY2, 0, 0>(ye, li, lj, acc);
       const int q = 2 * (lj * W1 + li);
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
@@ -658,7 +670,7 @@ __global__ __launch_bounds__(FBS) void k_down2d_m(const float* __restrict__ x, i
     float o[2] = {0.0f, 0.0f};
     if (node_free(d, gi, gj)) {
       float acc[2];
-      gather_rows<NEX3, -1, -1>(ye, li, lj, acc);
+      gather_rows<NEX3, NEY3, -1, -1>(ye, li, lj, acc);
       const int q = 2 * (lj * W1 + li);
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = sr[q + c] - acc[c];
@@ -683,7 +695,7 @@ __global__ __launch_bounds__(FBS) void k_up2d_m(const float* __restrict__ x, int
   constexpr int NEXA = W1 + 1, NEYA = H1 + 1, NEXB = W1 - 1, NEYB = H1 - 1;   // element blocks of the sweeps
   __shared__ float xl[4 * LW * LH];
   __shared__ float s0[H0 * W0 * 2], sr[H1 * W1 * 2], sd[H1 * W1 * 2], s1[H1 * W1 * 2];
-  __shared__ __align__(16) float ye[8 * NEXA * NEYA];
+  __shared__ __align__(16) float ye[4 * ye_pitch(NEXA * NEYA)];
   const Tile tl = xcd_tile();
   const int I0 = (int)tl.x * TX, J0 = (int)tl.y * TY;
   const int ex0 = I0 - 2, ey0 = J0 - 2;
@@ -716,7 +728,7 @@ __global__ __launch_bounds__(FBS) void k_up2d_m(const float* __restrict__ x, int
       rr[1] = pre.r[u][1];
       float vn[9][2], acc[2];
       node_apply<2, float, OpCoarse2KLDS<float>, false, true, false>(op, d, gi, gj, 0, vn, acc, dg);
-      gather_rows<NEXA, 1, 1>(ye, li, lj, acc);
+      gather_rows<NEXA, NEYA, 1, 1>(ye, li, lj, acc);
       const int q = 2 * ((lj + 1) * W0 + li + 1);
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = s0[q + c] + omega * (rr[c] - acc[c]) * recip(dg[c]);
@@ -735,7 +747,7 @@ __global__ __launch_bounds__(FBS) void k_up2d_m(const float* __restrict__ x, int
     if (gi >= 1) {
       const int li = gi - I0 + 1, lj = gj - J0 + 1;     // position in region 1
       float acc[2];
-      gather_rows<NEXB, 0, 0>(ye, li, lj, acc);
+      gather_rows<NEXB, NEYB, 0, 0>(ye, li, lj, acc);
       const int q = 2 * (lj * W1 + li);
 #pragma unroll
       for (int c = 0; c < 2; ++c) o[c] = s1[q + c] + omega * (sr[q + c] - acc[c]) * recip(sd[q + c]);
