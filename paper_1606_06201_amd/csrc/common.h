@@ -1,6 +1,7 @@
 // Internal declarations of the ipmg library (gfx950 / HIP).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 #include <string>
 #include <vector>

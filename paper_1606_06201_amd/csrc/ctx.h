@@ -277,6 +277,22 @@ struct ProfScope {
   }
 };
 
+// Timing of one launch by its own dispatch packet: the start and stop events of
+// hipExtLaunchKernel (null when the class is not being timed).  The interval is
+// the kernel's run alone, without the marker packets that a pair of hipEventRecord
+// calls would place around the dispatch.
+struct ProfLaunch {
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  ProfLaunch(Ctx& c, int cls) {
+    if (cls >= 0 && ((c.prof_mask >> cls) & 1u) && 2 * (c.prof_used + 1) <= (int)c.prof_ev.size()) {
+      const int slot = c.prof_used++;
+      c.prof_cls[slot] = cls;
+      t0 = c.prof_ev[2 * slot];
+      t1 = c.prof_ev[2 * slot + 1];
+    }
+  }
+};
+
 // Host driver (solver.hip).
 void ctx_init(Ctx& c, const ipmg_desc& d, hipStream_t st);
 void ctx_free(Ctx& c);

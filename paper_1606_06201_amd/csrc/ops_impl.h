@@ -1065,9 +1065,13 @@ struct OpsImpl : Ops {
     const dim3 g((unsigned)((d.nx1 + 63) / 64), (unsigned)((d.ny1 + 4 * NJ - 1) / (4 * NJ)), 1);
     IPMG_REQUIRE((int64_t)g.x * g.y <= MAX_PARTIALS, IPMG_E_INVALID, "grid too large for one reduction");
     {
-      ProfScope ps(c, PC_DIR_APPLY);
-      if (zs) k_dir_apply2d<TY, Op, NJ, true><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate, zs);
-      else k_dir_apply2d<TY, Op, NJ, false><<<g, BS, 0, c.stream>>>(op, d, y, pold, p, q, aug, c.red, first, gate, zs);
+      const ProfLaunch pl(c, PC_DIR_APPLY);
+      if (zs)
+        hipExtLaunchKernelGGL(k_dir_apply2d<TY, Op, NJ, true>, g, dim3(BS), 0, c.stream, pl.t0, pl.t1, 0, op, d, y,
+                              pold, p, q, aug, c.red, first, gate, zs);
+      else
+        hipExtLaunchKernelGGL(k_dir_apply2d<TY, Op, NJ, false>, g, dim3(BS), 0, c.stream, pl.t0, pl.t1, 0, op, d, y,
+                              pold, p, q, aug, c.red, first, gate, zs);
     }
     k_dir_fin<TY><<<1, BS, 0, c.stream>>>(y, pold, p, q, aug.b != nullptr, aug.c, d.nslots, first, c.red,
                                           g.x * g.y, gate, zs);
